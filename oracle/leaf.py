@@ -111,7 +111,12 @@ def leaf_svd(d: np.ndarray, e: np.ndarray, s: int, max_sweeps: int | None = None
     B = dense_bidiagonal(d, e, s)
     W = np.eye(m)
     Q = np.eye(m + s)
-    bnorm = float(np.max(np.abs(B))) if B.size else 0.0
+    # Exact scaling by a power of two (not in the paper) so that no square in
+    # the shift or the bulge can overflow or underflow; undone on the values.
+    bmax = float(np.max(np.abs(B))) if B.size else 0.0
+    p = math.ldexp(1.0, math.frexp(bmax)[1]) if 0.0 < bmax < math.inf else 1.0
+    B = B / p
+    bnorm = bmax / p
     tiny = EPS * bnorm
 
     # s = 1: rotate the extra column's entry away, bottom row first.  Each
@@ -170,7 +175,7 @@ def leaf_svd(d: np.ndarray, e: np.ndarray, s: int, max_sweeps: int | None = None
         _gk_step(B, W, Q, lo, hi)
         sweeps += 1
 
-    sig = np.array([B[i, i] for i in range(m)], dtype=np.float64)
+    sig = np.array([B[i, i] for i in range(m)], dtype=np.float64) * p
     neg = sig < 0.0
     sig[neg] = -sig[neg]
     W[:, neg] = -W[:, neg]

@@ -60,7 +60,7 @@ def test_leaf_against_numpy_svd(m, s):
         assert np.linalg.norm(B @ Q[:, m]) <= 1e-14 * np.linalg.norm(B)
 
 
-@pytest.mark.parametrize("case", ["zero_diag_mid", "zero_diag_last", "zero_e", "all_zero", "graded"])
+@pytest.mark.parametrize("case", ["zero_diag_mid", "zero_diag_last", "zero_e", "all_zero", "graded", "huge", "tiny"])
 def test_leaf_special(case):
     m, s = 12, 1
     d, e = _leaf_input(m, s, 7)
@@ -78,14 +78,23 @@ def test_leaf_special(case):
         e[:] = 0.0
     elif case == "graded":
         d = d * 10.0 ** (-np.arange(m))
+    elif case == "huge":
+        d = d * 1e300
+        e = e * 1e300
+    elif case == "tiny":
+        d = d * 1e-300
+        e = e * 1e-300
     B = obdc.dense_bidiagonal(d, e, s)
     sig, W, Q, _ = oracle.leaf_svd(d, e, s)
-    ref = np.sort(np.linalg.svd(B, compute_uv=False))
-    nb = max(np.linalg.norm(B), 1e-300)
-    assert np.max(np.abs(sig - ref)) <= 1e-14 * max(ref[-1], 1e-300) + 1e-300
+    # compare in units of the largest entry (numpy's SVD is scale-safe)
+    unit = max(float(np.max(np.abs(B))), 1e-320)
+    ref = np.sort(np.linalg.svd(B / unit, compute_uv=False))
+    Bn = B / unit
+    nb = max(np.linalg.norm(Bn), 1e-300)
+    assert np.max(np.abs(sig / unit - ref)) <= 1e-14 * max(ref[-1], 1e-300) + 1e-300
     S = np.zeros((m, m + s))
-    S[np.arange(m), np.arange(m)] = sig
-    assert np.linalg.norm(B - W @ S @ Q.T) <= 1e-14 * nb
+    S[np.arange(m), np.arange(m)] = sig / unit
+    assert np.linalg.norm(Bn - W @ S @ Q.T) <= 1e-14 * nb
     assert np.max(np.abs(W.T @ W - np.eye(m))) <= 1e-14
     assert np.max(np.abs(Q.T @ Q - np.eye(m + s))) <= 1e-14
 
