@@ -1,0 +1,187 @@
+"""Benchmark: bidiagonal divide-and-conquer SVD with full vectors, FP64, one
+MI355X.
+
+Default workload: n = 16384 upper bidiagonal with d, e iid N(0, 1) (fixed
+seed), sigma + full U and V^T.  A step is one whole solve with the inputs
+already resident in HBM.  Prints one JSON line.
+
+  value     nominal GFLOP/s = (8/3) n^3 / time  (the paper's convention,
+            Section 4.2.2; deflation removes most of that work, so the
+            executed vector-update flops are reported beside it)
+  roofline  the kernel kind with the largest share of the timed region,
+            measured with HIP events on the solve's stream, against its
+            bound (MFMA FP64 peak, HBM bandwidth, or FP64 vector ALU)
+  cpu_baseline  the CPU oracle timed on a bounded sample of the same
+            workload family on this host
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_MFMA = 78.6e12     # dense FP64 matrix, FLOP/s
+PEAK_FP64_VALU = 78.6e12     # FP64 vector, FLOP/s
+PEAK_HBM = 8.0e12            # bytes/s
+METRIC = "bidiag SVD+vectors time & GFLOP/s at n=16384 FP64; secular iters/root, learned vs plain"
+
+WORKLOADS = {
+    "n16384_normal": ("n = 16384, d, e iid N(0,1), seed 250811767", 16384),
+    "n32768_normal": ("n = 32768, d, e iid N(0,1), seed 250811967", 32768),
+    "n16384_ones": ("n = 16384, d = e = 1 (no deflation, update-GEMM bound)", 16384),
+    "n4096_uniform": ("n = 4096, d, e iid U(-1,1)", 4096),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="n16384_normal", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=4096, help="size of the CPU oracle sample")
+    return ap.parse_args()
+
+
+def kernel_work(kind: str, stats: dict, n: int, launches: int):
+    """(bound, algorithmic units per launch, unit, peak) of a kernel kind."""
+    if kind == "update_gemm":
+        return "mfma", stats["update_flops"] / max(launches, 1), "TFLOP/s", PEAK_FP64_MFMA
+    if kind == "final":
+        # write U and V^T in full; read each column's support once
+        byts = 8.0 * (2.0 * n * n + stats["final_read_elems"])
+        return "hbm", byts / max(launches, 1), "GB/s", PEAK_HBM
+    if kind == "gather":
+        return "hbm", stats["gather_bytes"] / max(launches, 1), "GB/s", PEAK_HBM
+    if kind == "secular":
+        # ~12 FP64 flops per pole term per evaluation
+        return "alu", 12.0 * stats["secular_terms"] / max(launches, 1), "TFLOP/s", PEAK_FP64_VALU
+    if kind == "leaf":
+        return "alu", stats["leaf_flops"] / max(launches, 1), "TFLOP/s", PEAK_FP64_VALU
+    return "hbm", 0.0, "GB/s", PEAK_HBM
+
+
+def cpu_baseline(n: int):
+    import numpy as np  # noqa: F401
+
+    import oracle
+    from paper_2508_11467_amd import inputs
+
+    d, e = inputs.normal(n, inputs.seed_for(3))
+    t0 = time.perf_counter()
+    oracle.bdsdc(d, e)
+    t = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    return {
+        "value": (8.0 / 3.0) * n ** 3 / t / 1e9,
+        "unit": "GFLOP/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"one n={n} N(0,1) bidiagonal (same generator) solved by the NumPy oracle in {t:.2f} s; "
+                  f"nominal (8/3)n^3 flops",
+        "seconds": t,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); "
+              "this solver has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2508_11467_amd import inputs
+    from paper_2508_11467_amd.api import Solver
+
+    desc, n = WORKLOADS[args.workload]
+    d, e = inputs.workload(args.workload)
+    dev = torch.device("cuda:0")
+    dt = torch.from_numpy(d).to(dev)
+    et = torch.from_numpy(e).to(dev)
+    sig = torch.empty(n, dtype=torch.float64, device=dev)
+    ub = torch.empty((n, n), dtype=torch.float64, device=dev)
+    vb = torch.empty((n, n), dtype=torch.float64, device=dev)
+    solver = Solver(0, timing=True)
+    for _ in range(args.warmup):
+        solver.svd(dt, et, out=(sig, ub, vb))
+    torch.cuda.synchronize()
+    info, stats = solver.info()
+    solver.clear_timing()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        solver.svd(dt, et, out=(sig, ub, vb))
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / args.steps
+    info, stats = solver.info()
+    timing = solver.timing()
+    nominal = (8.0 / 3.0) * n ** 3
+    value = nominal / (ms * 1e-3) / 1e9
+
+    # dominant kernel kind over the timed region
+    kinds = {k: v for k, v in timing.items() if v[1] > 0}
+    dom = max(kinds, key=lambda k: kinds[k][0])
+    tot_ms, launches = kinds[dom]
+    per_launch_launches = launches / args.steps
+    bound, work, unit, peak = kernel_work(dom, stats, n, per_launch_launches)
+    avg_s = tot_ms * 1e-3 / launches
+    achieved = work / avg_s
+    scale = 1e9 if unit == "GB/s" else 1e12
+    roofline = {
+        "bound": bound,
+        "kernel": dom,
+        "achieved": achieved / scale,
+        "peak": peak / scale,
+        "unit": unit,
+        "frac": achieved / peak,
+        "traffic": None,
+        "avg_launch_ms": avg_s * 1e3,
+        "share_of_step": tot_ms / args.steps / ms,
+    }
+    iters_per_root = stats["secular_evals"] / max(stats["roots"], 1)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": n, "leaf_size": 32, "secular_start": "plain"},
+        "executed_update_gflops": stats["update_flops"] / (ms * 1e-3) / 1e9,
+        "update_flops": stats["update_flops"],
+        "nominal_flops": nominal,
+        "secular_iters_per_root": iters_per_root,
+        "root_N": stats["root_N"],
+        "roots": stats["roots"],
+        "info": info,
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in sorted(kinds.items())},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_n)
+    print(json.dumps(line), flush=True)
+    solver.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,186 @@
+/*
+ * bdc.h -- C ABI of the MI355X bidiagonal divide-and-conquer SVD.
+ *
+ * Computes B = U diag(sigma) V^T for an n x n real upper bidiagonal B with
+ * diagonal d (length n) and superdiagonal e (length n-1), with full singular
+ * vectors, in IEEE binary64.  This is the bidiagonal SVD stage of the paper's
+ * GPU-centered SVD (Section 4.2, "Diagonalization"; the BDC algorithm of
+ * Algorithm 2 with the deflation of Algorithm 3 and the merge of Algorithm 4).
+ * The result satisfies sigma_1 >= ... >= sigma_n >= 0 with U and V orthogonal
+ * (the SVD definition of Section 1).
+ *
+ * Memory.  Every matrix and vector argument is a device pointer on the device
+ * the handle was created for.  Matrices are column-major with leading
+ * dimension n.  The caller owns all arguments; inputs are never written;
+ * outputs are overwritten entirely and are also used as scratch during the
+ * call.  The handle owns its workspace (grown on demand, kept between calls).
+ *
+ * Streams.  Every compute call only enqueues work on `stream` and returns;
+ * nothing synchronises the device.  A handle may be used by one host thread
+ * at a time, and calls on one handle must not overlap on different streams.
+ *
+ * Errors.  Every function returns a status: BDC_OK (0); -i when argument i
+ * (1-based) is invalid, detected on the host before any device work; or one
+ * of the negative BDC_ERR_* codes below.  Conditions found on the device
+ * (non-finite input, iteration caps) are reported by bdc_get_info after the
+ * stream has been synchronised.
+ */
+#ifndef BDC_H_
+#define BDC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bdc_handle_s* bdc_handle_t;
+typedef void* bdc_stream_t; /* a hipStream_t; NULL = the default stream */
+
+enum {
+  BDC_OK = 0,
+  BDC_ERR_INVALID_HANDLE = -1001, /* NULL or destroyed handle */
+  BDC_ERR_NO_DEVICE = -1002,      /* no HIP device, or device index out of range */
+  BDC_ERR_NOMEM = -1003,          /* workspace would exceed the cap, or hipMalloc failed */
+  BDC_ERR_HIP = -1004,            /* a HIP runtime call failed */
+  BDC_ERR_NONFINITE = -1005,      /* (info) d or e holds Inf or NaN */
+  BDC_ERR_UNSUPPORTED = -1006     /* option value not supported by this build */
+};
+
+/* Options; bdc_default_options fills the defaults. */
+typedef struct {
+  int leaf_size;              /* largest leaf (rows), 4..32; default 32 (Section 4.2.2: 32 was best) */
+  int max_secular_iters;      /* evaluations of the secular function per root, 2..64; default 64 */
+  int max_leaf_sweeps;        /* QR sweeps per leaf row, 1..1000; default 40 (cap = value * m) */
+  size_t workspace_cap_bytes; /* 0 = unlimited */
+  int timing;                 /* 1: record per-kernel event times (bdc_get_timing) */
+} bdc_options_t;
+
+void bdc_default_options(bdc_options_t* opt);
+
+/* Create a handle on HIP device `device`.  opt may be NULL (defaults).
+ * Returns BDC_ERR_NO_DEVICE when the device does not exist. */
+int bdc_create(bdc_handle_t* handle, int device, const bdc_options_t* opt);
+
+/* Wait for the handle's outstanding work, then free it and its workspace. */
+int bdc_destroy(bdc_handle_t handle);
+
+/* B = U diag(sigma) VT for one n x n upper bidiagonal (Algorithm 2).
+ *   n      >= 0 (0 is a no-op)
+ *   d      device, n doubles (diagonal)
+ *   e      device, n-1 doubles (superdiagonal); may be NULL when n <= 1
+ *   sigma  device, n doubles, out: descending, >= 0
+ *   U      device, n*n doubles, column-major, out: left singular vectors
+ *   VT     device, n*n doubles, column-major, out: V^T (row i = right vector i)
+ *   stream the HIP stream to enqueue on
+ * U and VT must not overlap each other or the inputs. */
+int bdc_svd(bdc_handle_t handle, int64_t n, const double* d, const double* e,
+            double* sigma, double* U, double* VT, bdc_stream_t stream);
+
+/* Many independent bidiagonals of uneven sizes in one call; merge levels of
+ * all problems run together (the independent subproblems noted in Section
+ * 4.2.2).
+ *   batch   >= 0 problems; sizes  host array of `batch` sizes n_i >= 0
+ *   d, e    device, packed: problem i at offset off_i = sum_{j<i} n_j (e uses
+ *           the same offsets; its entry off_i + n_i - 1 is ignored)
+ *   sigma   device, packed like d
+ *   U, VT   device, packed: problem i at offset sum_{j<i} n_j^2, each
+ *           n_i x n_i column-major */
+int bdc_svd_batched(bdc_handle_t handle, int64_t batch, const int64_t* sizes,
+                    const double* d, const double* e, double* sigma, double* U,
+                    double* VT, bdc_stream_t stream);
+
+/* Diagnostics of the last bdc_svd / bdc_svd_batched call; valid once its
+ * stream has been synchronised (this call synchronises the handle's stream).
+ *   info  out (may be NULL): 0 on success, BDC_ERR_NONFINITE when the input
+ *         held Inf/NaN, else the number of leaves plus secular roots that hit
+ *         their iteration cap (their results are the last iterate).
+ *   stats out (may be NULL): counters, see bdc_stats_t. */
+typedef struct {
+  int64_t merges;              /* merge nodes solved */
+  int64_t roots;               /* secular roots solved (sum of N over merges) */
+  int64_t secular_evals;       /* evaluations of the secular function (sum over roots) */
+  int64_t deflated_small_z;    /* deflations by small z component */
+  int64_t deflated_zero_d;     /* deflations of values within tol of 0 */
+  int64_t deflated_close;      /* deflations of close value pairs */
+  int64_t rotations;           /* Givens rotations applied by deflation */
+  double update_flops;         /* flops of the vector-update products actually executed */
+  int64_t root_N;              /* non-deflated size at the root merge (first problem) */
+  int64_t levels;              /* merge levels */
+  int64_t secular_terms;       /* pole terms summed by the secular evaluations */
+  double leaf_flops;           /* flops of the rotations applied by the leaf solves */
+  double gather_bytes;         /* bytes moved gathering the kept columns (read + write) */
+  int64_t final_read_elems;    /* nonzero-support entries read to write U and V^T */
+} bdc_stats_t;
+
+int bdc_get_info(bdc_handle_t handle, int64_t* info, bdc_stats_t* stats);
+
+/* Per-kernel times, when options.timing = 1, summed over the calls since the
+ * handle was created or bdc_clear_timing was last called.  Each launch is
+ * bracketed by HIP events on the call's stream.  Synchronises the stream,
+ * fills up to `cap` entries of kernel names / total milliseconds / launch
+ * counts and returns the number of kernel kinds. */
+int bdc_get_timing(bdc_handle_t handle, int cap, const char** names, double* ms,
+                   int64_t* launches);
+int bdc_clear_timing(bdc_handle_t handle);
+
+/* ---- single-step entry points ------------------------------------------
+ * They run one stage of a merge through the same device code as bdc_svd, on
+ * caller-provided inputs, so each stage can be compared with an independent
+ * implementation on identical inputs.  All arrays are device pointers. */
+
+/* Leaf SVD by QR iteration (Algorithm 2 step (1)) of the m x (m+s) upper
+ * bidiagonal with diagonal d (m) and superdiagonal e (m-1+s; with s = 1 the
+ * last entry is in column m+1).  1 <= m <= 32, s in {0,1}.
+ * Out: sigma (m, ascending), W (m*m, col-major), Q ((m+s)^2, col-major, the
+ * last column spans the null space when s = 1). */
+int bdc_step_leaf(bdc_handle_t handle, int m, int s, const double* d, const double* e,
+                  double* sigma, double* W, double* Q, bdc_stream_t stream);
+
+/* z formation, sort and deflation of one merge (Algorithm 3).
+ *   m, s, k = m/2: node size; sig  (m) children's values (sig[0..k-2] the
+ *   left child's, ascending; sig[k-1] ignored; sig[k..m-1] the right child's,
+ *   ascending); qrow1 (k): last row of the left child's right basis, qrow1[k-1]
+ *   = last entry of its null vector; qrow2 (m-k+s): first row of the right
+ *   child's right basis, qrow2[m-k] = first entry of its null vector if s=1;
+ *   alpha, beta: the middle row's entries (Section 4.2.1 divide step).
+ * Out (device):
+ *   perm   (m int32): sorted position -> node column (middle = k-1 first)
+ *   dz     (2m doubles): values then z at sorted positions after deflation,
+ *          scaled by the power of two `scale`
+ *   status (m int32): 0 kept, 1 small z, 2 value within tol of 0, 3 close pair
+ *   rot_pos (2m int32) and rot_cs (2m doubles): rotation r rotates sorted
+ *          positions (rot_pos[2r], rot_pos[2r+1]) with (c, s) =
+ *          (rot_cs[2r], rot_cs[2r+1]); kind 2 when rot_pos[2r] = 0, else 3
+ *   misc   (8 doubles): scale, tol, c0, s0, N, n1, n2, n3 (counts as doubles)
+ *   nrot   (1 int32): number of rotations. */
+int bdc_step_deflate(bdc_handle_t handle, int m, int s, const double* sig,
+                     const double* qrow1, const double* qrow2, double alpha, double beta,
+                     int32_t* perm, double* dz, int32_t* status, int32_t* rot_pos,
+                     double* rot_cs, double* misc, int32_t* nrot, bdc_stream_t stream);
+
+/* Roots of the secular equation 1 + sum_j z_j^2/(d_j^2 - w^2) = 0 (eq.
+ * M-svd-val) for d (N, strictly increasing, d[0] = 0) and z (N, no zero):
+ * w_i = d[o_i] + tau_i; iters = evaluations per root. */
+int bdc_step_secular(bdc_handle_t handle, int N, const double* d, const double* z,
+                     int32_t* o, double* tau, int32_t* iters, bdc_stream_t stream);
+
+/* Recomputed z (eq. bdc-zi) and the normalised singular vectors of
+ * M~ = e_1 zt^T + diag(d) (eq. M-svd-vec), from d, z, o, tau as above.
+ * Out: zt (N), UM and VM (N*N col-major, column i belongs to root i). */
+int bdc_step_vectors(bdc_handle_t handle, int N, const double* d, const double* z,
+                     const int32_t* o, const double* tau, double* zt, double* UM,
+                     double* VM, bdc_stream_t stream);
+
+/* C (M x N, ldc) = A (M x K, lda) * B (K x N, ldb), column-major, with the
+ * FP64 matrix-core kernel of the vector update (eq. bdc-Mv2Bv-u-vt). */
+int bdc_step_gemm(bdc_handle_t handle, int M, int N, int K, const double* A, int lda,
+                  const double* B, int ldb, double* C, int ldc, bdc_stream_t stream);
+
+const char* bdc_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BDC_H_ */

@@ -1,0 +1,202 @@
+"""Python binding of the bidiagonal divide-and-conquer SVD (torch tensors in,
+torch tensors out).  Argument marshalling only: every step of the solve runs
+in the HIP kernels of libbdc.so, which must be built; there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import check
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _f64(t, device) -> torch.Tensor:
+    t = torch.as_tensor(t, dtype=torch.float64, device=device)
+    return t.contiguous()
+
+
+class Solver:
+    """One handle of the C ABI (workspace, plan cache) on one GPU."""
+
+    def __init__(self, device: int | torch.device = 0, leaf_size: int = 32, max_secular_iters: int = 64,
+                 max_leaf_sweeps: int = 40, workspace_cap_bytes: int = 0, timing: bool = False):
+        self.lib = _lib.load()
+        dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        if dev.type != "cuda":
+            raise ValueError("the solver runs on a GPU device")
+        self.device = torch.device("cuda", dev.index if dev.index is not None else 0)
+        opt = _lib.Options()
+        self.lib.bdc_default_options(ctypes.byref(opt))
+        opt.leaf_size = leaf_size
+        opt.max_secular_iters = max_secular_iters
+        opt.max_leaf_sweeps = max_leaf_sweeps
+        opt.workspace_cap_bytes = workspace_cap_bytes
+        opt.timing = 1 if timing else 0
+        h = ctypes.c_void_p()
+        check("bdc_create", self.lib.bdc_create(ctypes.byref(h), self.device.index, ctypes.byref(opt)))
+        self.handle = h
+
+    def close(self) -> None:
+        if self.handle:
+            self.lib.bdc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self) -> int:
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    # ---------------------------------------------------------------- solves
+    def svd(self, d, e, out=None):
+        """B = U diag(sigma) VT for the n x n upper bidiagonal (d, e).
+
+        Returns (sigma, U, VT) as float64 tensors on the device; sigma is
+        descending.  ``out`` may supply (sigma, Ubuf, VTbuf) buffers of shapes
+        (n,), (n, n), (n, n); U and VT are returned as transposed views of the
+        column-major buffers."""
+        d = _f64(d, self.device)
+        n = d.shape[0]
+        e = _f64(e, self.device) if n > 1 else None
+        if e is not None and e.shape[0] < n - 1:
+            raise ValueError("e must hold n-1 entries")
+        if out is None:
+            sigma = torch.empty(n, dtype=torch.float64, device=self.device)
+            ub = torch.empty((n, n), dtype=torch.float64, device=self.device)
+            vb = torch.empty((n, n), dtype=torch.float64, device=self.device)
+        else:
+            sigma, ub, vb = out
+        check("bdc_svd", self.lib.bdc_svd(self.handle, n, _ptr(d), _ptr(e), _ptr(sigma), _ptr(ub),
+                                          _ptr(vb), self._stream()))
+        return sigma, ub.T, vb.T
+
+    def svd_batched(self, sizes, d, e):
+        """Many bidiagonals in one call.  d, e packed at offsets sum(n_j);
+        returns (sigma packed like d, U packed, VT packed), where problem i's
+        U is ``U[mo_i : mo_i + n_i*n_i].view(n_i, n_i).T`` with
+        mo_i = sum_{j<i} n_j^2 (column-major storage)."""
+        sizes = [int(x) for x in sizes]
+        arr = (ctypes.c_int64 * max(1, len(sizes)))(*sizes)
+        d = _f64(d, self.device)
+        e = _f64(e, self.device)
+        tot = sum(sizes)
+        tot2 = sum(x * x for x in sizes)
+        sigma = torch.empty(tot, dtype=torch.float64, device=self.device)
+        U = torch.empty(tot2, dtype=torch.float64, device=self.device)
+        VT = torch.empty(tot2, dtype=torch.float64, device=self.device)
+        check("bdc_svd_batched", self.lib.bdc_svd_batched(self.handle, len(sizes), arr, _ptr(d), _ptr(e),
+                                                          _ptr(sigma), _ptr(U), _ptr(VT), self._stream()))
+        return sigma, U, VT
+
+    def info(self):
+        """(info, stats dict) of the last solve (synchronises)."""
+        info = ctypes.c_int64()
+        st = _lib.Stats()
+        check("bdc_get_info", self.lib.bdc_get_info(self.handle, ctypes.byref(info), ctypes.byref(st)))
+        return int(info.value), st.as_dict()
+
+    def timing(self) -> dict:
+        cap = 32
+        names = (ctypes.c_char_p * cap)()
+        ms = (ctypes.c_double * cap)()
+        cnt = (ctypes.c_int64 * cap)()
+        k = self.lib.bdc_get_timing(self.handle, cap, names, ms, cnt)
+        if k < 0:
+            raise _lib.BdcError("bdc_get_timing", k)
+        return {names[i].decode(): (ms[i], int(cnt[i])) for i in range(k)}
+
+    def clear_timing(self) -> None:
+        check("bdc_clear_timing", self.lib.bdc_clear_timing(self.handle))
+
+    # ---------------------------------------------------------------- steps
+    def step_leaf(self, d, e, s: int):
+        d = _f64(d, self.device)
+        m = d.shape[0]
+        e = _f64(e, self.device) if m - 1 + s > 0 else None
+        sig = torch.empty(m, dtype=torch.float64, device=self.device)
+        W = torch.empty((m, m), dtype=torch.float64, device=self.device)
+        Q = torch.empty((m + s, m + s), dtype=torch.float64, device=self.device)
+        check("bdc_step_leaf", self.lib.bdc_step_leaf(self.handle, m, s, _ptr(d), _ptr(e), _ptr(sig), _ptr(W),
+                                                      _ptr(Q), self._stream()))
+        return sig, W.T, Q.T
+
+    def step_deflate(self, m: int, s: int, sig, qrow1, qrow2, alpha: float, beta: float) -> dict:
+        sig = _f64(sig, self.device)
+        q1 = _f64(qrow1, self.device)
+        q2 = _f64(qrow2, self.device)
+        dev = self.device
+        perm = torch.empty(m, dtype=torch.int32, device=dev)
+        dz = torch.empty(2 * m, dtype=torch.float64, device=dev)
+        status = torch.empty(m, dtype=torch.int32, device=dev)
+        rot_pos = torch.zeros(2 * m, dtype=torch.int32, device=dev)
+        rot_cs = torch.zeros(2 * m, dtype=torch.float64, device=dev)
+        misc = torch.empty(8, dtype=torch.float64, device=dev)
+        nrot = torch.zeros(1, dtype=torch.int32, device=dev)
+        check("bdc_step_deflate", self.lib.bdc_step_deflate(
+            self.handle, m, s, _ptr(sig), _ptr(q1), _ptr(q2), float(alpha), float(beta), _ptr(perm), _ptr(dz),
+            _ptr(status), _ptr(rot_pos), _ptr(rot_cs), _ptr(misc), _ptr(nrot), self._stream()))
+        nr = int(nrot.item())
+        misc = misc.cpu().numpy()
+        return {
+            "perm": perm.cpu().numpy(), "d": dz[:m].cpu().numpy(), "z": dz[m:].cpu().numpy(),
+            "status": status.cpu().numpy(), "rot_pos": rot_pos[: 2 * nr].cpu().numpy().reshape(-1, 2),
+            "rot_cs": rot_cs[: 2 * nr].cpu().numpy().reshape(-1, 2), "scale": misc[0], "tol": misc[1],
+            "c0": misc[2], "s0": misc[3], "N": int(misc[4]), "counts": (int(misc[5]), int(misc[6]), int(misc[7])),
+        }
+
+    def step_secular(self, d, z):
+        d = _f64(d, self.device)
+        z = _f64(z, self.device)
+        N = d.shape[0]
+        o = torch.empty(N, dtype=torch.int32, device=self.device)
+        tau = torch.empty(N, dtype=torch.float64, device=self.device)
+        it = torch.empty(N, dtype=torch.int32, device=self.device)
+        check("bdc_step_secular", self.lib.bdc_step_secular(self.handle, N, _ptr(d), _ptr(z), _ptr(o), _ptr(tau),
+                                                            _ptr(it), self._stream()))
+        return o, tau, it
+
+    def step_vectors(self, d, z, o, tau):
+        d = _f64(d, self.device)
+        z = _f64(z, self.device)
+        o = torch.as_tensor(o, dtype=torch.int32, device=self.device).contiguous()
+        tau = _f64(tau, self.device)
+        N = d.shape[0]
+        zt = torch.empty(N, dtype=torch.float64, device=self.device)
+        UM = torch.empty((N, N), dtype=torch.float64, device=self.device)
+        VM = torch.empty((N, N), dtype=torch.float64, device=self.device)
+        check("bdc_step_vectors", self.lib.bdc_step_vectors(self.handle, N, _ptr(d), _ptr(z), _ptr(o), _ptr(tau),
+                                                            _ptr(zt), _ptr(UM), _ptr(VM), self._stream()))
+        return zt, UM.T, VM.T
+
+    def step_gemm(self, A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
+        """C = A @ B through the update kernel (A, B float64 on the device)."""
+        M, K = A.shape
+        K2, N = B.shape
+        assert K == K2
+        Ac = A.T.contiguous()  # column-major storage
+        Bc = B.T.contiguous()
+        C = torch.empty((N, M), dtype=torch.float64, device=self.device)
+        check("bdc_step_gemm", self.lib.bdc_step_gemm(self.handle, M, N, K, _ptr(Ac), max(1, M), _ptr(Bc),
+                                                      max(1, K), _ptr(C), max(1, M), self._stream()))
+        return C.T
+
+
+_DEFAULT: dict = {}
+
+
+def svd(d, e, device: int = 0):
+    """B = U diag(sigma) VT on the GPU with a cached default solver."""
+    s = _DEFAULT.get(device)
+    if s is None:
+        s = _DEFAULT[device] = Solver(device)
+    return s.svd(d, e)

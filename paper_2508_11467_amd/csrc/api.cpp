@@ -1,0 +1,550 @@
+// C ABI of the bidiagonal divide-and-conquer SVD: argument checks, the merge
+// tree plan, the workspace, and the level-by-level launch sequence.
+//
+// The host only builds the plan (the recursive split of Section 4.2.1 at
+// k = floor(m/2) down to leaves of at most leaf_size rows) and enqueues
+// kernels: every size that depends on the data (how many values survive
+// deflation, how many roots, how many rotations) is written and read on the
+// device, so a whole solve is one stream of launches with no host
+// synchronisation and no matrix traffic between host and device.  Nodes of
+// equal height in the tree -- across all problems of a batch -- form one
+// level and run in the same launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "bdc.h"
+#include "bdc_internal.h"
+
+using namespace bdc;
+
+namespace {
+
+constexpr uint32_t kMagic = 0xBDC05EEDu;
+
+enum Kind { kReset = 0, kLeaf, kPrep, kRotate, kGather, kSecular, kLowner, kVectors, kOrder, kUpdate, kFinal, kKinds };
+const char* kKindNames[kKinds] = {"reset", "leaf", "deflate", "rotate", "gather", "secular",
+                                  "lowner", "vectors", "order", "update_gemm", "final"};
+
+struct Level {
+  int nnodes = 0;
+  int max_m = 0;
+  NodeDesc* dev = nullptr;
+};
+
+struct Plan {
+  std::vector<int64_t> sizes;
+  int leaf = 0;
+  int64_t total_n = 0, total_n2 = 0;
+  int nleaves = 0;
+  LeafDesc* dev_leaves = nullptr;
+  std::vector<Level> levels;
+  std::vector<NodeDesc> host_nodes;
+  int nnodes = 0;
+  int nprob = 0;
+  int64_t* dev_prob = nullptr;  // n, vec, mat, col_off, tile_off (nprob each)
+  int64_t total_cols = 0, total_tiles = 0;
+  int root_id0 = -1;  // node id of the first problem's root merge
+  void* block = nullptr;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct bdc_handle_s {
+  uint32_t magic = kMagic;
+  int device = 0;
+  bdc_options_t opt{};
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  int64_t cap_n = -1, cap_n2 = -1;
+  int cap_nodes = -1;
+  Work w{};
+  Plan plan;
+  bool plan_valid = false;
+  hipStream_t last_stream = nullptr;
+  bool have_call = false;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int old = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&old) != hipSuccess) old = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (old >= 0) (void)hipSetDevice(old);
+  }
+};
+
+bool valid(bdc_handle_t h) { return h != nullptr && h->magic == kMagic; }
+
+void free_plan(Plan& p) {
+  if (p.block) (void)hipFree(p.block);
+  p = Plan();
+}
+
+int build_node(std::vector<LeafDesc>& leaves, std::vector<std::vector<NodeDesc>>& by_h,
+               int64_t mat_off, int64_t vec_off, int32_t n, int leaf, int32_t r0, int32_t m, int32_t s) {
+  if (m <= leaf) {
+    leaves.push_back(LeafDesc{mat_off, vec_off, n, r0, m, s});
+    return 0;
+  }
+  const int32_t k = m / 2;
+  const int hl = build_node(leaves, by_h, mat_off, vec_off, n, leaf, r0, k - 1, 1);
+  const int hr = build_node(leaves, by_h, mat_off, vec_off, n, leaf, r0 + k, m - k, s);
+  const int h = 1 + std::max(hl, hr);
+  if ((int)by_h.size() <= h) by_h.resize(h + 1);
+  by_h[h].push_back(NodeDesc{mat_off, vec_off, n, r0, m, s, k, -1});
+  return h;
+}
+
+int make_plan(bdc_handle_t h, const int64_t* sizes, int64_t batch) {
+  const int leaf = h->opt.leaf_size;
+  if (h->plan_valid && h->plan.leaf == leaf && (int64_t)h->plan.sizes.size() == batch &&
+      std::equal(h->plan.sizes.begin(), h->plan.sizes.end(), sizes))
+    return BDC_OK;
+  if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
+  free_plan(h->plan);
+  h->plan_valid = false;
+  Plan p;
+  p.sizes.assign(sizes, sizes + batch);
+  p.leaf = leaf;
+  p.nprob = (int)batch;
+  std::vector<LeafDesc> leaves;
+  std::vector<std::vector<NodeDesc>> by_h;
+  std::vector<int64_t> pn(batch), pvec(batch), pmat(batch), pcol(batch), ptile(batch);
+  int64_t vo = 0, mo = 0, co = 0, to = 0;
+  for (int64_t i = 0; i < batch; ++i) {
+    const int64_t n = sizes[i];
+    pn[i] = n;
+    pvec[i] = vo;
+    pmat[i] = mo;
+    pcol[i] = co;
+    ptile[i] = to;
+    if (n > 0) build_node(leaves, by_h, mo, vo, (int32_t)n, leaf, 0, (int32_t)n, 0);
+    vo += n;
+    mo += n * n;
+    co += n;
+    to += ((n + 63) / 64) * ((n + 63) / 64);
+  }
+  p.total_n = vo;
+  p.total_n2 = mo;
+  p.total_cols = co;
+  p.total_tiles = to;
+  p.nleaves = (int)leaves.size();
+  // node ids level by level; remember the first problem's root
+  int id = 0;
+  for (size_t hh = 1; hh < by_h.size(); ++hh)
+    for (auto& nd : by_h[hh]) {
+      nd.id = id++;
+      if (nd.vec_off == 0 && nd.r0 == 0 && batch > 0 && nd.m == sizes[0]) p.root_id0 = nd.id;
+      p.host_nodes.push_back(nd);
+    }
+  p.nnodes = id;
+  size_t bytes = align_up(sizeof(LeafDesc) * std::max<size_t>(1, leaves.size())) +
+                 align_up(sizeof(NodeDesc) * std::max(1, id)) +
+                 align_up(sizeof(int64_t) * 5 * std::max<int64_t>(1, batch));
+  if (hipMalloc(&p.block, bytes) != hipSuccess) return BDC_ERR_NOMEM;
+  char* b = (char*)p.block;
+  p.dev_leaves = (LeafDesc*)b;
+  b += align_up(sizeof(LeafDesc) * std::max<size_t>(1, leaves.size()));
+  NodeDesc* nodes_dev = (NodeDesc*)b;
+  b += align_up(sizeof(NodeDesc) * std::max(1, id));
+  p.dev_prob = (int64_t*)b;
+  if (!leaves.empty() &&
+      hipMemcpy(p.dev_leaves, leaves.data(), sizeof(LeafDesc) * leaves.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return BDC_ERR_HIP;
+  if (id > 0 && hipMemcpy(nodes_dev, p.host_nodes.data(), sizeof(NodeDesc) * id, hipMemcpyHostToDevice) != hipSuccess)
+    return BDC_ERR_HIP;
+  std::vector<int64_t> prob(5 * std::max<int64_t>(1, batch), 0);
+  for (int64_t i = 0; i < batch; ++i) {
+    prob[i] = pn[i];
+    prob[batch + i] = pvec[i];
+    prob[2 * batch + i] = pmat[i];
+    prob[3 * batch + i] = pcol[i];
+    prob[4 * batch + i] = ptile[i];
+  }
+  if (batch > 0 && hipMemcpy(p.dev_prob, prob.data(), sizeof(int64_t) * 5 * batch, hipMemcpyHostToDevice) != hipSuccess)
+    return BDC_ERR_HIP;
+  int off = 0;
+  for (size_t hh = 1; hh < by_h.size(); ++hh) {
+    Level L;
+    L.nnodes = (int)by_h[hh].size();
+    L.dev = nodes_dev + off;
+    for (auto& nd : by_h[hh]) L.max_m = std::max(L.max_m, nd.m);
+    off += L.nnodes;
+    p.levels.push_back(L);
+  }
+  h->plan = std::move(p);
+  h->plan_valid = true;
+  return BDC_OK;
+}
+
+// Workspace: four n x n matrices per problem (Uwork, Vwork, UM, VM), the
+// per-position arrays and the node states.
+int ensure_workspace(bdc_handle_t h, int64_t tn, int64_t tn2, int nnodes) {
+  if (tn <= h->cap_n && tn2 <= h->cap_n2 && nnodes <= h->cap_nodes && h->arena) return BDC_OK;
+  tn = std::max<int64_t>(tn, h->cap_n);
+  tn2 = std::max<int64_t>(tn2, h->cap_n2);
+  nnodes = std::max(nnodes, h->cap_nodes);
+  const size_t N1 = (size_t)std::max<int64_t>(tn, 1), N2 = (size_t)std::max<int64_t>(tn2, 1);
+  const size_t nd_ = (size_t)std::max(nnodes, 1);
+  size_t bytes = 4 * align_up(N2 * 8) + 8 * align_up(N1 * 8) + align_up(2 * N1 * 8) +
+                 19 * align_up(N1 * 4) + 2 * align_up(2 * N1 * 4) + align_up(nd_ * sizeof(NodeState)) +
+                 align_up(sizeof(Ctl));
+  if (h->opt.workspace_cap_bytes && bytes > h->opt.workspace_cap_bytes) return BDC_ERR_NOMEM;
+  if (h->arena) {
+    if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
+    (void)hipFree(h->arena);
+    h->arena = nullptr;
+    h->arena_bytes = 0;
+  }
+  if (hipMalloc(&h->arena, bytes) != hipSuccess) {
+    h->arena = nullptr;
+    h->cap_n = h->cap_n2 = -1;
+    h->cap_nodes = -1;
+    return BDC_ERR_NOMEM;
+  }
+  h->arena_bytes = bytes;
+  char* b = (char*)h->arena;
+  auto take = [&](size_t nbytes) {
+    char* r = b;
+    b += align_up(nbytes);
+    return (void*)r;
+  };
+  Work& w = h->w;
+  w.Uw = (double*)take(N2 * 8);
+  w.Vw = (double*)take(N2 * 8);
+  w.UM = (double*)take(N2 * 8);
+  w.VM = (double*)take(N2 * 8);
+  w.sig = (double*)take(N1 * 8);
+  w.ps_d = (double*)take(N1 * 8);
+  w.ps_z = (double*)take(N1 * 8);
+  w.sd = (double*)take(N1 * 8);
+  w.sz = (double*)take(N1 * 8);
+  w.dval = (double*)take(N1 * 8);
+  w.tau = (double*)take(N1 * 8);
+  w.zt = (double*)take(N1 * 8);
+  w.rot_cs = (double*)take(2 * N1 * 8);
+  w.col = (int32_t*)take(N1 * 4);
+  w.ulo = (int32_t*)take(N1 * 4);
+  w.uhi = (int32_t*)take(N1 * 4);
+  w.vlo = (int32_t*)take(N1 * 4);
+  w.vhi = (int32_t*)take(N1 * 4);
+  w.ps_c = (int32_t*)take(N1 * 4);
+  w.ps_col = (int32_t*)take(N1 * 4);
+  w.ps_sup = (int32_t*)take(N1 * 4);
+  w.status = (int32_t*)take(N1 * 4);
+  w.ps_rot = (int32_t*)take(N1 * 4);
+  w.cand = (int32_t*)take(N1 * 4);
+  w.scol = (int32_t*)take(N1 * 4);
+  w.srot = (int32_t*)take(N1 * 4);
+  w.sgrp = (int32_t*)take(N1 * 4);
+  w.gsurv = (int32_t*)take(N1 * 4);
+  w.dcol = (int32_t*)take(N1 * 4);
+  w.drot = (int32_t*)take(N1 * 4);
+  w.o = (int32_t*)take(N1 * 4);
+  w.iters = (int32_t*)take(N1 * 4);
+  w.rot_pos = (int32_t*)take(2 * N1 * 4);
+  w.rot_col = (int32_t*)take(2 * N1 * 4);
+  w.st = (NodeState*)take(nd_ * sizeof(NodeState));
+  w.ctl = (Ctl*)take(sizeof(Ctl));
+  h->cap_n = tn;
+  h->cap_n2 = tn2;
+  h->cap_nodes = nnodes;
+  return BDC_OK;
+}
+
+hipEvent_t next_event(bdc_handle_t h) {
+  if (h->pool_used == h->pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->pool.push_back(e);
+  }
+  return h->pool[h->pool_used++];
+}
+
+struct Timer {
+  bdc_handle_t h;
+  hipStream_t st;
+  int kind;
+  hipEvent_t a = nullptr;
+  Timer(bdc_handle_t h_, hipStream_t st_, int kind_) : h(h_), st(st_), kind(kind_) {
+    if (h->opt.timing) {
+      a = next_event(h);
+      if (a) (void)hipEventRecord(a, st);
+    }
+  }
+  ~Timer() {
+    if (h->opt.timing && a) {
+      hipEvent_t b = next_event(h);
+      if (b) {
+        (void)hipEventRecord(b, st);
+        h->recs.push_back({kind, a, b});
+      }
+    }
+  }
+};
+
+int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, double* U, double* VT,
+             hipStream_t st) {
+  const Plan& p = h->plan;
+  Work w = h->w;
+  w.d = d;
+  w.e = e;
+  w.GU = U;
+  w.GV = VT;
+  w.max_secular_iters = h->opt.max_secular_iters;
+  w.max_leaf_sweeps = h->opt.max_leaf_sweeps;
+  {
+    Timer t(h, st, kReset);
+    launch_reset(w.ctl, st);
+  }
+  {
+    Timer t(h, st, kLeaf);
+    launch_leaf(p.dev_leaves, p.nleaves, w, st);
+  }
+  for (const Level& L : p.levels) {
+    { Timer t(h, st, kPrep); launch_prep(L.dev, L.nnodes, L.max_m, w, st); }
+    { Timer t(h, st, kRotate); launch_rotate(L.dev, L.nnodes, L.max_m, w, st); }
+    { Timer t(h, st, kGather); launch_gather(L.dev, L.nnodes, L.max_m, w, st); }
+    { Timer t(h, st, kSecular); launch_secular(L.dev, L.nnodes, L.max_m, w, st); }
+    { Timer t(h, st, kLowner); launch_lowner(L.dev, L.nnodes, L.max_m, w, st); }
+    { Timer t(h, st, kVectors); launch_vectors(L.dev, L.nnodes, L.max_m, w, st); }
+    { Timer t(h, st, kOrder); launch_order(L.dev, L.nnodes, L.max_m, w, st); }
+    { Timer t(h, st, kUpdate); launch_update(L.dev, L.nnodes, L.max_m, w, st); }
+  }
+  {
+    Timer t(h, st, kFinal);
+    const int64_t np = p.nprob;
+    launch_final(p.dev_prob, p.dev_prob + np, p.dev_prob + 2 * np, p.dev_prob + 3 * np, p.dev_prob + 4 * np,
+                 p.nprob, p.total_cols, p.total_tiles, w, sigma, U, VT, st);
+  }
+  if (hipGetLastError() != hipSuccess) return BDC_ERR_HIP;
+  h->last_stream = st;
+  h->have_call = true;
+  return BDC_OK;
+}
+
+int solve(bdc_handle_t h, int64_t batch, const int64_t* sizes, const double* d, const double* e,
+          double* sigma, double* U, double* VT, hipStream_t st) {
+  DeviceGuard g(h->device);
+  if (!g.ok) return BDC_ERR_HIP;
+  int rc = make_plan(h, sizes, batch);
+  if (rc != BDC_OK) return rc;
+  rc = ensure_workspace(h, h->plan.total_n, h->plan.total_n2, h->plan.nnodes);
+  if (rc != BDC_OK) return rc;
+  if (h->plan.total_n == 0) {
+    h->last_stream = st;
+    h->have_call = true;
+    launch_reset(h->w.ctl, st);
+    return hipGetLastError() == hipSuccess ? BDC_OK : BDC_ERR_HIP;
+  }
+  return run_plan(h, d, e, sigma, U, VT, st);
+}
+
+}  // namespace
+
+int bdc::handle_info(bdc_handle_t h, int* device, int* max_secular_iters, int* max_leaf_sweeps) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  *device = h->device;
+  *max_secular_iters = h->opt.max_secular_iters;
+  *max_leaf_sweeps = h->opt.max_leaf_sweeps;
+  return BDC_OK;
+}
+
+extern "C" {
+
+void bdc_default_options(bdc_options_t* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->leaf_size = 32;
+  opt->max_secular_iters = 64;
+  opt->max_leaf_sweeps = 40;
+  opt->workspace_cap_bytes = 0;
+  opt->timing = 0;
+}
+
+int bdc_create(bdc_handle_t* handle, int device, const bdc_options_t* opt) {
+  if (!handle) return -1;
+  *handle = nullptr;
+  bdc_options_t o;
+  bdc_default_options(&o);
+  if (opt) o = *opt;
+  if (o.leaf_size < 4 || o.leaf_size > kMaxLeaf) return -3;
+  if (o.max_secular_iters < 2 || o.max_secular_iters > 64) return -3;
+  if (o.max_leaf_sweeps < 1 || o.max_leaf_sweeps > 1000) return -3;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return BDC_ERR_NO_DEVICE;
+  if (device < 0 || device >= count) return BDC_ERR_NO_DEVICE;
+  bdc_handle_s* h = new (std::nothrow) bdc_handle_s();
+  if (!h) return BDC_ERR_NOMEM;
+  h->device = device;
+  h->opt = o;
+  *handle = h;
+  return BDC_OK;
+}
+
+int bdc_destroy(bdc_handle_t h) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  {
+    DeviceGuard g(h->device);
+    if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
+    free_plan(h->plan);
+    if (h->arena) (void)hipFree(h->arena);
+    for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
+  }
+  h->magic = 0;
+  delete h;
+  return BDC_OK;
+}
+
+int bdc_svd(bdc_handle_t h, int64_t n, const double* d, const double* e, double* sigma, double* U,
+            double* VT, bdc_stream_t stream) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  if (n < 0 || n > (int64_t)INT32_MAX / 2) return -2;
+  if (n > 0 && !d) return -3;
+  if (n > 1 && !e) return -4;
+  if (n > 0 && !sigma) return -5;
+  if (n > 0 && !U) return -6;
+  if (n > 0 && !VT) return -7;
+  if (n > 0 && U == VT) return -7;
+  return solve(h, 1, &n, d, e, sigma, U, VT, (hipStream_t)stream);
+}
+
+int bdc_svd_batched(bdc_handle_t h, int64_t batch, const int64_t* sizes, const double* d,
+                    const double* e, double* sigma, double* U, double* VT, bdc_stream_t stream) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  if (batch < 0 || batch > (int64_t)INT32_MAX) return -2;
+  if (batch > 0 && !sizes) return -3;
+  int64_t total = 0, maxn = 0;
+  for (int64_t i = 0; i < batch; ++i) {
+    if (sizes[i] < 0 || sizes[i] > (int64_t)INT32_MAX / 2) return -3;
+    total += sizes[i];
+    maxn = std::max(maxn, sizes[i]);
+  }
+  if (total > (int64_t)INT32_MAX) return -3;
+  if (total > 0 && !d) return -4;
+  if (maxn > 1 && !e) return -5;
+  if (total > 0 && !sigma) return -6;
+  if (total > 0 && !U) return -7;
+  if (total > 0 && (!VT || VT == U)) return -8;
+  return solve(h, batch, sizes, d, e, sigma, U, VT, (hipStream_t)stream);
+}
+
+int bdc_get_info(bdc_handle_t h, int64_t* info, bdc_stats_t* stats) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  if (info) *info = 0;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (!h->have_call || !h->arena) return BDC_OK;
+  DeviceGuard g(h->device);
+  if (hipStreamSynchronize(h->last_stream) != hipSuccess) return BDC_ERR_HIP;
+  Ctl ctl;
+  if (hipMemcpy(&ctl, h->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) return BDC_ERR_HIP;
+  if (info) *info = ctl.nonfinite ? (int64_t)BDC_ERR_NONFINITE : (int64_t)ctl.leaf_capped + ctl.secular_capped;
+  if (stats && h->plan_valid) {
+    const Plan& p = h->plan;
+    std::vector<NodeState> sts(p.nnodes);
+    if (p.nnodes > 0 &&
+        hipMemcpy(sts.data(), h->w.st, sizeof(NodeState) * p.nnodes, hipMemcpyDeviceToHost) != hipSuccess)
+      return BDC_ERR_HIP;
+    stats->merges = p.nnodes;
+    stats->levels = (int64_t)p.levels.size();
+    stats->secular_evals = (int64_t)ctl.secular_evals;
+    double fl = 0.0;
+    for (int i = 0; i < p.nnodes; ++i) {
+      const NodeState& s = sts[i];
+      const NodeDesc& nd = p.host_nodes[i];
+      stats->roots += s.N;
+      stats->deflated_small_z += s.nsmall_z;
+      stats->deflated_zero_d += s.nzero_d;
+      stats->deflated_close += s.nclose;
+      stats->rotations += s.nrot;
+      const double N = s.N, top = s.n1 + 1 + s.n2, bot = 1 + s.n2 + s.n3;
+      fl += 2.0 * N * (nd.k * top + (nd.m - nd.k) * bot);          // left vectors
+      fl += 2.0 * N * (nd.k * top + (nd.m + nd.s - nd.k) * bot);   // right vectors
+    }
+    stats->update_flops = fl;
+    if (p.root_id0 >= 0) stats->root_N = sts[p.root_id0].N;
+    stats->secular_terms = (int64_t)ctl.secular_terms;
+    stats->leaf_flops = (double)ctl.leaf_rot_flops;
+    double gb = 0.0;
+    for (int i = 0; i < p.nnodes; ++i) {
+      const NodeDesc& nd = p.host_nodes[i];
+      gb += 16.0 * sts[i].N * (2.0 * nd.m + nd.s);  // read + write, U and V columns
+    }
+    stats->gather_bytes = gb;
+    // supports read by the final pass
+    const size_t tn = (size_t)p.total_n;
+    std::vector<int32_t> lo(tn), hi(tn), vl(tn), vh(tn), col(tn);
+    if (tn > 0 &&
+        (hipMemcpy(lo.data(), h->w.ulo, 4 * tn, hipMemcpyDeviceToHost) != hipSuccess ||
+         hipMemcpy(hi.data(), h->w.uhi, 4 * tn, hipMemcpyDeviceToHost) != hipSuccess ||
+         hipMemcpy(vl.data(), h->w.vlo, 4 * tn, hipMemcpyDeviceToHost) != hipSuccess ||
+         hipMemcpy(vh.data(), h->w.vhi, 4 * tn, hipMemcpyDeviceToHost) != hipSuccess))
+      return BDC_ERR_HIP;
+    int64_t fr = 0;
+    for (size_t c = 0; c < tn; ++c) fr += (int64_t)(hi[c] - lo[c]) + (int64_t)(vh[c] - vl[c]);
+    stats->final_read_elems = fr;
+  }
+  return BDC_OK;
+}
+
+int bdc_get_timing(bdc_handle_t h, int cap, const char** names, double* ms, int64_t* launches) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  double tot[kKinds] = {0};
+  int64_t cnt[kKinds] = {0};
+  if (h->have_call) {
+    DeviceGuard g(h->device);
+    if (hipStreamSynchronize(h->last_stream) != hipSuccess) return BDC_ERR_HIP;
+    for (auto& r : h->recs) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) tot[r.kind] += t;
+      cnt[r.kind] += 1;
+    }
+  }
+  for (int i = 0; i < kKinds && i < cap; ++i) {
+    if (names) names[i] = kKindNames[i];
+    if (ms) ms[i] = tot[i];
+    if (launches) launches[i] = cnt[i];
+  }
+  return kKinds;
+}
+
+int bdc_clear_timing(bdc_handle_t h) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  h->recs.clear();
+  h->pool_used = 0;
+  return BDC_OK;
+}
+
+const char* bdc_status_string(int status) {
+  switch (status) {
+    case BDC_OK: return "ok";
+    case BDC_ERR_INVALID_HANDLE: return "invalid handle";
+    case BDC_ERR_NO_DEVICE: return "no such HIP device";
+    case BDC_ERR_NOMEM: return "out of device memory or over the workspace cap";
+    case BDC_ERR_HIP: return "HIP runtime error";
+    case BDC_ERR_NONFINITE: return "input holds Inf or NaN";
+    case BDC_ERR_UNSUPPORTED: return "unsupported option";
+    default: return status < 0 ? "invalid argument" : "iteration caps reached";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// Internal structures of the bidiagonal divide-and-conquer solver (device
+// descriptors, per-call workspace pointers, kernel launchers).
+//
+// Layout in HBM (per problem p of size n, offsets mat_off = sum n_j^2 and
+// vec_off = sum n_j over the problems before it):
+//   Uwork, Vwork   n x n column-major working left / right singular vectors.
+//                  A node (r0, m, s) owns rows and columns [r0, r0+m) of Uwork
+//                  and [r0, r0+m+s) of Vwork.  Columns are never moved when a
+//                  merge deflates them: the node's sorted order is kept as an
+//                  index (col[]), and each physical column records the row
+//                  range outside which it is zero (ulo/uhi, vlo/vhi), so the
+//                  rows outside are never read or written.
+//   GU, GV         gathered non-deflated columns of a merge (m x N and
+//                  (m+s) x N at the node's diagonal block).  These live in the
+//                  caller's U and VT buffers, which are free until the end.
+//   UM, VM         N x N singular vectors of the deflated M at the node's
+//                  diagonal block of an n x n workspace matrix.
+//   per-position   arrays of length n indexed vec_off + r0 + i for a node.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bdc.h"
+
+namespace bdc {
+
+constexpr int kMaxLeaf = 32;
+// flags of a column touched by a deflation rotation
+constexpr int kRotV = 1;  // its right vector (both deflation rotations)
+constexpr int kRotU = 2;  // its left vector (close-pair rotations only)
+
+struct LeafDesc {
+  int64_t mat_off;
+  int64_t vec_off;
+  int32_t ld;  // problem size n
+  int32_t r0, m, s;
+};
+
+struct NodeDesc {
+  int64_t mat_off;
+  int64_t vec_off;
+  int32_t ld;
+  int32_t r0, m, s, k;
+  int32_t id;  // index into the node-state array
+};
+
+// Written on the device by the deflation kernel of a merge.
+struct NodeState {
+  int32_t N;         // non-deflated size (secular roots)
+  int32_t n1, n2, n3;  // kept columns supported on the left child, both, right child
+  int32_t nrot;      // deflation rotations
+  int32_t nsmall_z, nzero_d, nclose;
+  double scale;      // power of two the merge was scaled by
+  double tol;        // deflation tolerance (scaled units)
+  double c0, s0;     // rotation combining the children's null vectors
+  double rho;        // sum of the kept z_j^2
+};
+
+// Per-call device counters.
+struct Ctl {
+  int32_t nonfinite;
+  int32_t leaf_capped;
+  int32_t secular_capped;
+  int32_t pad;
+  unsigned long long secular_evals;
+  unsigned long long secular_terms;
+  unsigned long long leaf_rot_flops;
+};
+
+// Device pointers of one call (passed to every kernel by value).
+struct Work {
+  const double* d;  // inputs, packed per problem at vec_off
+  const double* e;
+  double* Uw;  // working vectors, packed per problem at mat_off
+  double* Vw;
+  double* GU;  // gathered kept columns (caller's U buffer)
+  double* GV;  // (caller's VT buffer)
+  double* UM;
+  double* VM;
+  // per node-position arrays (packed at vec_off)
+  double* sig;       // values of the node's sorted positions (unscaled)
+  int32_t* col;      // physical column of each sorted position
+  int32_t* ulo;      // row support of each physical column of Uwork: [ulo, uhi)
+  int32_t* uhi;
+  int32_t* vlo;      // and of Vwork
+  int32_t* vhi;
+  double* ps_d;      // merge scratch at sorted positions: value (scaled)
+  double* ps_z;      //   z
+  int32_t* ps_c;     //   node column (the children's sorted positions)
+  int32_t* ps_col;   //   physical column
+  int32_t* ps_sup;   //   1 left child, 2 both, 3 right child, 0 the new d = 0
+  int32_t* status;   //   deflation status
+  int32_t* ps_rot;   //   which side a deflation rotation touched (kRotU | kRotV)
+  int32_t* cand;     // positions that pass the small-z test
+  double* sd;        // kept values (scaled), ascending
+  double* sz;        // kept z
+  int32_t* scol;     // physical column of kept value i
+  int32_t* srot;     // rotation flags of kept value i
+  int32_t* sgrp;     // position of kept value i in the update order
+  int32_t* gsurv;    // kept value at update position g
+  double* dval;      // deflated values (scaled), ascending
+  int32_t* dcol;     // their physical columns
+  int32_t* drot;     // their rotation flags
+  int32_t* o;        // secular roots: origin pole
+  double* tau;       //   offset from it
+  int32_t* iters;    //   evaluations
+  double* zt;        // recomputed z
+  int32_t* rot_pos;  // rotations: sorted positions (2 per rotation)
+  int32_t* rot_col;  //   physical columns (2 per rotation)
+  double* rot_cs;    //   (c, s)
+  NodeState* st;
+  Ctl* ctl;
+  int max_secular_iters;
+  int max_leaf_sweeps;
+};
+
+// ---- launchers (defined next to their kernels) ----
+void launch_reset(Ctl* ctl, hipStream_t st);
+void launch_leaf(const LeafDesc* leaves, int nleaves, const Work& w, hipStream_t st);
+void launch_prep(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
+void launch_rotate(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
+void launch_gather(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
+void launch_secular(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
+void launch_lowner(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
+void launch_vectors(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
+void launch_order(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
+void launch_update(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
+void launch_final(const int64_t* prob_n, const int64_t* prob_vec, const int64_t* prob_mat,
+                  const int64_t* col_off, const int64_t* tile_off, int nprob, int64_t total_cols,
+                  int64_t total_tiles, const Work& w, double* sigma, double* U, double* VT,
+                  hipStream_t st);
+// device and iteration options of a handle (BDC_OK or BDC_ERR_INVALID_HANDLE)
+int handle_info(bdc_handle_t h, int* device, int* max_secular_iters, int* max_leaf_sweeps);
+
+void launch_gemm_plain(int M, int N, int K, const double* A, int lda, const double* B, int ldb,
+                       double* C, int ldc, hipStream_t st);
+
+}  // namespace bdc

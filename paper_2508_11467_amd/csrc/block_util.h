@@ -1,0 +1,67 @@
+// Workgroup-level reductions and scans for 256-thread blocks (4 wave64s).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace bdc {
+
+constexpr int kBlock = 256;
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ inline double wave_maxd(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ inline double wave_prod(double v) {
+  for (int off = 32; off > 0; off >>= 1) v *= __shfl_xor(v, off, 64);
+  return v;
+}
+
+// All threads of the 256-thread block get the block maximum.
+__device__ inline double block_max(double v, double* sh /* >= 4 */) {
+  v = wave_maxd(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+__device__ inline double block_sum(double v, double* sh /* >= 4 */) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// Exclusive prefix sum over the block of K counters per thread.  sh must hold
+// 256*K ints.  total[] receives the block totals.
+template <int K>
+__device__ inline void block_exscan(int (&v)[K], int (&total)[K], int* sh) {
+  const int t = threadIdx.x;
+  __syncthreads();
+  for (int q = 0; q < K; ++q) sh[q * kBlock + t] = v[q];
+  __syncthreads();
+  // Hillis-Steele inclusive scan per counter
+  for (int off = 1; off < kBlock; off <<= 1) {
+    int add[K];
+    for (int q = 0; q < K; ++q) add[q] = t >= off ? sh[q * kBlock + t - off] : 0;
+    __syncthreads();
+    for (int q = 0; q < K; ++q) sh[q * kBlock + t] += add[q];
+    __syncthreads();
+  }
+  for (int q = 0; q < K; ++q) {
+    total[q] = sh[q * kBlock + kBlock - 1];
+    v[q] = sh[q * kBlock + t] - v[q];
+  }
+  __syncthreads();
+}
+
+}  // namespace bdc

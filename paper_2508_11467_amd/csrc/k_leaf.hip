@@ -1,0 +1,275 @@
+// Leaf solves of the divide-and-conquer tree (Algorithm 2 step (1): the
+// bottom subproblems by QR iteration).
+//
+// One 64-lane wavefront per leaf of m <= 32 rows and m+s columns.  The
+// bidiagonal lives in LDS; every lane computes the same scalar Givens
+// sequence (implicit-shift Golub-Kahan sweeps with a Wilkinson shift, zero
+// diagonal chasing), and lane r applies each rotation to row r of the
+// accumulated W (m x m) and Q ((m+s) x (m+s)), stored column-major in LDS so
+// the 64 lanes touch consecutive words.  The leaf is first scaled by a power
+// of two so no square can overflow; the values are scaled back on output.
+// Output columns are written sorted by value (ascending); each physical
+// column records the leaf's row range as its support.
+#include "bdc_internal.h"
+
+namespace bdc {
+namespace {
+
+constexpr double kEps = 0x1p-52;
+constexpr int kLd = kMaxLeaf + 1;  // LDS column stride (doubles)
+
+__device__ inline void givens(double f, double g, double& c, double& s, double& r) {
+  if (g == 0.0) {
+    c = f >= 0.0 ? 1.0 : -1.0;
+    s = 0.0;
+    r = fabs(f);
+    return;
+  }
+  r = hypot(f, g);
+  c = f / r;
+  s = g / r;
+}
+
+// columns (i, j) of an LDS matrix <- (c a_i + s a_j, -s a_i + c a_j), row = lane
+__device__ inline void rot_cols(double* A, int rows, int i, int j, double c, double s, int lane) {
+  if (lane < rows) {
+    const double ai = A[lane + i * kLd];
+    const double aj = A[lane + j * kLd];
+    A[lane + i * kLd] = c * ai + s * aj;
+    A[lane + j * kLd] = -s * ai + c * aj;
+  }
+}
+
+__device__ inline double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__global__ __launch_bounds__(64) void k_leaf(const LeafDesc* __restrict__ leaves, Work w) {
+  unsigned long long nrot_w = 0, nrot_q = 0;  // rotations applied to W and to Q
+  __shared__ double W[kMaxLeaf * kLd];
+  __shared__ double Q[(kMaxLeaf + 1) * kLd];
+  __shared__ double dd[kMaxLeaf + 1];
+  __shared__ double ee[kMaxLeaf + 1];
+
+  const LeafDesc L = leaves[blockIdx.x];
+  const int m = L.m, s = L.s, ms = m + s, r0 = L.r0;
+  const int lane = threadIdx.x;
+  const int64_t ld = L.ld;
+  const int64_t pv = L.vec_off;
+
+  for (int i = lane; i < kMaxLeaf * kLd; i += 64) W[i] = 0.0;
+  for (int i = lane; i < (kMaxLeaf + 1) * kLd; i += 64) Q[i] = 0.0;
+  if (lane < m) W[lane + lane * kLd] = 1.0;
+  if (lane < ms) Q[lane + lane * kLd] = 1.0;
+
+  // load and scale by a power of two
+  double dv = 0.0, ev = 0.0;
+  if (lane < m) dv = w.d[pv + r0 + lane];
+  if (lane < m - 1 + s) ev = w.e[pv + r0 + lane];
+  // every entry of d and e belongs to exactly one leaf or one merge's middle
+  // row, so leaves and merges between them check all of the input
+  const bool bad = !(fabs(dv) <= 1.79769313486231570e308) || !(fabs(ev) <= 1.79769313486231570e308);
+  if (__any(bad) && lane == 0) atomicOr(&w.ctl->nonfinite, 1);
+  double amax = wave_max(fmax(fabs(dv), fabs(ev)));
+  double p = 1.0;
+  if (amax > 0.0 && amax <= 1.79e308) {
+    int ex;
+    frexp(amax, &ex);
+    p = ldexp(1.0, ex);
+  }
+  if (lane <= kMaxLeaf) {
+    dd[lane] = lane < m ? dv / p : 0.0;
+    ee[lane] = lane < m - 1 + s ? ev / p : 0.0;
+  }
+  __syncthreads();
+  const double tiny = kEps * (amax / p);
+
+  // s = 1: remove the extra column's entry, bottom row first.  The right
+  // rotation of columns (j, m) zeroes B[j, m] and moves a fill-in to B[j-1, m].
+  if (s == 1) {
+    double f = ee[m - 1];
+    ee[m - 1] = 0.0;
+    for (int j = m - 1; j >= 0; --j) {
+      double c, sn, r;
+      givens(dd[j], f, c, sn, r);
+      dd[j] = r;
+      if (j > 0) {
+        const double t = ee[j - 1];
+        ee[j - 1] = c * t;
+        f = -sn * t;
+      }
+      rot_cols(Q, ms, j, m, c, sn, lane);
+      ++nrot_q;
+    }
+  }
+
+  const int max_steps = w.max_leaf_sweeps * (m > 0 ? m : 1) + 4 * m;
+  int steps = 0;
+  int hi = m - 1;
+  while (hi > 0) {
+    for (int i = 0; i < hi; ++i)
+      if (fabs(ee[i]) <= kEps * (fabs(dd[i]) + fabs(dd[i + 1]))) ee[i] = 0.0;
+    if (ee[hi - 1] == 0.0) {
+      --hi;
+      continue;
+    }
+    if (steps >= max_steps) {
+      if (lane == 0) atomicAdd(&w.ctl->leaf_capped, 1);
+      break;
+    }
+    ++steps;
+    int lo = hi - 1;
+    while (lo > 0 && ee[lo - 1] != 0.0) --lo;
+    int zero_at = -1;
+    for (int i = lo; i <= hi; ++i)
+      if (fabs(dd[i]) <= tiny) {
+        zero_at = i;
+        break;
+      }
+    if (zero_at >= 0) {
+      const int i = zero_at;
+      dd[i] = 0.0;
+      if (i < hi) {
+        // chase B[i, i+1] along row i with left rotations of rows (j, i)
+        double f = ee[i];
+        ee[i] = 0.0;
+        for (int j = i + 1; j <= hi; ++j) {
+          double c, sn, r;
+          givens(dd[j], f, c, sn, r);
+          dd[j] = r;
+          if (j < hi) {
+            const double t = ee[j];
+            f = -sn * t;
+            ee[j] = c * t;
+          }
+          rot_cols(W, m, j, i, c, sn, lane);
+          ++nrot_w;
+        }
+      } else {
+        // chase B[hi-1, hi] up column hi with right rotations of columns (j, hi)
+        double f = ee[hi - 1];
+        ee[hi - 1] = 0.0;
+        for (int j = hi - 1; j >= lo; --j) {
+          double c, sn, r;
+          givens(dd[j], f, c, sn, r);
+          dd[j] = r;
+          if (j > lo) {
+            const double t = ee[j - 1];
+            f = -sn * t;
+            ee[j - 1] = c * t;
+          }
+          rot_cols(Q, ms, j, hi, c, sn, lane);
+          ++nrot_q;
+        }
+      }
+      continue;
+    }
+    // Wilkinson shift: eigenvalue of the trailing 2x2 of B^T B nearer its end
+    double mu;
+    {
+      const double dm = dd[hi - 1], dn = dd[hi], fm = ee[hi - 1];
+      const double g = (hi - 1 > lo) ? ee[hi - 2] : 0.0;
+      const double t11 = dm * dm + g * g, t12 = dm * fm, t22 = dn * dn + fm * fm;
+      if (t12 == 0.0) {
+        mu = t22;
+      } else {
+        const double delta = 0.5 * (t11 - t22);
+        const double root = hypot(delta, t12);
+        const double denom = delta + (delta >= 0.0 ? root : -root);
+        mu = t22 - t12 * t12 / denom;
+      }
+    }
+    // one implicit-shift sweep, bulge chased from lo to hi
+    double y = dd[lo] * dd[lo] - mu;
+    double z = dd[lo] * ee[lo];
+    double bulge = 0.0;
+    for (int k = lo; k < hi; ++k) {
+      if (k > lo) {
+        y = ee[k - 1];
+        z = bulge;
+      }
+      double c, sn, r;
+      givens(y, z, c, sn, r);
+      if (k > lo) ee[k - 1] = r;
+      const double dk = dd[k], ek = ee[k], dk1 = dd[k + 1];
+      const double ndk = c * dk + sn * ek;
+      const double nek = -sn * dk + c * ek;
+      bulge = sn * dk1;
+      const double ndk1 = c * dk1;
+      rot_cols(Q, ms, k, k + 1, c, sn, lane);
+      ++nrot_q;
+      givens(ndk, bulge, c, sn, r);
+      dd[k] = r;
+      ee[k] = c * nek + sn * ndk1;
+      dd[k + 1] = -sn * nek + c * ndk1;
+      if (k < hi - 1) {
+        const double t = ee[k + 1];
+        bulge = sn * t;
+        ee[k + 1] = c * t;
+      }
+      rot_cols(W, m, k, k + 1, c, sn, lane);
+      ++nrot_w;
+    }
+  }
+
+  // signs, ranks (ascending, ties by index) and output
+  __syncthreads();
+  double sv = 0.0;
+  int rank = 0;
+  if (lane < m) {
+    const double di = dd[lane];
+    sv = fabs(di);
+    if (di < 0.0)
+      for (int r = 0; r < m; ++r) W[r + lane * kLd] = -W[r + lane * kLd];
+    for (int j = 0; j < m; ++j) {
+      const double sj = fabs(dd[j]);
+      rank += (sj < sv || (sj == sv && j < lane)) ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  double* Uw = w.Uw + L.mat_off;
+  double* Vw = w.Vw + L.mat_off;
+  for (int c = 0; c < m; ++c) {
+    const int rc = __shfl(rank, c, 64);
+    const int64_t pc = r0 + rc;
+    if (lane < m) Uw[(r0 + lane) + pc * ld] = W[lane + c * kLd];
+    if (lane < ms) Vw[(r0 + lane) + pc * ld] = Q[lane + c * kLd];
+  }
+  if (s == 1 && lane < ms) Vw[(r0 + lane) + (int64_t)(r0 + m) * ld] = Q[lane + m * kLd];
+  if (lane < m) {
+    w.sig[pv + r0 + rank] = sv * p;
+    w.col[pv + r0 + lane] = r0 + lane;
+    w.ulo[pv + r0 + lane] = r0;
+    w.uhi[pv + r0 + lane] = r0 + m;
+    w.vlo[pv + r0 + lane] = r0;
+    w.vhi[pv + r0 + lane] = r0 + ms;
+  }
+  if (s == 1 && lane == 0) {
+    w.vlo[pv + r0 + m] = r0;
+    w.vhi[pv + r0 + m] = r0 + ms;
+  }
+  // 6 flops per row per rotation
+  if (lane == 0) atomicAdd(&w.ctl->leaf_rot_flops, 6ull * (nrot_w * (unsigned long long)m + nrot_q * (unsigned long long)ms));
+}
+
+__global__ void k_reset(Ctl* ctl) {
+  ctl->nonfinite = 0;
+  ctl->leaf_capped = 0;
+  ctl->secular_capped = 0;
+  ctl->pad = 0;
+  ctl->secular_evals = 0ull;
+  ctl->secular_terms = 0ull;
+  ctl->leaf_rot_flops = 0ull;
+}
+
+}  // namespace
+
+void launch_reset(Ctl* ctl, hipStream_t st) { hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, ctl); }
+
+void launch_leaf(const LeafDesc* leaves, int nleaves, const Work& w, hipStream_t st) {
+  if (nleaves <= 0) return;
+  hipLaunchKernelGGL(k_leaf, dim3(nleaves), dim3(64), 0, st, leaves, w);
+}
+
+}  // namespace bdc

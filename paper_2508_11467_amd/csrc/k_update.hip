@@ -1,0 +1,423 @@
+// Vector side of a merge and the final output.
+//   k_rotate   applies the deflation rotations (Algorithm 3's rotation step)
+//              row-parallel: one thread per row of the node applies the whole
+//              list in order.  Columns touched are first zero-filled outside
+//              their support so the rotated columns are dense over the node.
+//   k_gather   copies the kept columns, in update order [left-only | d = 0 |
+//              mixed | right-only], into the compact GU / GV blocks.  Deflated
+//              columns are not moved at all.
+//   k_order    merges the roots with the deflated values (Algorithm 2 step
+//              (3)'s sort, done per node), records each sorted position's
+//              physical column and updates the supports.
+//   k_update   the vector update of eq. bdc-Mv2Bv-u-vt as FP64 matrix-core
+//              GEMMs.  With the update order above, the rows of the left
+//              child's block need only the columns [left-only | d=0 | mixed]
+//              and the right child's rows only [d=0 | mixed | right-only]: two
+//              contiguous products per side instead of the paper's three.
+//              Results are written straight into the kept columns' physical
+//              places, scaled to unit length already.
+//   k_final_u / k_final_vt  write sigma, U and V^T in descending order
+//              (the root's ascending order reversed), expanding each column's
+//              support to the full matrix; V^T goes through an LDS transpose.
+#include "bdc_internal.h"
+#include "block_util.h"
+
+namespace bdc {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+inline int grid_y(int nnodes, int units, int cap_total) {
+  int gy = units;
+  int cap = cap_total / (nnodes > 0 ? nnodes : 1);
+  if (cap < 1) cap = 1;
+  if (gy > cap) gy = cap;
+  if (gy < 1) gy = 1;
+  if (gy > 65535) gy = 65535;
+  return gy;
+}
+
+// ------------------------------------------------------------------ rotate
+__global__ __launch_bounds__(256) void k_rotate(const NodeDesc* __restrict__ nodes, Work w) {
+  const NodeDesc nd = nodes[blockIdx.x];
+  const int nrot = w.st[nd.id].nrot;
+  if (nrot == 0) return;
+  const int m = nd.m, s = nd.s, r0 = nd.r0;
+  const int64_t ld = nd.ld, pv = nd.vec_off;
+  const int64_t rb = 2 * (nd.vec_off + nd.r0);
+  double* U = w.Uw + nd.mat_off;
+  double* V = w.Vw + nd.mat_off;
+  for (int row = blockIdx.y * kBlock + threadIdx.x; row < m + s; row += gridDim.y * kBlock) {
+    const int gr = r0 + row;
+    const bool inU = row < m;
+    // zero-fill the touched columns outside their current support
+    for (int q = 0; q < nrot; ++q) {
+      const bool both = w.rot_pos[rb + 2 * q] != 0;
+      for (int h = 0; h < 2; ++h) {
+        const int pc = w.rot_col[rb + 2 * q + h];
+        if (both && inU && (gr < w.ulo[pv + pc] || gr >= w.uhi[pv + pc])) U[gr + pc * ld] = 0.0;
+        if (gr < w.vlo[pv + pc] || gr >= w.vhi[pv + pc]) V[gr + pc * ld] = 0.0;
+      }
+    }
+    for (int q = 0; q < nrot; ++q) {
+      const bool both = w.rot_pos[rb + 2 * q] != 0;
+      const int pp = w.rot_col[rb + 2 * q], pj = w.rot_col[rb + 2 * q + 1];
+      const double c = w.rot_cs[rb + 2 * q], sn = w.rot_cs[rb + 2 * q + 1];
+      if (both && inU) {
+        const double a = U[gr + pp * ld], b = U[gr + pj * ld];
+        U[gr + pp * ld] = c * a + sn * b;
+        U[gr + pj * ld] = -sn * a + c * b;
+      }
+      const double a = V[gr + pp * ld], b = V[gr + pj * ld];
+      V[gr + pp * ld] = c * a + sn * b;
+      V[gr + pj * ld] = -sn * a + c * b;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ gather
+__global__ __launch_bounds__(256) void k_gather(const NodeDesc* __restrict__ nodes, Work w) {
+  const NodeDesc nd = nodes[blockIdx.x];
+  const int N = w.st[nd.id].N;
+  const int m = nd.m, s = nd.s, r0 = nd.r0, k = nd.k;
+  const int64_t ld = nd.ld, pv = nd.vec_off, vo = nd.vec_off + nd.r0;
+  const double* U = w.Uw + nd.mat_off;
+  const double* V = w.Vw + nd.mat_off;
+  double* GU = w.GU + nd.mat_off;
+  double* GV = w.GV + nd.mat_off;
+  for (int g = blockIdx.y; g < N; g += gridDim.y) {
+    const int i = w.gsurv[vo + g];
+    double* gu = GU + r0 + (int64_t)(r0 + g) * ld;
+    double* gv = GV + r0 + (int64_t)(r0 + g) * ld;
+    if (i == 0) {
+      // d = 0 position: left vector e_{k-1} (the middle row), right vector x1
+      const int64_t pc = r0 + k - 1;
+      for (int row = threadIdx.x; row < m; row += kBlock) gu[row] = (row == k - 1) ? 1.0 : 0.0;
+      for (int row = threadIdx.x; row < m + s; row += kBlock) gv[row] = V[(r0 + row) + pc * ld];
+    } else {
+      const int64_t pc = w.scol[vo + i];
+      const int rf = w.srot[vo + i];
+      const bool fu = (rf & kRotU) != 0, fv = (rf & kRotV) != 0;
+      const int ul = fu ? r0 : w.ulo[pv + pc], uh = fu ? r0 + m : w.uhi[pv + pc];
+      const int vl = fv ? r0 : w.vlo[pv + pc], vh = fv ? r0 + m + s : w.vhi[pv + pc];
+      for (int row = threadIdx.x; row < m; row += kBlock) {
+        const int gr = r0 + row;
+        gu[row] = (gr >= ul && gr < uh) ? U[gr + pc * ld] : 0.0;
+      }
+      for (int row = threadIdx.x; row < m + s; row += kBlock) {
+        const int gr = r0 + row;
+        gv[row] = (gr >= vl && gr < vh) ? V[gr + pc * ld] : 0.0;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ order
+__device__ inline double root_value(const double* d, const int* o, const double* tau, int i) {
+  return d[o[i]] + tau[i];
+}
+
+__global__ __launch_bounds__(256) void k_order(const NodeDesc* __restrict__ nodes, Work w) {
+  const NodeDesc nd = nodes[blockIdx.x];
+  const NodeState st = w.st[nd.id];
+  const int N = st.N, m = nd.m, s = nd.s, r0 = nd.r0, D = nd.m - st.N;
+  const int64_t pv = nd.vec_off, vo = nd.vec_off + nd.r0;
+  const double* d = w.sd + vo;
+  const int* o = w.o + vo;
+  const double* tau = w.tau + vo;
+  const double* dv = w.dval + vo;
+  const double p = st.scale;
+  for (int idx = blockIdx.y * kBlock + threadIdx.x; idx < m; idx += gridDim.y * kBlock) {
+    if (idx < N) {
+      const int i = idx;
+      const double wi = root_value(d, o, tau, i);
+      int lo = 0, hi = D;  // deflated values strictly below w_i
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (dv[mid] < wi) lo = mid + 1;
+        else hi = mid;
+      }
+      const int dest = i + lo;
+      const int pc = w.scol[vo + i];
+      w.sig[vo + dest] = wi * p;
+      w.col[vo + dest] = pc;
+      w.ulo[pv + pc] = r0;
+      w.uhi[pv + pc] = r0 + m;
+      w.vlo[pv + pc] = r0;
+      w.vhi[pv + pc] = r0 + m + s;
+    } else {
+      const int q = idx - N;
+      const double v = dv[q];
+      int lo = 0, hi = N;  // roots at or below v (roots first on ties)
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (root_value(d, o, tau, mid) <= v) lo = mid + 1;
+        else hi = mid;
+      }
+      const int dest = q + lo;
+      const int pc = w.dcol[vo + q];
+      w.sig[vo + dest] = v * p;
+      w.col[vo + dest] = pc;
+      const int rf = w.drot[vo + q];
+      if (rf & kRotU) {  // rotated columns were made dense over the node
+        w.ulo[pv + pc] = r0;
+        w.uhi[pv + pc] = r0 + m;
+      }
+      if (rf & kRotV) {
+        w.vlo[pv + pc] = r0;
+        w.vhi[pv + pc] = r0 + m + s;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ GEMM
+// 64 x 64 output tile per 256-thread workgroup; each wavefront owns a 32 x 32
+// quarter as 2 x 2 blocks of v_mfma_f64_16x16x4f64.  A (M x K) and B (K x N)
+// are column-major; 16-deep K slabs are staged in LDS.
+constexpr int TM = 64, TN = 64, TK = 16;
+
+struct TileSmem {
+  double A[TK * TM];
+  double B[TK * TN];
+};
+
+template <class Store>
+__device__ inline void gemm_tile(TileSmem& sm, const double* __restrict__ A, int64_t lda,
+                                 const double* __restrict__ B, int64_t ldb, int M, int N, int K,
+                                 int tm0, int tn0, Store store) {
+  const int t = threadIdx.x, wv = t >> 6, l = t & 63;
+  const int wm = wv & 1, wn = wv >> 1;
+  const int li = l & 15, lk = l >> 4;
+  v4d acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += TK) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + kBlock * q;
+      const int r = e & (TM - 1), kk = e >> 6;
+      const int gr = tm0 + r, gk = k0 + kk;
+      sm.A[kk * TM + r] = (gr < M && gk < K) ? A[gr + (int64_t)gk * lda] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + kBlock * q;
+      const int kk = e & (TK - 1), c = e >> 4;
+      const int gk = k0 + kk, gc = tn0 + c;
+      sm.B[kk * TN + c] = (gk < K && gc < N) ? B[gk + (int64_t)gc * ldb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      double af[2], bf[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) af[a] = sm.A[(kk + lk) * TM + wm * 32 + a * 16 + li];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bf[b] = sm.B[(kk + lk) * TN + wn * 32 + b * 16 + li];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+  }
+  // D[i][j] of a 16x16 block sits in lane j + 16 * (i % 4), register i / 4
+  // (checked against a host product)
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = tm0 + wm * 32 + a * 16 + lk + 4 * r;
+        const int colc = tn0 + wn * 32 + b * 16 + li;
+        if (row < M && colc < N) store(row, colc, acc[a][b][r]);
+      }
+}
+
+struct NodeStore {
+  double* C;
+  const int* scol;
+  int64_t ld;
+  int rowbase;
+  __device__ void operator()(int row, int c, double v) const {
+    C[(rowbase + row) + (int64_t)scol[c] * ld] = v;
+  }
+};
+
+// grid: (node, tile slot, side-half).  side-half: 0 U rows [0,k), 1 U rows
+// [k,m), 2 V rows [0,k), 3 V rows [k,m+s).
+__global__ __launch_bounds__(256) void k_update(const NodeDesc* __restrict__ nodes, Work w) {
+  __shared__ TileSmem sm;
+  const NodeDesc nd = nodes[blockIdx.x];
+  const NodeState st = w.st[nd.id];
+  const int N = st.N, n1 = st.n1, n2 = st.n2;
+  const int m = nd.m, s = nd.s, k = nd.k, r0 = nd.r0;
+  const int64_t ld = nd.ld, vo = nd.vec_off + nd.r0;
+  const int sub = blockIdx.z;
+  const bool isV = sub >= 2, bottom = sub & 1;
+  const int rows = bottom ? (isV ? m + s - k : m - k) : k;
+  const int kb = bottom ? n1 : 0;
+  const int ke = bottom ? N : n1 + 1 + n2;
+  const int K = ke - kb;
+  const int rowoff = bottom ? k : 0;
+  const double* G = (isV ? w.GV : w.GU) + nd.mat_off;
+  const double* Mv = (isV ? w.VM : w.UM) + nd.mat_off;
+  const double* A = G + (r0 + rowoff) + (int64_t)(r0 + kb) * ld;
+  const double* B = Mv + (r0 + kb) + (int64_t)r0 * ld;
+  NodeStore store{(isV ? w.Vw : w.Uw) + nd.mat_off, w.scol + vo, ld, r0 + rowoff};
+  const int tiles_m = (rows + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
+  const int ntiles = tiles_m * tiles_n;
+  for (int tile = blockIdx.y; tile < ntiles; tile += gridDim.y) {
+    const int tm = tile % tiles_m, tn = tile / tiles_m;
+    gemm_tile(sm, A, ld, B, ld, rows, N, K, tm * TM, tn * TN, store);
+  }
+}
+
+struct PlainStore {
+  double* C;
+  int64_t ldc;
+  __device__ void operator()(int row, int c, double v) const { C[row + (int64_t)c * ldc] = v; }
+};
+
+__global__ __launch_bounds__(256) void k_gemm_plain(int M, int N, int K, const double* A, int lda,
+                                                     const double* B, int ldb, double* C, int ldc) {
+  __shared__ TileSmem sm;
+  const int tiles_m = (M + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
+  for (int tile = blockIdx.x; tile < tiles_m * tiles_n; tile += gridDim.x) {
+    const int tm = tile % tiles_m, tn = tile / tiles_m;
+    gemm_tile(sm, A, lda, B, ldb, M, N, K, tm * TM, tn * TN, PlainStore{C, ldc});
+  }
+}
+
+// ------------------------------------------------------------------ final
+// U: one workgroup per output column t (descending order), rows in parallel.
+__global__ __launch_bounds__(256) void k_final_u(const int64_t* __restrict__ pn,
+                                                 const int64_t* __restrict__ pvec,
+                                                 const int64_t* __restrict__ pmat,
+                                                 const int64_t* __restrict__ col_off, int nprob,
+                                                 Work w, double* sigma, double* U) {
+  // find the problem owning global column blockIdx.x
+  const int64_t gcol = blockIdx.x;
+  int lo = 0, hi = nprob;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (col_off[mid] <= gcol) lo = mid;
+    else hi = mid;
+  }
+  const int64_t n = pn[lo], pv = pvec[lo], mo = pmat[lo];
+  const int64_t tcol = gcol - col_off[lo];
+  if (tcol >= n) return;
+  const int64_t src = n - 1 - tcol;
+  const int64_t pc = w.col[pv + src];
+  const int ul = w.ulo[pv + pc], uh = w.uhi[pv + pc];
+  if (threadIdx.x == 0) sigma[pv + tcol] = w.sig[pv + src];
+  const double* in = w.Uw + mo + pc * n;
+  double* out = U + mo + tcol * n;
+  for (int64_t r = threadIdx.x; r < n; r += kBlock) out[r] = (r >= ul && r < uh) ? in[r] : 0.0;
+}
+
+// V^T: 64 x 64 tiles; reads columns of Vwork (coalesced), writes rows of V^T
+// as columns of the column-major output (coalesced) through LDS.
+__global__ __launch_bounds__(256) void k_final_vt(const int64_t* __restrict__ pn,
+                                                  const int64_t* __restrict__ pvec,
+                                                  const int64_t* __restrict__ pmat,
+                                                  const int64_t* __restrict__ tile_off, int nprob,
+                                                  Work w, double* VT) {
+  __shared__ double tileS[64][65];
+  __shared__ int64_t pcs[64];
+  __shared__ int lov[64], hiv[64];
+  const int64_t gt = blockIdx.x;
+  int lo = 0, hi = nprob;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (tile_off[mid] <= gt) lo = mid;
+    else hi = mid;
+  }
+  const int64_t n = pn[lo], pv = pvec[lo], mo = pmat[lo];
+  const int64_t nt = (n + 63) / 64;
+  const int64_t tl = gt - tile_off[lo];
+  if (tl >= nt * nt) return;
+  const int64_t t0 = (tl % nt) * 64;  // output rows of V^T (singular vector index)
+  const int64_t j0 = (tl / nt) * 64;  // output columns of V^T (coordinate index)
+  const int t = threadIdx.x;
+  if (t < 64) {
+    const int64_t tv = t0 + t;
+    if (tv < n) {
+      const int64_t pc = w.col[pv + (n - 1 - tv)];
+      pcs[t] = pc;
+      lov[t] = w.vlo[pv + pc];
+      hiv[t] = w.vhi[pv + pc];
+    } else {
+      pcs[t] = -1;
+    }
+  }
+  __syncthreads();
+  const double* Vw = w.Vw + mo;
+  // load: element (j, tv) = V[j0 + jj, pc(tv)]
+  for (int e = t; e < 64 * 64; e += kBlock) {
+    const int jj = e & 63, tt = e >> 6;
+    const int64_t j = j0 + jj;
+    double v = 0.0;
+    const int64_t pc = pcs[tt];
+    if (pc >= 0 && j < n && j >= lov[tt] && j < hiv[tt]) v = Vw[j + pc * n];
+    tileS[tt][jj] = v;
+  }
+  __syncthreads();
+  double* out = VT + mo;
+  for (int e = t; e < 64 * 64; e += kBlock) {
+    const int tt = e & 63, jj = e >> 6;
+    const int64_t tv = t0 + tt, j = j0 + jj;
+    if (tv < n && j < n) out[tv + j * n] = tileS[tt][jj];
+  }
+}
+
+}  // namespace
+
+void launch_rotate(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {
+  if (nnodes <= 0) return;
+  const int gy = grid_y(nnodes, (max_m + 1 + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL(k_rotate, dim3(nnodes, gy), dim3(kBlock), 0, st, nodes, w);
+}
+
+void launch_gather(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {
+  if (nnodes <= 0) return;
+  const int gy = grid_y(nnodes, max_m, 4096);
+  hipLaunchKernelGGL(k_gather, dim3(nnodes, gy), dim3(kBlock), 0, st, nodes, w);
+}
+
+void launch_order(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {
+  if (nnodes <= 0) return;
+  const int gy = grid_y(nnodes, (max_m + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL(k_order, dim3(nnodes, gy), dim3(kBlock), 0, st, nodes, w);
+}
+
+void launch_update(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {
+  if (nnodes <= 0) return;
+  const int tiles = ((max_m + 1 + TM - 1) / TM) * ((max_m + TN - 1) / TN);
+  const int gy = grid_y(nnodes, tiles, 2048);
+  hipLaunchKernelGGL(k_update, dim3(nnodes, gy, 4), dim3(kBlock), 0, st, nodes, w);
+}
+
+void launch_gemm_plain(int M, int N, int K, const double* A, int lda, const double* B, int ldb,
+                       double* C, int ldc, hipStream_t st) {
+  if (M <= 0 || N <= 0) return;
+  int tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
+  if (tiles > 4096) tiles = 4096;
+  hipLaunchKernelGGL(k_gemm_plain, dim3(tiles), dim3(kBlock), 0, st, M, N, K, A, lda, B, ldb, C, ldc);
+}
+
+void launch_final(const int64_t* prob_n, const int64_t* prob_vec, const int64_t* prob_mat,
+                  const int64_t* col_off, const int64_t* tile_off, int nprob, int64_t total_cols,
+                  int64_t total_tiles, const Work& w, double* sigma, double* U, double* VT,
+                  hipStream_t st) {
+  if (nprob <= 0 || total_cols <= 0) return;
+  hipLaunchKernelGGL(k_final_u, dim3((unsigned)total_cols), dim3(kBlock), 0, st, prob_n, prob_vec,
+                     prob_mat, col_off, nprob, w, sigma, U);
+  hipLaunchKernelGGL(k_final_vt, dim3((unsigned)total_tiles), dim3(kBlock), 0, st, prob_n,
+                     prob_vec, prob_mat, tile_off, nprob, w, VT);
+}
+
+}  // namespace bdc

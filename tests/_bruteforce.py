@@ -68,3 +68,43 @@ def gk_singular_values(d, e):
     w, _ = jacobi_eigh(golub_kahan(d, e))
     w = np.sort(w)[::-1]
     return w[: len(d)].astype(np.float64)
+
+
+def sturm_count(d, e, x):
+    """Number of singular values of the bidiagonal (d, e) below x >= 0, from
+    the LDL^T inertia of the Golub-Kahan tridiagonal T - x I (T has zero
+    diagonal and off-diagonal d_1, e_1, d_2, ...): eigenvalues of T below x
+    number n + (singular values below x)."""
+    n = len(d)
+    off = np.empty(2 * n - 1)
+    off[0::2] = d
+    off[1::2] = np.asarray(e)[: n - 1]
+    neg = 0
+    q = -x
+    tiny = 1e-300
+    if q < 0:
+        neg += 1
+    for b in off:
+        if q == 0.0:
+            q = -tiny
+        q = -x - (b * b) / q
+        if q < 0:
+            neg += 1
+    return neg - n
+
+
+def singular_value_by_bisection(d, e, i, iters=100):
+    """The i-th largest singular value (0-based) by bisection on sturm_count."""
+    n = len(d)
+    hi = float(np.max(np.abs(d)) + np.max(np.abs(np.asarray(e)[: n - 1]), initial=0.0)) * 2.0 + 1e-300
+    lo = 0.0
+    target = n - i  # number of values <= sigma_i from below
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        if mid == lo or mid == hi:
+            break
+        if sturm_count(d, e, mid) >= target:
+            hi = mid
+        else:
+            lo = mid
+    return 0.5 * (lo + hi)
