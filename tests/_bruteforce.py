@@ -80,14 +80,16 @@ def sturm_count(d, e, x):
     off[0::2] = d
     off[1::2] = np.asarray(e)[: n - 1]
     neg = 0
-    q = -x
     tiny = 1e-300
+    q = -x
+    if q == 0.0:
+        q = -tiny  # a zero pivot counts as negative, consistently
     if q < 0:
         neg += 1
     for b in off:
+        q = -x - (b * b) / q
         if q == 0.0:
             q = -tiny
-        q = -x - (b * b) / q
         if q < 0:
             neg += 1
     return neg - n
