@@ -54,7 +54,10 @@ typedef struct {
   int max_secular_iters;      /* evaluations of the secular function per root, 2..64; default 64 */
   int max_leaf_sweeps;        /* QR sweeps per leaf row, 1..1000; default 40 (cap = value * m) */
   size_t workspace_cap_bytes; /* 0 = unlimited */
-  int timing;                 /* 1: record per-kernel event times (bdc_get_timing) */
+  int timing;                 /* 1: record per-kernel event times (bdc_get_timing); launches
+                                 kernels one by one (no graph) */
+  int use_graph;              /* 1 (default): capture a solve's launch sequence once per
+                                 (sizes, buffers) as a HIP graph and replay it */
 } bdc_options_t;
 
 void bdc_default_options(bdc_options_t* opt);

@@ -26,8 +26,9 @@ reading used here (the same one the GPU kernel implements independently):
 * safeguard: the root stays bracketed; a step that leaves the bracket or is
   not finite is replaced by bisection of the bracket;
 * stop when |f| <= 8 eps (1 + sum_j |z_j^2 / (d_j^2 - omega^2)|), or when the
-  step changes tau by no more than 2 eps |tau|, or after 64 evaluations.
-  One "iteration" is one O(N) evaluation of f, the midpoint one included.
+  step changes tau by no more than 2 eps |tau| (that step is accepted without
+  evaluating f again), or after 64 evaluations.  One "iteration" is one O(N)
+  evaluation of f, the midpoint one included.
 
 The summation order is fixed: terms of poles left of the interval are added
 from the first pole upwards, terms right of it from the last pole downwards,
@@ -159,21 +160,26 @@ def _solve_block(d, zsq, rho, idx):
         tau_new = np.where(bad, 0.5 * (lo[a_idx] + hi[a_idx]), tau_new)
         small_step = np.abs(tau_new - tau[a_idx]) <= 2.0 * EPS * np.abs(tau_new)
         tau[a_idx] = tau_new
-        # evaluate at the new point
-        fn, psin, dpsin, phin, dphin, En, deltan = _evaluate(d, zsq, ov[a_idx], tau_new, lp[a_idx])
-        iters[a_idx] += 1
-        f[a_idx] = fn
-        psi[a_idx] = psin
-        dpsi[a_idx] = dpsin
-        phi[a_idx] = phin
-        dphi[a_idx] = dphin
-        E[a_idx] = En
-        delta[a_idx] = deltan
+        # a step at the rounding level is accepted as it is; elsewhere f is
+        # evaluated at the new point
+        done[a_idx[small_step]] = True
+        e_idx = a_idx[~small_step]
+        if e_idx.size == 0:
+            continue
+        fn, psin, dpsin, phin, dphin, En, deltan = _evaluate(d, zsq, ov[e_idx], tau[e_idx], lp[e_idx])
+        iters[e_idx] += 1
+        f[e_idx] = fn
+        psi[e_idx] = psin
+        dpsi[e_idx] = dpsin
+        phi[e_idx] = phin
+        dphi[e_idx] = dphin
+        E[e_idx] = En
+        delta[e_idx] = deltan
         neg = fn < 0.0
-        lo[a_idx] = np.where(neg, tau_new, lo[a_idx])
-        hi[a_idx] = np.where(neg, hi[a_idx], tau_new)
-        conv = (np.abs(fn) <= 8.0 * EPS * En) | small_step | (iters[a_idx] >= MAX_ITERS)
-        done[a_idx] = conv
+        lo[e_idx] = np.where(neg, tau[e_idx], lo[e_idx])
+        hi[e_idx] = np.where(neg, hi[e_idx], tau[e_idx])
+        conv = (np.abs(fn) <= 8.0 * EPS * En) | (iters[e_idx] >= MAX_ITERS)
+        done[e_idx] = conv
     return o, tau, iters
 
 

@@ -30,6 +30,7 @@ class Options(ctypes.Structure):
         ("max_leaf_sweeps", c_int),
         ("workspace_cap_bytes", ctypes.c_size_t),
         ("timing", c_int),
+        ("use_graph", c_int),
     ]
 
 

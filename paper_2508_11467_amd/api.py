@@ -26,7 +26,8 @@ class Solver:
     """One handle of the C ABI (workspace, plan cache) on one GPU."""
 
     def __init__(self, device: int | torch.device = 0, leaf_size: int = 32, max_secular_iters: int = 64,
-                 max_leaf_sweeps: int = 40, workspace_cap_bytes: int = 0, timing: bool = False):
+                 max_leaf_sweeps: int = 40, workspace_cap_bytes: int = 0, timing: bool = False,
+                 use_graph: bool = True):
         self.lib = _lib.load()
         dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         if dev.type != "cuda":
@@ -39,6 +40,7 @@ class Solver:
         opt.max_leaf_sweeps = max_leaf_sweeps
         opt.workspace_cap_bytes = workspace_cap_bytes
         opt.timing = 1 if timing else 0
+        opt.use_graph = 1 if use_graph else 0
         h = ctypes.c_void_p()
         check("bdc_create", self.lib.bdc_create(ctypes.byref(h), self.device.index, ctypes.byref(opt)))
         self.handle = h

@@ -69,6 +69,10 @@ struct bdc_handle_s {
   bool plan_valid = false;
   hipStream_t last_stream = nullptr;
   bool have_call = false;
+  // captured launch sequence of the current plan and buffers
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void* gkey[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   struct Rec {
     int kind;
     hipEvent_t a, b;
@@ -93,6 +97,12 @@ struct DeviceGuard {
 };
 
 bool valid(bdc_handle_t h) { return h != nullptr && h->magic == kMagic; }
+
+void drop_graph(bdc_handle_t h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  h->gexec = nullptr;
+  for (auto& k : h->gkey) k = nullptr;
+}
 
 void free_plan(Plan& p) {
   if (p.block) (void)hipFree(p.block);
@@ -120,6 +130,7 @@ int make_plan(bdc_handle_t h, const int64_t* sizes, int64_t batch) {
       std::equal(h->plan.sizes.begin(), h->plan.sizes.end(), sizes))
     return BDC_OK;
   if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
+  drop_graph(h);
   free_plan(h->plan);
   h->plan_valid = false;
   Plan p;
@@ -211,6 +222,7 @@ int ensure_workspace(bdc_handle_t h, int64_t tn, int64_t tn2, int nnodes) {
   if (h->opt.workspace_cap_bytes && bytes > h->opt.workspace_cap_bytes) return BDC_ERR_NOMEM;
   if (h->arena) {
     if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
+    drop_graph(h);
     (void)hipFree(h->arena);
     h->arena = nullptr;
     h->arena_bytes = 0;
@@ -314,7 +326,7 @@ int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, do
   w.max_leaf_sweeps = h->opt.max_leaf_sweeps;
   {
     Timer t(h, st, kReset);
-    launch_reset(w.ctl, st);
+    launch_reset(w.ctl, w.st, p.nnodes, st);
   }
   {
     Timer t(h, st, kLeaf);
@@ -353,10 +365,39 @@ int solve(bdc_handle_t h, int64_t batch, const int64_t* sizes, const double* d, 
   if (h->plan.total_n == 0) {
     h->last_stream = st;
     h->have_call = true;
-    launch_reset(h->w.ctl, st);
+    launch_reset(h->w.ctl, h->w.st, 0, st);
     return hipGetLastError() == hipSuccess ? BDC_OK : BDC_ERR_HIP;
   }
-  return run_plan(h, d, e, sigma, U, VT, st);
+  if (h->opt.timing || !h->opt.use_graph) return run_plan(h, d, e, sigma, U, VT, st);
+  // replay the captured sequence when the plan and the buffers are the same
+  const void* key[5] = {d, e, sigma, U, VT};
+  bool same = h->gexec != nullptr;
+  for (int i = 0; i < 5 && same; ++i) same = key[i] == h->gkey[i];
+  if (!same) {
+    if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
+    drop_graph(h);
+    if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
+      return BDC_ERR_HIP;
+    if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return BDC_ERR_HIP;
+    const int rc = run_plan(h, d, e, sigma, U, VT, h->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(h->cap_stream, &g);
+    if (rc != BDC_OK || ec != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc != BDC_OK ? rc : BDC_ERR_HIP;
+    }
+    const hipError_t ei = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      h->gexec = nullptr;
+      return BDC_ERR_HIP;
+    }
+    for (int i = 0; i < 5; ++i) h->gkey[i] = key[i];
+  }
+  if (hipGraphLaunch(h->gexec, st) != hipSuccess) return BDC_ERR_HIP;
+  h->last_stream = st;
+  h->have_call = true;
+  return BDC_OK;
 }
 
 }  // namespace
@@ -379,6 +420,7 @@ void bdc_default_options(bdc_options_t* opt) {
   opt->max_leaf_sweeps = 40;
   opt->workspace_cap_bytes = 0;
   opt->timing = 0;
+  opt->use_graph = 1;
 }
 
 int bdc_create(bdc_handle_t* handle, int device, const bdc_options_t* opt) {
@@ -406,6 +448,8 @@ int bdc_destroy(bdc_handle_t h) {
   {
     DeviceGuard g(h->device);
     if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
+    drop_graph(h);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     free_plan(h->plan);
     if (h->arena) (void)hipFree(h->arena);
     for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);

@@ -55,6 +55,7 @@ struct NodeState {
   double tol;        // deflation tolerance (scaled units)
   double c0, s0;     // rotation combining the children's null vectors
   double rho;        // sum of the kept z_j^2
+  unsigned long long zmax_bits;  // max(d, |z|) of the merge, as bits (atomic max)
 };
 
 // Per-call device counters.
@@ -116,7 +117,7 @@ struct Work {
 };
 
 // ---- launchers (defined next to their kernels) ----
-void launch_reset(Ctl* ctl, hipStream_t st);
+void launch_reset(Ctl* ctl, NodeState* st, int nnodes, hipStream_t st_);
 void launch_leaf(const LeafDesc* leaves, int nleaves, const Work& w, hipStream_t st);
 void launch_prep(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
 void launch_rotate(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);

@@ -23,7 +23,6 @@ namespace bdc {
 namespace {
 
 constexpr double kEps = 0x1p-52;
-constexpr int kChunk = 1024;
 
 // number of a[0..n) (ascending) strictly below x
 __device__ inline int count_less(const double* a, int n, double x) {
@@ -47,85 +46,90 @@ __device__ inline int count_leq(const double* a, int n, double x) {
   return lo;
 }
 
-__global__ __launch_bounds__(256) void k_prep(const NodeDesc* __restrict__ nodes, Work w) {
-  __shared__ double shd[8];
-  __shared__ int shi[kBlock * 6];
-  __shared__ int c_pos[kChunk];
-  __shared__ double c_d[kChunk];
-  __shared__ double c_z[kChunk];
-  __shared__ int c_sup[kChunk];
-  __shared__ int sh_cnt[4];
+struct MergeHead {
+  double p, a_s, b_s, rr, c0, s0;
+};
 
-  const NodeDesc nd = nodes[blockIdx.x];
-  const int m = nd.m, k = nd.k, s = nd.s, r0 = nd.r0, m2 = nd.m - nd.k;
+// Scale, z_1 and the rotation (c0, s0) combining the children's null vectors:
+// x1 = c0 [q1; 0] + s0 [0; q2] carries z_1 = rr, y = -s0 [q1; 0] + c0 [0; q2]
+// is the node's own null vector.  The scale is the power of two above the
+// largest of |alpha|, |beta| and the children's largest values (the last of
+// each ascending list).
+__device__ inline MergeHead merge_head(const NodeDesc& nd, const Work& w) {
+  const int k = nd.k, s = nd.s, r0 = nd.r0, m = nd.m;
   const int64_t ld = nd.ld, pv = nd.vec_off, vo = nd.vec_off + nd.r0;
-  double* V = w.Vw + nd.mat_off;
-  const int t = threadIdx.x;
-
+  const double* V = w.Vw + nd.mat_off;
   // the middle row of the split: alpha in the left child's last column,
   // beta in the right child's first column
   const double alpha = w.d[pv + r0 + k - 1];
   const double beta = w.e[pv + r0 + k - 1];
-  if (t == 0 && !(fabs(alpha) <= DBL_MAX && fabs(beta) <= DBL_MAX)) atomicOr(&w.ctl->nonfinite, 1);
-
-  // ---- scale: a power of two bringing every value of the merge below 1
-  double vmax = fmax(fabs(alpha), fabs(beta));
-  for (int c = t; c < m; c += kBlock)
-    if (c != k - 1) vmax = fmax(vmax, fabs(w.sig[vo + c]));
-  vmax = block_max(vmax, shd);
-  double p = 1.0;
+  double vmax = fmax(fmax(fabs(alpha), fabs(beta)), fmax(w.sig[vo + k - 2], w.sig[vo + m - 1]));
+  MergeHead h;
+  h.p = 1.0;
   if (vmax > 0.0 && vmax <= DBL_MAX) {
     int ex;
     frexp(vmax, &ex);
-    p = ldexp(1.0, ex);
+    h.p = ldexp(1.0, ex);
   }
-  const double a_s = alpha / p;
-  const double b_s = beta / p;
-
-  // ---- z_1 and the rotation (c0, s0) that combines the children's null
-  // vectors: x1 = c0 [q1; 0] + s0 [0; q2] carries z_1, y = -s0 [q1; 0] + c0 [0; q2]
-  // is the node's own null vector
+  h.a_s = alpha / h.p;
+  h.b_s = beta / h.p;
   const double lam1 = V[(r0 + k - 1) + (int64_t)(r0 + k - 1) * ld];
   const double phi2 = s ? V[(r0 + k) + (int64_t)(r0 + m) * ld] : 0.0;
-  const double a = a_s * lam1;
-  const double b = b_s * phi2;
-  const double rr = sqrt(a * a + b * b);
-  double c0 = 1.0, s0 = 0.0;
-  if (rr != 0.0) {
-    c0 = a / rr;
-    s0 = b / rr;
+  const double a = h.a_s * lam1;
+  const double b = h.b_s * phi2;
+  h.rr = sqrt(a * a + b * b);
+  h.c0 = 1.0;
+  h.s0 = 0.0;
+  if (h.rr != 0.0) {
+    h.c0 = a / h.rr;
+    h.s0 = b / h.rr;
   }
+  return h;
+}
 
-  // ---- z and d of every node column, and its place in the sorted order:
-  // the new d = 0 first, then the two ascending child lists merged (ties
-  // take the left child first)
+// z and d of every node column and its place in the sorted order: the new
+// d = 0 first, then the two ascending child lists merged (ties take the left
+// child first).  Many workgroups per node; the largest of d and |z| is
+// combined with an atomic max on the bit pattern (non-negative doubles order
+// like their bits).
+__global__ __launch_bounds__(256) void k_zsort(const NodeDesc* __restrict__ nodes, Work w) {
+  __shared__ double shd[8];
+  const NodeDesc nd = nodes[blockIdx.x];
+  const int m = nd.m, k = nd.k, r0 = nd.r0, m2 = nd.m - nd.k;
+  const int64_t ld = nd.ld, pv = nd.vec_off, vo = nd.vec_off + nd.r0;
+  const double* V = w.Vw + nd.mat_off;
+  if ((int)blockIdx.y * kBlock >= m) return;
+  const MergeHead h = merge_head(nd, w);
+  if (blockIdx.y == 0 && threadIdx.x == 0 &&
+      !(fabs(w.d[pv + r0 + k - 1]) <= DBL_MAX && fabs(w.e[pv + r0 + k - 1]) <= DBL_MAX))
+    atomicOr(&w.ctl->nonfinite, 1);
   const double* sig = w.sig + vo;
   double lmax = 0.0;
-  for (int c = t; c < m; c += kBlock) {
+  for (int c = blockIdx.y * kBlock + threadIdx.x; c < m; c += gridDim.y * kBlock) {
     double dv, zv;
     int pc, pos, sup;
     if (c < k - 1) {
       pc = w.col[vo + c];
       const double sv = sig[c];
-      dv = sv / p;
+      dv = sv / h.p;
       const int row = r0 + k - 1;  // last row of the left child's right basis
       const double q = (row >= w.vlo[pv + pc] && row < w.vhi[pv + pc]) ? V[row + (int64_t)pc * ld] : 0.0;
-      zv = a_s * q;
+      zv = h.a_s * q;
       pos = 1 + c + count_less(sig + k, m2, sv);
       sup = 1;
     } else if (c == k - 1) {
       pc = r0 + k - 1;
       dv = 0.0;
-      zv = rr;
+      zv = h.rr;
       pos = 0;
       sup = 0;
     } else {
       pc = w.col[vo + c];
       const double sv = sig[c];
-      dv = sv / p;
+      dv = sv / h.p;
       const int row = r0 + k;  // first row of the right child's right basis
       const double q = (row >= w.vlo[pv + pc] && row < w.vhi[pv + pc]) ? V[row + (int64_t)pc * ld] : 0.0;
-      zv = b_s * q;
+      zv = h.b_s * q;
       pos = 1 + (c - k) + count_leq(sig, k - 1, sv);
       sup = 3;
     }
@@ -138,122 +142,185 @@ __global__ __launch_bounds__(256) void k_prep(const NodeDesc* __restrict__ nodes
     w.status[vo + pos] = 0;
     lmax = fmax(lmax, fmax(dv, fabs(zv)));
   }
-  // tol stands for eps * ||M||: 8 * 2^-52 * max(max d, max |z|)
-  const double tol = 8.0 * kEps * block_max(lmax, shd);
+  lmax = block_max(lmax, shd);
+  if (threadIdx.x == 0)
+    atomicMax(&w.st[nd.id].zmax_bits, (unsigned long long)__double_as_longlong(lmax));
+}
 
-  // ---- small z components (independent of each other): z_j -> 0.  The
-  // others are compacted, in order, into the candidate list.
-  {
-    const int per = (m - 1 + kBlock - 1) / kBlock;
-    const int b0 = 1 + t * per;
-    const int b1 = min(m, b0 + per);
-    int cnt[1] = {0}, tot[1];
-    for (int pos = b0; pos < b1; ++pos) {
-      const double z = w.ps_z[vo + pos];
-      if (!(fabs(z) < tol || z == 0.0)) ++cnt[0];
+// Deflation of one node (one workgroup).  The scan of the paper's rules over
+// positions 2..m is sequential as written, but its decisions are not: after
+// a candidate (a position whose z is not small and whose value is not within
+// tol of 0) has been processed, the "last kept value" it is compared with is
+// always that candidate's own sorted value -- it either became the last kept
+// value or was merged into it, which sets the kept value to it.  So each
+// close-pair decision is d_j - d_prev < tol with d_prev the previous
+// candidate's value, computed in parallel; only the z accumulation along a
+// run of close pairs (kept value followed by the values merged into it) and
+// the rotations into z_1 stay sequential, one thread per run.
+__global__ __launch_bounds__(256) void k_prep(const NodeDesc* __restrict__ nodes, Work w) {
+  __shared__ double shd[8];
+  __shared__ int shi[kBlock * 6];
+  __shared__ double shl[kBlock];
+  __shared__ int shh[kBlock];
+  __shared__ int sh_cnt[4];
+
+  const NodeDesc nd = nodes[blockIdx.x];
+  const int m = nd.m, k = nd.k, s = nd.s, r0 = nd.r0;
+  const int64_t ld = nd.ld, pv = nd.vec_off, vo = nd.vec_off + nd.r0;
+  double* V = w.Vw + nd.mat_off;
+  const int t = threadIdx.x;
+  const MergeHead h = merge_head(nd, w);
+  const double p = h.p, c0 = h.c0, s0 = h.s0;
+  const double zmax = __longlong_as_double((long long)w.st[nd.id].zmax_bits);
+  // tol stands for eps * ||M||: 8 * 2^-52 * max(max d, max |z|)
+  const double tol = 8.0 * kEps * zmax;
+  const int64_t rb = 2 * vo;
+
+  // positions 1..m-1 in contiguous segments, one per thread
+  const int per = (m - 1 + kBlock - 1) / kBlock;
+  const int b0 = min(m, 1 + t * per);
+  const int b1 = min(m, b0 + per);
+
+  // pass 1: classes; the last candidate value of each segment
+  int cnt[3] = {0, 0, 0}, tot[3];  // near-zero values, candidates, close-pair followers
+  double seg_last = 0.0;
+  int seg_has = 0;
+  for (int pos = b0; pos < b1; ++pos) {
+    const double z = w.ps_z[vo + pos], d = w.ps_d[vo + pos];
+    if (fabs(z) < tol || z == 0.0) continue;
+    if (d < tol || d == 0.0) {
+      ++cnt[0];
+      continue;
     }
-    block_exscan<1>(cnt, tot, shi);
-    int ci = cnt[0];
-    for (int pos = b0; pos < b1; ++pos) {
-      const double z = w.ps_z[vo + pos];
-      if (fabs(z) < tol || z == 0.0) {
-        w.status[vo + pos] = 1;
-        w.ps_z[vo + pos] = 0.0;
-      } else {
-        w.cand[vo + ci++] = pos;
-      }
+    ++cnt[1];
+    seg_last = d;
+    seg_has = 1;
+  }
+  // previous candidate value at each segment start: right-most defined value
+  // among earlier segments (inclusive scan with "later defined wins")
+  shl[t] = seg_last;
+  shh[t] = seg_has;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    double lv = 0.0;
+    int lh = 0;
+    if (t >= off) {
+      lv = shl[t - off];
+      lh = shh[t - off];
     }
-    if (t == 0) sh_cnt[0] = tot[0];
+    __syncthreads();
+    if (t >= off && !shh[t] && lh) {
+      shl[t] = lv;
+      shh[t] = 1;
+    }
     __syncthreads();
   }
-  const int ncand = sh_cnt[0];
-
-  // ---- the sequential scan (one thread): a value within tol of d_1 = 0 is
-  // rotated into z_1 from the right and set to 0; a value within tol of the
-  // last kept value is rotated into it from both sides, the earlier position
-  // keeping the combined z and taking the later value; otherwise it is kept.
-  double z0 = 0.0, dlast = 0.0, zlast = 0.0;
-  int last = -1, suplast = 0, rotlast = 0, nrot = 0, nzero = 0, nclose = 0;
-  const int64_t rb = 2 * vo;
-  if (t == 0) z0 = w.ps_z[vo];
-  for (int base = 0; base < ncand; base += kChunk) {
-    const int nb = min(kChunk, ncand - base);
-    __syncthreads();
-    for (int i = t; i < nb; i += kBlock) {
-      const int pos = w.cand[vo + base + i];
-      c_pos[i] = pos;
-      c_d[i] = w.ps_d[vo + pos];
-      c_z[i] = w.ps_z[vo + pos];
-      c_sup[i] = w.ps_sup[vo + pos];
+  double dprev = t > 0 ? shl[t - 1] : 0.0;
+  int has_prev = t > 0 ? shh[t - 1] : 0;
+  __syncthreads();
+  // pass 1b: close-pair followers in the segment
+  {
+    double dp = dprev;
+    int hp = has_prev;
+    for (int pos = b0; pos < b1; ++pos) {
+      const double z = w.ps_z[vo + pos], d = w.ps_d[vo + pos];
+      if (fabs(z) < tol || z == 0.0 || d < tol || d == 0.0) continue;
+      if (hp && (d - dp < tol || d == dp)) ++cnt[2];
+      dp = d;
+      hp = 1;
     }
-    __syncthreads();
-    if (t == 0) {
-      for (int i = 0; i < nb; ++i) {
-        const int j = c_pos[i];
-        const double dj = c_d[i], zj = c_z[i];
-        if (dj < tol || dj == 0.0) {
-          const double r = sqrt(z0 * z0 + zj * zj);
-          const double c = z0 / r, sn = zj / r;
-          w.rot_pos[rb + 2 * nrot] = 0;
-          w.rot_pos[rb + 2 * nrot + 1] = j;
-          w.rot_col[rb + 2 * nrot] = r0 + k - 1;
-          w.rot_col[rb + 2 * nrot + 1] = w.ps_col[vo + j];
-          w.rot_cs[rb + 2 * nrot] = c;
-          w.rot_cs[rb + 2 * nrot + 1] = sn;
-          ++nrot;
-          z0 = r;
-          w.ps_z[vo + j] = 0.0;
-          w.ps_d[vo + j] = 0.0;
-          w.status[vo + j] = 2;
-          w.ps_rot[vo + j] = kRotV;
-          ++nzero;
-        } else if (last >= 0 && (dj - dlast < tol || dj == dlast)) {
-          const double r = sqrt(zlast * zlast + zj * zj);
-          const double c = zlast / r, sn = zj / r;
-          w.rot_pos[rb + 2 * nrot] = last;
-          w.rot_pos[rb + 2 * nrot + 1] = j;
-          w.rot_col[rb + 2 * nrot] = w.ps_col[vo + last];
-          w.rot_col[rb + 2 * nrot + 1] = w.ps_col[vo + j];
-          w.rot_cs[rb + 2 * nrot] = c;
-          w.rot_cs[rb + 2 * nrot + 1] = sn;
-          ++nrot;
-          zlast = r;
-          dlast = dj;
-          rotlast = kRotU | kRotV;
-          w.ps_z[vo + j] = 0.0;
-          w.status[vo + j] = 3;
-          w.ps_rot[vo + j] = kRotU | kRotV;
-          if (suplast != c_sup[i]) {
-            suplast = 2;
-            w.ps_sup[vo + j] = 2;
-          }
-          ++nclose;
-        } else {
-          if (last >= 0) {
-            w.ps_d[vo + last] = dlast;
-            w.ps_z[vo + last] = zlast;
-            w.ps_sup[vo + last] = suplast;
-            w.ps_rot[vo + last] = rotlast;
-          }
-          last = j;
-          dlast = dj;
-          zlast = zj;
-          suplast = c_sup[i];
-          rotlast = 0;
-        }
+  }
+  block_exscan<3>(cnt, tot, shi);
+  const int nzero = tot[0], ncand = tot[1], nclose = tot[2];
+  // pass 2: statuses, lists, rotation slots of the followers
+  {
+    int iz = cnt[0], ic = cnt[1], ifl = cnt[2];
+    double dp = dprev;
+    int hp = has_prev;
+    for (int pos = b0; pos < b1; ++pos) {
+      const double z = w.ps_z[vo + pos], d = w.ps_d[vo + pos];
+      if (fabs(z) < tol || z == 0.0) {
+        w.status[vo + pos] = 1;  // small z component: z_j -> 0
+        w.ps_z[vo + pos] = 0.0;
+        continue;
+      }
+      if (d < tol || d == 0.0) {
+        w.status[vo + pos] = 2;  // within tol of d_1 = 0: rotated into z_1, value 0
+        w.cand[vo + iz++] = pos;
+        continue;
+      }
+      const bool close = hp && (d - dp < tol || d == dp);
+      w.status[vo + pos] = close ? 3 : 0;
+      // rotation slot of a follower, kept in sgrp until the lists are built
+      w.sgrp[vo + pos] = close ? nzero + ifl++ : -1;
+      w.cand[vo + nzero + ic++] = pos;
+      dp = d;
+      hp = 1;
+    }
+  }
+  __syncthreads();
+
+  // rotations into z_1 (one thread; all near-zero values precede every
+  // candidate in the scan order, so they take rotation slots 0..nzero-1)
+  if (t == 0) {
+    double z0 = w.ps_z[vo];
+    for (int q = 0; q < nzero; ++q) {
+      const int j = w.cand[vo + q];
+      const double zj = w.ps_z[vo + j];
+      const double r = sqrt(z0 * z0 + zj * zj);
+      const double c = z0 / r, sn = zj / r;
+      w.rot_pos[rb + 2 * q] = 0;
+      w.rot_pos[rb + 2 * q + 1] = j;
+      w.rot_col[rb + 2 * q] = r0 + k - 1;
+      w.rot_col[rb + 2 * q + 1] = w.ps_col[vo + j];
+      w.rot_cs[rb + 2 * q] = c;
+      w.rot_cs[rb + 2 * q + 1] = sn;
+      z0 = r;
+      w.ps_z[vo + j] = 0.0;
+      w.ps_d[vo + j] = 0.0;
+      w.ps_rot[vo + j] = kRotV;
+    }
+    if (z0 < tol) z0 = tol;  // small z_1 is raised to tol (after the scan)
+    w.ps_z[vo] = z0;
+  }
+  // runs of close pairs: each kept candidate absorbs the followers after it
+  for (int u = t; u < ncand; u += kBlock) {
+    const int pp = w.cand[vo + nzero + u];
+    if (w.status[vo + pp] != 0) continue;
+    double zl = w.ps_z[vo + pp], dl = w.ps_d[vo + pp];
+    int sup = w.ps_sup[vo + pp], rot = 0;
+    for (int v = u + 1; v < ncand; ++v) {
+      const int j = w.cand[vo + nzero + v];
+      if (w.status[vo + j] != 3) break;
+      const double zj = w.ps_z[vo + j];
+      const double r = sqrt(zl * zl + zj * zj);
+      const double c = zl / r, sn = zj / r;
+      const int q = w.sgrp[vo + j];
+      w.rot_pos[rb + 2 * q] = pp;
+      w.rot_pos[rb + 2 * q + 1] = j;
+      w.rot_col[rb + 2 * q] = w.ps_col[vo + pp];
+      w.rot_col[rb + 2 * q + 1] = w.ps_col[vo + j];
+      w.rot_cs[rb + 2 * q] = c;
+      w.rot_cs[rb + 2 * q + 1] = sn;
+      zl = r;
+      dl = w.ps_d[vo + j];
+      rot = kRotU | kRotV;
+      w.ps_z[vo + j] = 0.0;
+      w.ps_rot[vo + j] = kRotU | kRotV;
+      const int sj = w.ps_sup[vo + j];
+      if (sup != sj) {
+        sup = 2;
+        w.ps_sup[vo + j] = 2;
       }
     }
+    w.ps_z[vo + pp] = zl;
+    w.ps_d[vo + pp] = dl;
+    w.ps_sup[vo + pp] = sup;
+    w.ps_rot[vo + pp] = rot;
   }
   if (t == 0) {
-    if (last >= 0) {
-      w.ps_d[vo + last] = dlast;
-      w.ps_z[vo + last] = zlast;
-      w.ps_sup[vo + last] = suplast;
-      w.ps_rot[vo + last] = rotlast;
-    }
-    if (z0 < tol) z0 = tol;  // small z_1 is raised to tol
-    w.ps_z[vo] = z0;
-    sh_cnt[1] = nrot;
+    sh_cnt[0] = ncand;
+    sh_cnt[1] = nzero + nclose;
     sh_cnt[2] = nzero;
     sh_cnt[3] = nclose;
   }
@@ -326,7 +393,7 @@ __global__ __launch_bounds__(256) void k_prep(const NodeDesc* __restrict__ nodes
       w.vlo[pv + r0 + m] = r0;
       w.vhi[pv + r0 + m] = r0 + m + s;
     }
-    NodeState st;
+    NodeState st = w.st[nd.id];
     st.N = N;
     st.n1 = n1;
     st.n2 = n2;
@@ -334,7 +401,7 @@ __global__ __launch_bounds__(256) void k_prep(const NodeDesc* __restrict__ nodes
     st.nrot = sh_cnt[1];
     st.nzero_d = sh_cnt[2];
     st.nclose = sh_cnt[3];
-    st.nsmall_z = m - 1 - ncand;
+    st.nsmall_z = m - 1 - sh_cnt[0] - sh_cnt[2];
     st.scale = p;
     st.tol = tol;
     st.c0 = c0;
@@ -347,8 +414,11 @@ __global__ __launch_bounds__(256) void k_prep(const NodeDesc* __restrict__ nodes
 }  // namespace
 
 void launch_prep(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {
-  (void)max_m;
   if (nnodes <= 0) return;
+  int gy = (max_m + kBlock - 1) / kBlock;
+  const int cap = 4096 / nnodes;
+  if (gy > cap) gy = cap > 0 ? cap : 1;
+  hipLaunchKernelGGL(k_zsort, dim3(nnodes, gy), dim3(kBlock), 0, st, nodes, w);
   hipLaunchKernelGGL(k_prep, dim3(nnodes), dim3(kBlock), 0, st, nodes, w);
 }
 

@@ -253,19 +253,27 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafDesc* __restrict__ leaves
   if (lane == 0) atomicAdd(&w.ctl->leaf_rot_flops, 6ull * (nrot_w * (unsigned long long)m + nrot_q * (unsigned long long)ms));
 }
 
-__global__ void k_reset(Ctl* ctl) {
-  ctl->nonfinite = 0;
-  ctl->leaf_capped = 0;
-  ctl->secular_capped = 0;
-  ctl->pad = 0;
-  ctl->secular_evals = 0ull;
-  ctl->secular_terms = 0ull;
-  ctl->leaf_rot_flops = 0ull;
+__global__ __launch_bounds__(256) void k_reset(Ctl* ctl, NodeState* st, int nnodes) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->nonfinite = 0;
+    ctl->leaf_capped = 0;
+    ctl->secular_capped = 0;
+    ctl->pad = 0;
+    ctl->secular_evals = 0ull;
+    ctl->secular_terms = 0ull;
+    ctl->leaf_rot_flops = 0ull;
+  }
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < nnodes; i += gridDim.x * 256) st[i].zmax_bits = 0ull;
 }
 
 }  // namespace
 
-void launch_reset(Ctl* ctl, hipStream_t st) { hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, ctl); }
+void launch_reset(Ctl* ctl, NodeState* nst, int nnodes, hipStream_t st) {
+  int blocks = (nnodes + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 64) blocks = 64;
+  hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, st, ctl, nst, nnodes);
+}
 
 void launch_leaf(const LeafDesc* leaves, int nleaves, const Work& w, hipStream_t st) {
   if (nleaves <= 0) return;

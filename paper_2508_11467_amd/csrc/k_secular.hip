@@ -27,42 +27,71 @@ namespace {
 
 constexpr double kEps = 0x1p-52;
 
-struct Eval {
-  double f, dpsi, dphi, E;
-};
+constexpr int kSecRoots = 64;    // roots per workgroup (one per lane)
+constexpr int kSecWaves = 4;     // wavefronts splitting the pole sums
+constexpr int kSecChunk = 512;   // poles staged in LDS per wavefront
 
-// f(omega) and the pieces of the rational model at omega = ov + tau; poles
-// 0..lp form psi, lp+1..N-1 form phi.
-__device__ inline Eval evaluate(const double* __restrict__ d, const double* __restrict__ z, int N,
-                                double ov, double tau, int lp) {
-  double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, E = 0.0;
-  for (int j = 0; j <= lp; ++j) {
-    const double dj = d[j], zj = z[j];
-    const double del = ((dj - ov) - tau) * ((dj + ov) + tau);
-    const double r = 1.0 / del;
-    const double tt = (zj * zj) * r;
-    psi += tt;
-    dpsi += tt * r;
-    E += fabs(tt);
-  }
-  for (int j = N - 1; j > lp; --j) {
-    const double dj = d[j], zj = z[j];
-    const double del = ((dj - ov) - tau) * ((dj + ov) + tau);
-    const double r = 1.0 / del;
-    const double tt = (zj * zj) * r;
-    phi += tt;
-    dphi += tt * r;
-    E += fabs(tt);
-  }
-  Eval ev;
-  ev.f = (1.0 + psi) + phi;
-  ev.dpsi = dpsi;
-  ev.dphi = dphi;
-  ev.E = 1.0 + E;
-  return ev;
+// 1/x to full precision: the hardware estimate refined by two Newton steps
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
 }
 
-__global__ __launch_bounds__(64) void k_secular(const NodeDesc* __restrict__ nodes, Work w) {
+struct Part {
+  double s, ds, E;
+};
+
+// Sum the pole terms j = j0, j0+step, ... (count terms) in that order.  Four
+// terms are formed at a time so their reciprocals overlap; they are still
+// accumulated one by one in order.
+__device__ inline void sum_terms(const double* __restrict__ dj, const double* __restrict__ zz, int j0, int step,
+                                 int count, double ov, double tau, Part& P) {
+  int q = 0;
+  for (; q + 4 <= count; q += 4) {
+    double t[4], r[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + (q + u) * step;
+      const double dd = dj[j];
+      const double del = ((dd - ov) - tau) * ((dd + ov) + tau);  // d_j^2 - omega^2
+      r[u] = recip(del);
+      t[u] = zz[j] * r[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      P.s += t[u];
+      P.ds = fma(t[u], r[u], P.ds);
+      P.E += fabs(t[u]);
+    }
+  }
+  for (; q < count; ++q) {
+    const int j = j0 + q * step;
+    const double dd = dj[j];
+    const double del = ((dd - ov) - tau) * ((dd + ov) + tau);
+    const double r = recip(del);
+    const double t = zz[j] * r;
+    P.s += t;
+    P.ds = fma(t, r, P.ds);
+    P.E += fabs(t);
+  }
+}
+
+// Secular roots of one node: 64 roots per workgroup, one per lane; the four
+// wavefronts each sum a quarter of the poles for all 64 roots (staged in LDS,
+// read by every lane at the same address), and wavefront 0 combines the
+// partial sums -- left-pole sums in ascending quarter order, right-pole sums
+// in descending order, so both stay summed from far to near -- and advances
+// each root's iteration.
+__global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ nodes, Work w) {
+  __shared__ double cd[kSecWaves][kSecChunk];
+  __shared__ double cz[kSecWaves][kSecChunk];
+  __shared__ double part[kSecWaves][5][kSecRoots];
+  __shared__ double b_ov[kSecRoots], b_tau[kSecRoots];
+  __shared__ int b_need[kSecRoots];
+  __shared__ int b_go;
   const NodeDesc nd = nodes[blockIdx.x];
   const int N = w.st[nd.id].N;
   const double rho = w.st[nd.id].rho;
@@ -70,89 +99,176 @@ __global__ __launch_bounds__(64) void k_secular(const NodeDesc* __restrict__ nod
   const double* __restrict__ d = w.sd + vo;
   const double* __restrict__ z = w.sz + vo;
   const int maxit = w.max_secular_iters;
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  // this wavefront's quarter of the poles
+  const int Q = (N + kSecWaves - 1) / kSecWaves;
+  const int q0 = min(N, wv * Q), q1 = min(N, q0 + Q);
+  const bool resident = (q1 - q0) <= kSecChunk;  // the quarter fits in LDS once
 
-  for (int base = blockIdx.y * 64; base < N; base += gridDim.y * 64) {
-    const int i = base + threadIdx.x;
+  if (resident && (int)blockIdx.y * kSecRoots < N) {
+    for (int j = q0 + lane; j < q1; j += 64) {
+      cd[wv][j - q0] = d[j];
+      cz[wv][j - q0] = z[j] * z[j];
+    }
+  }
+  for (int base = blockIdx.y * kSecRoots; base < N; base += gridDim.y * kSecRoots) {
+    const int i = base + lane;
     const bool active = i < N;
+    const bool last = (i == N - 1);
+    const int lp = active ? (last ? N - 2 : i) : 0;  // left model pole
+    const int rp = lp + 1;
+    double dl = 0.0, dr = 0.0, ov = 0.0, tau = 0.0, lo = 0.0, hi = 0.0, mu = 0.0, base_v = 0.0;
     int o = 0, iters = 0, capped = 0;
-    double tau = 0.0;
-    if (active && N == 1) {
-      tau = fabs(z[0]);  // f = 1 - z^2/omega^2: omega = |z| exactly
-    } else if (active) {
-      const bool last = (i == N - 1);
-      const int lp = last ? N - 2 : i;  // left model pole
-      const int rp = lp + 1;            // right model pole
-      const double dl = d[lp], dr = d[rp];
+    bool need = active && N > 1;
+    bool first = true;
+    if (active && N == 1) tau = fabs(z[0]);  // f = 1 - z^2/omega^2: omega = |z| exactly
+    if (need) {
+      dl = d[lp];
+      dr = d[rp];
       // first evaluation: the midpoint in omega^2 of the root's interval
-      const double base_v = last ? dr : dl;
-      const double mu = last ? 0.5 * rho : 0.5 * (dr - dl) * (dr + dl);
-      const double tmid = mu / (base_v + sqrt(base_v * base_v + mu));
-      Eval ev = evaluate(d, z, N, base_v, tmid, lp);
-      iters = 1;
-      const bool go_right = !last && ev.f < 0.0;
-      o = (last || go_right) ? rp : lp;
-      const double ov = d[o];
-      const double wmid = base_v + tmid;
-      tau = go_right ? -mu / (dr + wmid) : tmid;
-      double lo, hi;
-      if (last) {
-        lo = 0.0;
-        hi = rho / (dr + sqrt(dr * dr + rho));
-        if (ev.f < 0.0) lo = tau;
-        else hi = tau;
-      } else if (go_right) {
-        lo = tau;
-        hi = 0.0;
-      } else {
-        lo = 0.0;
-        hi = tau;
+      base_v = last ? dr : dl;
+      mu = last ? 0.5 * rho : 0.5 * (dr - dl) * (dr + dl);
+      ov = base_v;
+      tau = mu / (base_v + sqrt(base_v * base_v + mu));
+    }
+    for (;;) {
+      if (wv == 0) {
+        b_ov[lane] = ov;
+        b_tau[lane] = tau;
+        b_need[lane] = need ? 1 : 0;
+        const int any = __any(need) ? 1 : 0;
+        if (lane == 0) b_go = any;
       }
-      bool done = fabs(ev.f) <= 8.0 * kEps * ev.E;
-      while (!done) {
-        // two-pole model at the current point (pole differences in omega^2)
-        const double Dl = ((dl - ov) - tau) * ((dl + ov) + tau);
-        const double Dr = ((dr - ov) - tau) * ((dr + ov) + tau);
-        const double f = ev.f;
-        const double c = f - Dl * ev.dpsi - Dr * ev.dphi;
-        const double a = (Dl + Dr) * f - Dl * Dr * (ev.dpsi + ev.dphi);
-        const double b = Dl * Dr * f;
-        const double disc = sqrt(fabs(a * a - 4.0 * b * c));
-        double eta;
-        if (c == 0.0) eta = b / a;
-        else if (last) eta = (a >= 0.0) ? (a + disc) / (2.0 * c) : 2.0 * b / (a - disc);
-        else eta = (a <= 0.0) ? (a - disc) / (2.0 * c) : 2.0 * b / (a + disc);
-        // omega^2 step eta -> tau step
-        const double om = ov + tau;
-        const double omn = sqrt(om * om + eta);
-        double tn = tau + eta / (om + omn);
-        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-        const bool small_step = fabs(tn - tau) <= 2.0 * kEps * fabs(tn);
-        tau = tn;
-        ev = evaluate(d, z, N, ov, tau, lp);
+      __syncthreads();
+      if (!b_go) break;
+      // ---- partial sums of this wavefront's quarter
+      const bool nd_l = b_need[lane] != 0;
+      const double eov = b_ov[lane], etau = b_tau[lane];
+      Part L{0.0, 0.0, 0.0}, R{0.0, 0.0, 0.0};
+      for (int c0 = q0; c0 < q1; c0 += kSecChunk) {
+        const int c1 = min(q1, c0 + kSecChunk);
+        if (!resident) {
+          __builtin_amdgcn_wave_barrier();
+          for (int j = c0 + lane; j < c1; j += 64) {
+            cd[wv][j - c0] = d[j];
+            cz[wv][j - c0] = z[j] * z[j];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (nd_l) {
+          // left poles j <= lp in this chunk, upwards
+          const int le = min(c1, lp + 1);
+          if (le > c0) sum_terms(cd[wv], cz[wv], 0, 1, le - c0, eov, etau, L);
+        }
+      }
+      for (int c1 = q1; c1 > q0; c1 -= kSecChunk) {
+        const int c0 = max(q0, c1 - kSecChunk);
+        if (!resident) {
+          __builtin_amdgcn_wave_barrier();
+          for (int j = c0 + lane; j < c1; j += 64) {
+            cd[wv][j - c0] = d[j];
+            cz[wv][j - c0] = z[j] * z[j];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (nd_l) {
+          // right poles j > lp in this chunk, downwards
+          const int ls = max(c0, lp + 1);
+          if (c1 > ls) sum_terms(cd[wv], cz[wv], c1 - 1 - c0, -1, c1 - ls, eov, etau, R);
+        }
+      }
+      part[wv][0][lane] = L.s;
+      part[wv][1][lane] = L.ds;
+      part[wv][2][lane] = R.s;
+      part[wv][3][lane] = R.ds;
+      part[wv][4][lane] = L.E + R.E;
+      __syncthreads();
+      if (wv == 0 && need) {
+        double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, E = 0.0;
+        for (int q = 0; q < kSecWaves; ++q) {
+          psi += part[q][0][lane];
+          dpsi += part[q][1][lane];
+          E += part[q][4][lane];
+        }
+        for (int q = kSecWaves - 1; q >= 0; --q) {
+          phi += part[q][2][lane];
+          dphi += part[q][3][lane];
+        }
+        const double f = (1.0 + psi) + phi;
+        E = 1.0 + E;
         ++iters;
-        if (ev.f < 0.0) lo = tau;
-        else hi = tau;
-        const bool conv = fabs(ev.f) <= 8.0 * kEps * ev.E;
-        if (!conv && !small_step && iters >= maxit) capped = 1;
-        done = conv || small_step || iters >= maxit;
+        bool conv = fabs(f) <= 8.0 * kEps * E;
+        if (first) {
+          first = false;
+          // origin: the pole nearer the root, by the sign of f at the midpoint
+          const bool go_right = !last && f < 0.0;
+          o = (last || go_right) ? rp : lp;
+          const double wmid = base_v + tau;
+          ov = d[o];
+          if (go_right) tau = -mu / (dr + wmid);
+          if (last) {
+            lo = 0.0;
+            hi = rho / (dr + sqrt(dr * dr + rho));
+            if (f < 0.0) lo = tau;
+            else hi = tau;
+          } else if (go_right) {
+            lo = tau;
+            hi = 0.0;
+          } else {
+            lo = 0.0;
+            hi = tau;
+          }
+        } else {
+          if (f < 0.0) lo = tau;
+          else hi = tau;
+        }
+        if (!conv && iters < maxit) {
+          // two-pole rational model at the current point
+          const double Dl = ((dl - ov) - tau) * ((dl + ov) + tau);
+          const double Dr = ((dr - ov) - tau) * ((dr + ov) + tau);
+          const double c = f - Dl * dpsi - Dr * dphi;
+          const double a = (Dl + Dr) * f - Dl * Dr * (dpsi + dphi);
+          const double b = Dl * Dr * f;
+          const double disc = sqrt(fabs(a * a - 4.0 * b * c));
+          double eta;
+          if (c == 0.0) eta = b / a;
+          else if (last) eta = (a >= 0.0) ? (a + disc) / (2.0 * c) : 2.0 * b / (a - disc);
+          else eta = (a <= 0.0) ? (a - disc) / (2.0 * c) : 2.0 * b / (a + disc);
+          const double om = ov + tau;
+          const double omn = sqrt(om * om + eta);
+          double tn = tau + eta / (om + omn);
+          if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+          // a step at the rounding level is accepted without another evaluation
+          if (fabs(tn - tau) <= 2.0 * kEps * fabs(tn)) conv = true;
+          tau = tn;
+        }
+        if (!conv && iters >= maxit) capped = 1;
+        need = !conv && iters < maxit;
+      }
+      __syncthreads();
+    }
+    if (wv == 0) {
+      if (active) {
+        w.o[vo + i] = o;
+        w.tau[vo + i] = tau;
+        w.iters[vo + i] = iters;
+      }
+      int it_sum = iters, cap_sum = capped;
+      for (int off = 32; off > 0; off >>= 1) {
+        it_sum += __shfl_xor(it_sum, off, 64);
+        cap_sum += __shfl_xor(cap_sum, off, 64);
+      }
+      if (lane == 0) {
+        atomicAdd(&w.ctl->secular_evals, (unsigned long long)it_sum);
+        atomicAdd(&w.ctl->secular_terms, (unsigned long long)it_sum * (unsigned long long)N);
+        if (cap_sum) atomicAdd(&w.ctl->secular_capped, cap_sum);
       }
     }
-    if (active) {
-      w.o[vo + i] = o;
-      w.tau[vo + i] = tau;
-      w.iters[vo + i] = iters;
-    }
-    // counters: one atomic per wavefront
-    int it_sum = iters, cap_sum = capped;
-    for (int off = 32; off > 0; off >>= 1) {
-      it_sum += __shfl_xor(it_sum, off, 64);
-      cap_sum += __shfl_xor(cap_sum, off, 64);
-    }
-    if (threadIdx.x == 0) {
-      atomicAdd(&w.ctl->secular_evals, (unsigned long long)it_sum);
-      atomicAdd(&w.ctl->secular_terms, (unsigned long long)it_sum * (unsigned long long)N);
-      if (cap_sum) atomicAdd(&w.ctl->secular_capped, cap_sum);
-    }
+    __syncthreads();
   }
 }
 
@@ -243,8 +359,8 @@ inline int grid_y(int nnodes, int units, int cap_total) {
 
 void launch_secular(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {
   if (nnodes <= 0) return;
-  const int gy = grid_y(nnodes, (max_m + 63) / 64, 8192);
-  hipLaunchKernelGGL(k_secular, dim3(nnodes, gy), dim3(64), 0, st, nodes, w);
+  const int gy = grid_y(nnodes, (max_m + kSecRoots - 1) / kSecRoots, 4096);
+  hipLaunchKernelGGL(k_secular, dim3(nnodes, gy), dim3(kSecRoots * kSecWaves), 0, st, nodes, w);
 }
 
 void launch_lowner(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {

@@ -145,6 +145,33 @@ def test_deterministic(solver):
         assert np.array_equal(x, y)
 
 
+def test_graph_replay_tracks_inputs(gpu):
+    """A replayed launch sequence reads the new contents of the same buffers."""
+    import torch
+    from paper_2508_11467_amd.api import Solver
+    g = Solver(0)
+    p = Solver(0, use_graph=False)
+    try:
+        n = 700
+        dt = torch.empty(n, dtype=torch.float64, device="cuda")
+        et = torch.empty(n - 1, dtype=torch.float64, device="cuda")
+        out = (torch.empty(n, dtype=torch.float64, device="cuda"),
+               torch.empty((n, n), dtype=torch.float64, device="cuda"),
+               torch.empty((n, n), dtype=torch.float64, device="cuda"))
+        for seed in (1, 2, 3):
+            d, e = inputs.normal(n, seed)
+            dt.copy_(torch.from_numpy(d))
+            et.copy_(torch.from_numpy(e))
+            s1, U1, V1 = [x.clone() for x in g.svd(dt, et, out=out)]
+            s2, U2, V2 = p.svd(dt, et)
+            torch.cuda.synchronize()
+            assert torch.equal(s1, s2) and torch.equal(U1, U2) and torch.equal(V1, V2)
+            assert g.info()[0] == 0
+    finally:
+        g.close()
+        p.close()
+
+
 def test_nonfinite_reported(solver):
     d, e = inputs.uniform(100, 7)
     d[40] = np.nan
