@@ -18,6 +18,16 @@ namespace {
 constexpr double kEps = 0x1p-52;
 constexpr int kLd = kMaxLeaf + 1;  // LDS column stride (doubles)
 
+// lane k's value of a per-lane double, as a wave-uniform value
+__device__ inline double lane_val(double v, int k) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+  return __hiloint2double(hi, lo);
+}
+
+// (c, s, r) with c f + s g = r >= 0 and -s f + c g = 0.  The leaf is scaled
+// so that |f|, |g| <= 2; the reciprocal square root (hardware estimate and
+// two Newton steps) is used unless f^2 + g^2 is near underflow.
 __device__ inline void givens(double f, double g, double& c, double& s, double& r) {
   if (g == 0.0) {
     c = f >= 0.0 ? 1.0 : -1.0;
@@ -25,9 +35,20 @@ __device__ inline void givens(double f, double g, double& c, double& s, double& 
     r = fabs(f);
     return;
   }
-  r = hypot(f, g);
-  c = f / r;
-  s = g / r;
+  const double q = fma(f, f, g * g);
+  if (q > 0x1p-960) {
+    double y = __builtin_amdgcn_rsq(q);
+    const double hq = 0.5 * q;
+    y = y * fma(-hq * y, y, 1.5);
+    y = y * fma(-hq * y, y, 1.5);
+    c = f * y;
+    s = g * y;
+    r = q * y;
+  } else {
+    r = hypot(f, g);
+    c = f / r;
+    s = g / r;
+  }
 }
 
 // columns (i, j) of an LDS matrix <- (c a_i + s a_j, -s a_i + c a_j), row = lane
@@ -45,21 +66,26 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
+// One 64-lane wavefront per leaf.  Lane L holds d_L and e_L (the
+// superdiagonal entry right of d_L) in registers; the Givens chain runs on
+// wave-uniform values read with readlane, and each rotation of W and Q is
+// applied by lane r to row r of the column-major LDS copies.  Along a sweep
+// the column being rotated forward stays in a register, so each step reads
+// one new column (independent of the chain) and writes one.
 __global__ __launch_bounds__(64) void k_leaf(const LeafDesc* __restrict__ leaves, Work w) {
-  unsigned long long nrot_w = 0, nrot_q = 0;  // rotations applied to W and to Q
   __shared__ double W[kMaxLeaf * kLd];
   __shared__ double Q[(kMaxLeaf + 1) * kLd];
-  __shared__ double dd[kMaxLeaf + 1];
-  __shared__ double ee[kMaxLeaf + 1];
 
   const LeafDesc L = leaves[blockIdx.x];
   const int m = L.m, s = L.s, ms = m + s, r0 = L.r0;
   const int lane = threadIdx.x;
   const int64_t ld = L.ld;
   const int64_t pv = L.vec_off;
+  unsigned long long nrot_w = 0, nrot_q = 0;  // rotations applied to W and to Q
 
   for (int i = lane; i < kMaxLeaf * kLd; i += 64) W[i] = 0.0;
   for (int i = lane; i < (kMaxLeaf + 1) * kLd; i += 64) Q[i] = 0.0;
+  __syncthreads();
   if (lane < m) W[lane + lane * kLd] = 1.0;
   if (lane < ms) Q[lane + lane * kLd] = 1.0;
 
@@ -71,32 +97,30 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafDesc* __restrict__ leaves
   // row, so leaves and merges between them check all of the input
   const bool bad = !(fabs(dv) <= 1.79769313486231570e308) || !(fabs(ev) <= 1.79769313486231570e308);
   if (__any(bad) && lane == 0) atomicOr(&w.ctl->nonfinite, 1);
-  double amax = wave_max(fmax(fabs(dv), fabs(ev)));
+  const double amax = wave_max(fmax(fabs(dv), fabs(ev)));
   double p = 1.0;
   if (amax > 0.0 && amax <= 1.79e308) {
     int ex;
     frexp(amax, &ex);
     p = ldexp(1.0, ex);
   }
-  if (lane <= kMaxLeaf) {
-    dd[lane] = lane < m ? dv / p : 0.0;
-    ee[lane] = lane < m - 1 + s ? ev / p : 0.0;
-  }
-  __syncthreads();
+  double dreg = dv / p;  // d_lane
+  double ereg = ev / p;  // e_lane (lane m-1: the extra column's entry when s = 1)
   const double tiny = kEps * (amax / p);
+  __syncthreads();
 
   // s = 1: remove the extra column's entry, bottom row first.  The right
   // rotation of columns (j, m) zeroes B[j, m] and moves a fill-in to B[j-1, m].
   if (s == 1) {
-    double f = ee[m - 1];
-    ee[m - 1] = 0.0;
+    double f = lane_val(ereg, m - 1);
+    if (lane == m - 1) ereg = 0.0;
     for (int j = m - 1; j >= 0; --j) {
       double c, sn, r;
-      givens(dd[j], f, c, sn, r);
-      dd[j] = r;
+      givens(lane_val(dreg, j), f, c, sn, r);
+      if (lane == j) dreg = r;
       if (j > 0) {
-        const double t = ee[j - 1];
-        ee[j - 1] = c * t;
+        const double t = lane_val(ereg, j - 1);
+        if (lane == j - 1) ereg = c * t;
         f = -sn * t;
       }
       rot_cols(Q, ms, j, m, c, sn, lane);
@@ -108,9 +132,11 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafDesc* __restrict__ leaves
   int steps = 0;
   int hi = m - 1;
   while (hi > 0) {
-    for (int i = 0; i < hi; ++i)
-      if (fabs(ee[i]) <= kEps * (fabs(dd[i]) + fabs(dd[i + 1]))) ee[i] = 0.0;
-    if (ee[hi - 1] == 0.0) {
+    // negligible superdiagonals -> 0; then the unreduced block [lo, hi]
+    const double dnext = __shfl_down(dreg, 1, 64);
+    if (lane < hi && fabs(ereg) <= kEps * (fabs(dreg) + fabs(dnext))) ereg = 0.0;
+    const unsigned long long nz = __ballot(lane < hi && ereg != 0.0);
+    if (!((nz >> (hi - 1)) & 1ull)) {
       --hi;
       continue;
     }
@@ -119,45 +145,40 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafDesc* __restrict__ leaves
       break;
     }
     ++steps;
-    int lo = hi - 1;
-    while (lo > 0 && ee[lo - 1] != 0.0) --lo;
-    int zero_at = -1;
-    for (int i = lo; i <= hi; ++i)
-      if (fabs(dd[i]) <= tiny) {
-        zero_at = i;
-        break;
-      }
-    if (zero_at >= 0) {
-      const int i = zero_at;
-      dd[i] = 0.0;
+    const unsigned long long zero_below = ~nz & ((1ull << (hi - 1)) - 1ull);
+    const int lo = zero_below ? 64 - __builtin_clzll(zero_below) : 0;
+    const unsigned long long zd = __ballot(lane >= lo && lane <= hi && fabs(dreg) <= tiny);
+    if (zd) {
+      const int i = __builtin_ctzll(zd);
+      if (lane == i) dreg = 0.0;
       if (i < hi) {
         // chase B[i, i+1] along row i with left rotations of rows (j, i)
-        double f = ee[i];
-        ee[i] = 0.0;
+        double f = lane_val(ereg, i);
+        if (lane == i) ereg = 0.0;
         for (int j = i + 1; j <= hi; ++j) {
           double c, sn, r;
-          givens(dd[j], f, c, sn, r);
-          dd[j] = r;
+          givens(lane_val(dreg, j), f, c, sn, r);
+          if (lane == j) dreg = r;
           if (j < hi) {
-            const double t = ee[j];
+            const double t = lane_val(ereg, j);
             f = -sn * t;
-            ee[j] = c * t;
+            if (lane == j) ereg = c * t;
           }
           rot_cols(W, m, j, i, c, sn, lane);
           ++nrot_w;
         }
       } else {
         // chase B[hi-1, hi] up column hi with right rotations of columns (j, hi)
-        double f = ee[hi - 1];
-        ee[hi - 1] = 0.0;
+        double f = lane_val(ereg, hi - 1);
+        if (lane == hi - 1) ereg = 0.0;
         for (int j = hi - 1; j >= lo; --j) {
           double c, sn, r;
-          givens(dd[j], f, c, sn, r);
-          dd[j] = r;
+          givens(lane_val(dreg, j), f, c, sn, r);
+          if (lane == j) dreg = r;
           if (j > lo) {
-            const double t = ee[j - 1];
+            const double t = lane_val(ereg, j - 1);
             f = -sn * t;
-            ee[j - 1] = c * t;
+            if (lane == j - 1) ereg = c * t;
           }
           rot_cols(Q, ms, j, hi, c, sn, lane);
           ++nrot_q;
@@ -168,8 +189,8 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafDesc* __restrict__ leaves
     // Wilkinson shift: eigenvalue of the trailing 2x2 of B^T B nearer its end
     double mu;
     {
-      const double dm = dd[hi - 1], dn = dd[hi], fm = ee[hi - 1];
-      const double g = (hi - 1 > lo) ? ee[hi - 2] : 0.0;
+      const double dm = lane_val(dreg, hi - 1), dn = lane_val(dreg, hi), fm = lane_val(ereg, hi - 1);
+      const double g = (hi - 1 > lo) ? lane_val(ereg, hi - 2) : 0.0;
       const double t11 = dm * dm + g * g, t12 = dm * fm, t22 = dn * dn + fm * fm;
       if (t12 == 0.0) {
         mu = t22;
@@ -181,36 +202,55 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafDesc* __restrict__ leaves
       }
     }
     // one implicit-shift sweep, bulge chased from lo to hi
-    double y = dd[lo] * dd[lo] - mu;
-    double z = dd[lo] * ee[lo];
-    double bulge = 0.0;
+    double dk = lane_val(dreg, lo), ek = lane_val(ereg, lo);
+    double y = dk * dk - mu;
+    double z = dk * ek;
+    double bulge = 0.0, eprev = 0.0;
+    double qk = lane < ms ? Q[lane + lo * kLd] : 0.0;
+    double wk = lane < m ? W[lane + lo * kLd] : 0.0;
     for (int k = lo; k < hi; ++k) {
+      // next columns of Q and W (independent of the Givens chain)
+      const double qk1 = lane < ms ? Q[lane + (k + 1) * kLd] : 0.0;
+      const double wk1 = lane < m ? W[lane + (k + 1) * kLd] : 0.0;
+      const double dk1 = lane_val(dreg, k + 1);
+      const double ek1 = (k < hi - 1) ? lane_val(ereg, k + 1) : 0.0;
       if (k > lo) {
-        y = ee[k - 1];
+        y = eprev;
         z = bulge;
       }
       double c, sn, r;
       givens(y, z, c, sn, r);
-      if (k > lo) ee[k - 1] = r;
-      const double dk = dd[k], ek = ee[k], dk1 = dd[k + 1];
+      if (k > lo && lane == k - 1) ereg = r;
       const double ndk = c * dk + sn * ek;
       const double nek = -sn * dk + c * ek;
       bulge = sn * dk1;
       const double ndk1 = c * dk1;
-      rot_cols(Q, ms, k, k + 1, c, sn, lane);
-      ++nrot_q;
-      givens(ndk, bulge, c, sn, r);
-      dd[k] = r;
-      ee[k] = c * nek + sn * ndk1;
-      dd[k + 1] = -sn * nek + c * ndk1;
-      if (k < hi - 1) {
-        const double t = ee[k + 1];
-        bulge = sn * t;
-        ee[k + 1] = c * t;
+      {
+        const double a = c * qk + sn * qk1, b = -sn * qk + c * qk1;
+        if (lane < ms) Q[lane + k * kLd] = a;
+        qk = b;
       }
-      rot_cols(W, m, k, k + 1, c, sn, lane);
-      ++nrot_w;
+      givens(ndk, bulge, c, sn, r);
+      if (lane == k) dreg = r;
+      eprev = c * nek + sn * ndk1;  // e_k
+      dk = -sn * nek + c * ndk1;    // d_{k+1}
+      ek = ek1;
+      if (k < hi - 1) {
+        bulge = sn * ek1;
+        ek = c * ek1;  // e_{k+1}
+      }
+      {
+        const double a = c * wk + sn * wk1, b = -sn * wk + c * wk1;
+        if (lane < m) W[lane + k * kLd] = a;
+        wk = b;
+      }
     }
+    if (lane == hi - 1) ereg = eprev;
+    if (lane == hi) dreg = dk;
+    if (lane < ms) Q[lane + hi * kLd] = qk;
+    if (lane < m) W[lane + hi * kLd] = wk;
+    nrot_q += hi - lo;
+    nrot_w += hi - lo;
   }
 
   // signs, ranks (ascending, ties by index) and output
@@ -218,14 +258,13 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafDesc* __restrict__ leaves
   double sv = 0.0;
   int rank = 0;
   if (lane < m) {
-    const double di = dd[lane];
-    sv = fabs(di);
-    if (di < 0.0)
+    sv = fabs(dreg);
+    if (dreg < 0.0)
       for (int r = 0; r < m; ++r) W[r + lane * kLd] = -W[r + lane * kLd];
-    for (int j = 0; j < m; ++j) {
-      const double sj = fabs(dd[j]);
-      rank += (sj < sv || (sj == sv && j < lane)) ? 1 : 0;
-    }
+  }
+  for (int j = 0; j < m; ++j) {
+    const double sj = fabs(lane_val(dreg, j));
+    rank += (lane < m && (sj < sv || (sj == sv && j < lane))) ? 1 : 0;
   }
   __syncthreads();
   double* Uw = w.Uw + L.mat_off;

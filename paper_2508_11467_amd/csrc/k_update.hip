@@ -19,6 +19,8 @@
 //   k_final_u / k_final_vt  write sigma, U and V^T in descending order
 //              (the root's ascending order reversed), expanding each column's
 //              support to the full matrix; V^T goes through an LDS transpose.
+#include <algorithm>
+
 #include "bdc_internal.h"
 #include "block_util.h"
 
@@ -172,67 +174,90 @@ __global__ __launch_bounds__(256) void k_order(const NodeDesc* __restrict__ node
 }
 
 // ------------------------------------------------------------------ GEMM
-// 64 x 64 output tile per 256-thread workgroup; each wavefront owns a 32 x 32
-// quarter as 2 x 2 blocks of v_mfma_f64_16x16x4f64.  A (M x K) and B (K x N)
-// are column-major; 16-deep K slabs are staged in LDS.
-constexpr int TM = 64, TN = 64, TK = 16;
+// TM x TN output tile per 256-thread workgroup: four wavefronts in 2 x 2, each
+// owning a (TM/2) x (TN/2) block as (TM/32) x (TN/32) v_mfma_f64_16x16x4f64
+// tiles.  A (M x K) and B (K x N) are column-major; 16-deep K slabs are staged
+// in LDS, and the next slab is loaded into registers while the current one is
+// multiplied.
+constexpr int TK = 16;
 
+template <int TM, int TN>
 struct TileSmem {
   double A[TK * TM];
   double B[TK * TN];
 };
 
-template <class Store>
-__device__ inline void gemm_tile(TileSmem& sm, const double* __restrict__ A, int64_t lda,
+template <int TM, int TN, class Store>
+__device__ inline void gemm_tile(TileSmem<TM, TN>& sm, const double* __restrict__ A, int64_t lda,
                                  const double* __restrict__ B, int64_t ldb, int M, int N, int K,
                                  int tm0, int tn0, Store store) {
+  constexpr int FA = TM * TK / kBlock;  // A elements per thread per slab
+  constexpr int FB = TN * TK / kBlock;
+  constexpr int BM = TM / 32, BN = TN / 32;  // 16x16 blocks per wavefront
   const int t = threadIdx.x, wv = t >> 6, l = t & 63;
   const int wm = wv & 1, wn = wv >> 1;
   const int li = l & 15, lk = l >> 4;
-  v4d acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  v4d acc[BM][BN];
+#pragma unroll
+  for (int a = 0; a < BM; ++a)
+#pragma unroll
+    for (int b = 0; b < BN; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  double ra[FA], rb[FB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < FA; ++q) {
+      const int e = t + kBlock * q;
+      const int r = e % TM, kk = e / TM;
+      const int gr = tm0 + r, gk = k0 + kk;
+      ra[q] = (gr < M && gk < K) ? A[gr + (int64_t)gk * lda] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < FB; ++q) {
+      const int e = t + kBlock * q;
+      const int kk = e % TK, c = e / TK;
+      const int gk = k0 + kk, gc = tn0 + c;
+      rb[q] = (gk < K && gc < N) ? B[gk + (int64_t)gc * ldb] : 0.0;
+    }
+  };
+  if (K > 0) load(0);
   for (int k0 = 0; k0 < K; k0 += TK) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < FA; ++q) {
       const int e = t + kBlock * q;
-      const int r = e & (TM - 1), kk = e >> 6;
-      const int gr = tm0 + r, gk = k0 + kk;
-      sm.A[kk * TM + r] = (gr < M && gk < K) ? A[gr + (int64_t)gk * lda] : 0.0;
+      sm.A[(e / TM) * TM + e % TM] = ra[q];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < FB; ++q) {
       const int e = t + kBlock * q;
-      const int kk = e & (TK - 1), c = e >> 4;
-      const int gk = k0 + kk, gc = tn0 + c;
-      sm.B[kk * TN + c] = (gk < K && gc < N) ? B[gk + (int64_t)gc * ldb] : 0.0;
+      sm.B[(e % TK) * TN + e / TK] = rb[q];
     }
     __syncthreads();
+    if (k0 + TK < K) load(k0 + TK);
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
-      double af[2], bf[2];
+      double af[BM], bf[BN];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) af[a] = sm.A[(kk + lk) * TM + wm * 32 + a * 16 + li];
+      for (int a = 0; a < BM; ++a) af[a] = sm.A[(kk + lk) * TM + wm * (TM / 2) + a * 16 + li];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bf[b] = sm.B[(kk + lk) * TN + wn * 32 + b * 16 + li];
+      for (int b = 0; b < BN; ++b) bf[b] = sm.B[(kk + lk) * TN + wn * (TN / 2) + b * 16 + li];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < BM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < BN; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
   }
   // D[i][j] of a 16x16 block sits in lane j + 16 * (i % 4), register i / 4
   // (checked against a host product)
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < BM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < BN; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = tm0 + wm * 32 + a * 16 + lk + 4 * r;
-        const int colc = tn0 + wn * 32 + b * 16 + li;
+        const int row = tm0 + wm * (TM / 2) + a * 16 + lk + 4 * r;
+        const int colc = tn0 + wn * (TN / 2) + b * 16 + li;
         if (row < M && colc < N) store(row, colc, acc[a][b][r]);
       }
 }
@@ -247,13 +272,20 @@ struct NodeStore {
   }
 };
 
+// Nodes whose kept size N is at most kSmallN use 64 x 64 tiles, larger ones
+// 128 x 128; each launch skips the nodes of the other class.
+constexpr int kSmallN = 96;
+
 // grid: (node, tile slot, side-half).  side-half: 0 U rows [0,k), 1 U rows
-// [k,m), 2 V rows [0,k), 3 V rows [k,m+s).
+// [k,m), 2 V rows [0,k), 3 V rows [k,m+s).  Tiles are visited with the row
+// index fastest, so the workgroups on one XCD (every 8th) share B panels.
+template <int TM, int TN>
 __global__ __launch_bounds__(256) void k_update(const NodeDesc* __restrict__ nodes, Work w) {
-  __shared__ TileSmem sm;
+  __shared__ TileSmem<TM, TN> sm;
   const NodeDesc nd = nodes[blockIdx.x];
   const NodeState st = w.st[nd.id];
   const int N = st.N, n1 = st.n1, n2 = st.n2;
+  if ((TM <= 64) != (N <= kSmallN)) return;
   const int m = nd.m, s = nd.s, k = nd.k, r0 = nd.r0;
   const int64_t ld = nd.ld, vo = nd.vec_off + nd.r0;
   const int sub = blockIdx.z;
@@ -272,7 +304,7 @@ __global__ __launch_bounds__(256) void k_update(const NodeDesc* __restrict__ nod
   const int ntiles = tiles_m * tiles_n;
   for (int tile = blockIdx.y; tile < ntiles; tile += gridDim.y) {
     const int tm = tile % tiles_m, tn = tile / tiles_m;
-    gemm_tile(sm, A, ld, B, ld, rows, N, K, tm * TM, tn * TN, store);
+    gemm_tile<TM, TN>(sm, A, ld, B, ld, rows, N, K, tm * TM, tn * TN, store);
   }
 }
 
@@ -282,18 +314,20 @@ struct PlainStore {
   __device__ void operator()(int row, int c, double v) const { C[row + (int64_t)c * ldc] = v; }
 };
 
+template <int TM, int TN>
 __global__ __launch_bounds__(256) void k_gemm_plain(int M, int N, int K, const double* A, int lda,
                                                      const double* B, int ldb, double* C, int ldc) {
-  __shared__ TileSmem sm;
+  __shared__ TileSmem<TM, TN> sm;
   const int tiles_m = (M + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
   for (int tile = blockIdx.x; tile < tiles_m * tiles_n; tile += gridDim.x) {
     const int tm = tile % tiles_m, tn = tile / tiles_m;
-    gemm_tile(sm, A, lda, B, ldb, M, N, K, tm * TM, tn * TN, PlainStore{C, ldc});
+    gemm_tile<TM, TN>(sm, A, lda, B, ldb, M, N, K, tm * TM, tn * TN, PlainStore{C, ldc});
   }
 }
 
 // ------------------------------------------------------------------ final
-// U: one workgroup per output column t (descending order), rows in parallel.
+// U: one workgroup per output column t (descending order); rows in pairs
+// with 16-byte stores when the column start is 16-byte aligned.
 __global__ __launch_bounds__(256) void k_final_u(const int64_t* __restrict__ pn,
                                                  const int64_t* __restrict__ pvec,
                                                  const int64_t* __restrict__ pmat,
@@ -312,15 +346,39 @@ __global__ __launch_bounds__(256) void k_final_u(const int64_t* __restrict__ pn,
   if (tcol >= n) return;
   const int64_t src = n - 1 - tcol;
   const int64_t pc = w.col[pv + src];
-  const int ul = w.ulo[pv + pc], uh = w.uhi[pv + pc];
+  const int64_t ul = w.ulo[pv + pc], uh = w.uhi[pv + pc];
   if (threadIdx.x == 0) sigma[pv + tcol] = w.sig[pv + src];
   const double* in = w.Uw + mo + pc * n;
   double* out = U + mo + tcol * n;
-  for (int64_t r = threadIdx.x; r < n; r += kBlock) out[r] = (r >= ul && r < uh) ? in[r] : 0.0;
+  if ((((uintptr_t)out) & 15) == 0 && (((uintptr_t)in) & 15) == 0) {
+    const int64_t n2 = n >> 1;
+    double2* o2 = reinterpret_cast<double2*>(out);
+    const double2* i2 = reinterpret_cast<const double2*>(in);
+    for (int64_t r2 = threadIdx.x; r2 < n2; r2 += kBlock) {
+      const int64_t r = 2 * r2;
+      double2 v = make_double2(0.0, 0.0);
+      if (r + 1 >= ul && r < uh) {
+        if (r >= ul && r + 1 < uh) {
+          v = i2[r2];
+        } else {
+          v.x = (r >= ul && r < uh) ? in[r] : 0.0;
+          v.y = (r + 1 >= ul && r + 1 < uh) ? in[r + 1] : 0.0;
+        }
+      }
+      o2[r2] = v;
+    }
+    if ((n & 1) && threadIdx.x == 0) {
+      const int64_t r = n - 1;
+      out[r] = (r >= ul && r < uh) ? in[r] : 0.0;
+    }
+  } else {
+    for (int64_t r = threadIdx.x; r < n; r += kBlock) out[r] = (r >= ul && r < uh) ? in[r] : 0.0;
+  }
 }
 
-// V^T: 64 x 64 tiles; reads columns of Vwork (coalesced), writes rows of V^T
-// as columns of the column-major output (coalesced) through LDS.
+// V^T: 64 x 64 tiles; reads columns of Vwork (coalesced, skipped outside
+// each column's support), writes rows of V^T as columns of the column-major
+// output (coalesced) through LDS.
 __global__ __launch_bounds__(256) void k_final_vt(const int64_t* __restrict__ pn,
                                                   const int64_t* __restrict__ pvec,
                                                   const int64_t* __restrict__ pmat,
@@ -352,25 +410,38 @@ __global__ __launch_bounds__(256) void k_final_vt(const int64_t* __restrict__ pn
       hiv[t] = w.vhi[pv + pc];
     } else {
       pcs[t] = -1;
+      lov[t] = 0;
+      hiv[t] = 0;
     }
   }
   __syncthreads();
   const double* Vw = w.Vw + mo;
-  // load: element (j, tv) = V[j0 + jj, pc(tv)]
-  for (int e = t; e < 64 * 64; e += kBlock) {
-    const int jj = e & 63, tt = e >> 6;
+  // load: element (j, tv) = V[j0 + jj, pc(tv)]; one wavefront per 16 vectors
+  {
+    const int wv = t >> 6, jj = t & 63;
     const int64_t j = j0 + jj;
-    double v = 0.0;
-    const int64_t pc = pcs[tt];
-    if (pc >= 0 && j < n && j >= lov[tt] && j < hiv[tt]) v = Vw[j + pc * n];
-    tileS[tt][jj] = v;
+    for (int tt = wv; tt < 64; tt += 4) {
+      const int64_t pc = pcs[tt];
+      double v = 0.0;
+      if (pc >= 0 && j0 < hiv[tt] && j0 + 64 > lov[tt] && j < n && j >= lov[tt] && j < hiv[tt])
+        v = Vw[j + pc * n];
+      tileS[tt][jj] = v;
+    }
   }
   __syncthreads();
   double* out = VT + mo;
-  for (int e = t; e < 64 * 64; e += kBlock) {
-    const int tt = e & 63, jj = e >> 6;
+  // store: column j of V^T, rows t0..t0+63, two rows per thread
+  const bool vec = ((((uintptr_t)(out + t0)) & 15) == 0) && ((n & 1) == 0);
+  for (int e = t; e < 32 * 64; e += kBlock) {
+    const int tt = 2 * (e & 31), jj = e >> 5;
     const int64_t tv = t0 + tt, j = j0 + jj;
-    if (tv < n && j < n) out[tv + j * n] = tileS[tt][jj];
+    if (j >= n) continue;
+    if (vec && tv + 1 < n) {
+      *reinterpret_cast<double2*>(out + tv + j * n) = make_double2(tileS[tt][jj], tileS[tt + 1][jj]);
+    } else {
+      if (tv < n) out[tv + j * n] = tileS[tt][jj];
+      if (tv + 1 < n) out[tv + 1 + j * n] = tileS[tt + 1][jj];
+    }
   }
 }
 
@@ -396,17 +467,30 @@ void launch_order(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, h
 
 void launch_update(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {
   if (nnodes <= 0) return;
-  const int tiles = ((max_m + 1 + TM - 1) / TM) * ((max_m + TN - 1) / TN);
-  const int gy = grid_y(nnodes, tiles, 2048);
-  hipLaunchKernelGGL(k_update, dim3(nnodes, gy, 4), dim3(kBlock), 0, st, nodes, w);
+  {
+    const int tiles = ((max_m + 1 + 63) / 64) * ((std::min(max_m, kSmallN) + 63) / 64);
+    const int gy = grid_y(nnodes, tiles, 2048);
+    hipLaunchKernelGGL((k_update<64, 64>), dim3(nnodes, gy, 4), dim3(kBlock), 0, st, nodes, w);
+  }
+  if (max_m > kSmallN) {
+    const int tiles = ((max_m + 1 + 127) / 128) * ((max_m + 127) / 128);
+    const int gy = grid_y(nnodes, tiles, 1024);
+    hipLaunchKernelGGL((k_update<128, 128>), dim3(nnodes, gy, 4), dim3(kBlock), 0, st, nodes, w);
+  }
 }
 
 void launch_gemm_plain(int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                        double* C, int ldc, hipStream_t st) {
   if (M <= 0 || N <= 0) return;
-  int tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
-  if (tiles > 4096) tiles = 4096;
-  hipLaunchKernelGGL(k_gemm_plain, dim3(tiles), dim3(kBlock), 0, st, M, N, K, A, lda, B, ldb, C, ldc);
+  if (N <= kSmallN) {
+    int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+    if (tiles > 4096) tiles = 4096;
+    hipLaunchKernelGGL((k_gemm_plain<64, 64>), dim3(tiles), dim3(kBlock), 0, st, M, N, K, A, lda, B, ldb, C, ldc);
+  } else {
+    int tiles = ((M + 127) / 128) * ((N + 127) / 128);
+    if (tiles > 4096) tiles = 4096;
+    hipLaunchKernelGGL((k_gemm_plain<128, 128>), dim3(tiles), dim3(kBlock), 0, st, M, N, K, A, lda, B, ldb, C, ldc);
+  }
 }
 
 void launch_final(const int64_t* prob_n, const int64_t* prob_vec, const int64_t* prob_mat,
