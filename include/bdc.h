@@ -45,8 +45,20 @@ enum {
   BDC_ERR_NOMEM = -1003,          /* workspace would exceed the cap, or hipMalloc failed */
   BDC_ERR_HIP = -1004,            /* a HIP runtime call failed */
   BDC_ERR_NONFINITE = -1005,      /* (info) d or e holds Inf or NaN */
-  BDC_ERR_UNSUPPORTED = -1006     /* option value not supported by this build */
+  BDC_ERR_UNSUPPORTED = -1006,    /* option value not supported by this build */
+  BDC_ERR_NO_MODEL = -1007        /* learned start requested before bdc_mlp_set */
 };
+
+/* Start of the secular iteration (options.start). */
+enum {
+  BDC_START_PLAIN = 0,  /* first evaluation at the interval's midpoint in omega^2 */
+  BDC_START_LEARNED = 1 /* first evaluation at the position proposed by the MLP */
+};
+
+/* Size of the learned-start network: 19 features -> 64 -> 64 -> 64 -> 1. */
+#define BDC_MLP_FEATURES 19
+#define BDC_MLP_HIDDEN 64
+#define BDC_MLP_PARAMS (19 * 64 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 + 1)
 
 /* Options; bdc_default_options fills the defaults. */
 typedef struct {
@@ -58,6 +70,9 @@ typedef struct {
                                  kernels one by one (no graph) */
   int use_graph;              /* 1 (default): capture a solve's launch sequence once per
                                  (sizes, buffers) as a HIP graph and replay it */
+  int start;                  /* BDC_START_PLAIN (default) or BDC_START_LEARNED (needs
+                                 bdc_mlp_set first; same stopping rule, only the
+                                 first point of each root's iteration changes) */
 } bdc_options_t;
 
 void bdc_default_options(bdc_options_t* opt);
@@ -169,6 +184,24 @@ int bdc_step_deflate(bdc_handle_t handle, int m, int s, const double* sig,
 int bdc_step_secular(bdc_handle_t handle, int N, const double* d, const double* z,
                      int32_t* o, double* tau, int32_t* iters, bdc_stream_t stream);
 
+/* As bdc_step_secular, with each root's iteration started from a proposed
+ * position xstart[i] in (0, 1) of its interval (device, N floats; NULL = the
+ * plain midpoint start).  Interval of root i: (d_i, d_{i+1}), the last root's
+ * (d_{N-1}, sqrt(d_{N-1}^2 + sum z^2)). */
+int bdc_step_secular_start(bdc_handle_t handle, int N, const double* d, const double* z,
+                           const float* xstart, int32_t* o, double* tau, int32_t* iters,
+                           bdc_stream_t stream);
+
+/* Features of the learned start for the secular problem (d, z) as above:
+ * X (device, N x BDC_MLP_FEATURES floats, row-major).  Feature layout: for the
+ * 4 poles at and below root i and the 4 above it, the gap (d_j - lo)/h and
+ * the strength log2(z_j^2/(hi^2 - lo^2))/32; then log2(rho/(hi^2 - lo^2))/32
+ * and the far field (the secular function without those 8 poles, summed
+ * term by term in nearby blocks and by one monopole per distant block) at
+ * the interval's midpoint: asinh(value)/8, asinh(slope (hi^2 - lo^2))/8. */
+int bdc_step_features(bdc_handle_t handle, int N, const double* d, const double* z, float* X,
+                      bdc_stream_t stream);
+
 /* Recomputed z (eq. bdc-zi) and the normalised singular vectors of
  * M~ = e_1 zt^T + diag(d) (eq. M-svd-vec), from d, z, o, tau as above.
  * Out: zt (N), UM and VM (N*N col-major, column i belongs to root i). */
@@ -180,6 +213,46 @@ int bdc_step_vectors(bdc_handle_t handle, int N, const double* d, const double* 
  * FP64 matrix-core kernel of the vector update (eq. bdc-Mv2Bv-u-vt). */
 int bdc_step_gemm(bdc_handle_t handle, int M, int N, int K, const double* A, int lda,
                   const double* B, int ldb, double* C, int ldc, bdc_stream_t stream);
+
+/* ---- learned start of the secular iteration ------------------------------
+ * The paper solves each secular equation with LAPACK's lasd4; this build
+ * adds an optional learned first point: a 19 -> 64 -> 64 -> 64 -> 1 MLP
+ * (GELU hidden layers, logistic output) maps the features above to the
+ * root's fractional position in its interval.  Its hidden-layer products run
+ * on bfloat16 matrix cores with FP32 accumulation: every product operand
+ * (inputs, weights, activations and, in training, back-propagated gradients)
+ * is rounded to bfloat16; everything else is FP32.  Parameters: one FP32
+ * vector of BDC_MLP_PARAMS numbers, W1 (19 x 64 row-major, in x out), b1
+ * (64), W2 (64 x 64), b2, W3 (64 x 64), b3, W4 (64), b4 (1).  The network is
+ * owned by the handle; training updates it in place. */
+
+/* Copy host parameters into the handle (synchronous); resets Adam's state. */
+int bdc_mlp_set(bdc_handle_t handle, const float* params, int64_t count);
+/* Copy the handle's parameters to the host (waits for the handle's stream). */
+int bdc_mlp_get(bdc_handle_t handle, float* params, int64_t count);
+/* xhat (device, rows floats) = network(X) for X (device, rows x 19). */
+int bdc_mlp_forward(bdc_handle_t handle, const float* X, int64_t rows, float* xhat,
+                    bdc_stream_t stream);
+/* Gradient (device, BDC_MLP_PARAMS floats) and, if loss != NULL, the loss
+ * (device, 1 float) of the mean squared error of network(X) against y
+ * (device, rows floats) over the rows; 1 <= rows <= 2^24. */
+int bdc_mlp_grad(bdc_handle_t handle, const float* X, const float* y, int64_t rows, float* grad,
+                 float* loss, bdc_stream_t stream);
+/* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr)
+ * on the mean squared error; step s uses rows idx[s*batch .. s*batch+batch)
+ * of (X, y) (device int32 row indices).  loss_hist (device, steps floats,
+ * may be NULL) receives each step's batch loss before its update. */
+int bdc_mlp_train(bdc_handle_t handle, const float* X, const float* y, const int32_t* idx,
+                  int64_t batch, int64_t steps, float lr, float* loss_hist, bdc_stream_t stream);
+/* Collect training rows from later solves on this handle: after each merge's
+ * secular solve, every root appends its features (X, rows x 19), the
+ * position of the computed root in its interval (y) and a tag (3 int32:
+ * problem offset + node's first row, node rows, root index).  The row counter
+ * *count (device, uint64; the caller zeroes it) is advanced by every root;
+ * rows past `capacity` are not written.  Solves run without graph replay
+ * while collecting.  X = NULL stops collecting. */
+int bdc_set_harvest(bdc_handle_t handle, float* X, float* y, int32_t* tag, int64_t capacity,
+                    unsigned long long* count);
 
 const char* bdc_status_string(int status);
 

@@ -32,3 +32,4 @@ from .bdc import (  # noqa: F401
 )
 from .leaf import leaf_svd  # noqa: F401
 from .secular import lowner_z, secular_roots, vectors  # noqa: F401
+from . import learned  # noqa: F401

@@ -28,6 +28,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .leaf import leaf_svd, dense_bidiagonal
+from .learned import learned_roots
 from .secular import secular_roots, lowner_z, vectors
 
 EPS = 2.0 ** -52
@@ -295,10 +296,19 @@ class MergeStats:
     n_close: int
     counts: tuple
     iters: np.ndarray
+    # the merge's secular problem and its roots (kept values ascending)
+    dS: np.ndarray | None = None
+    zS: np.ndarray | None = None
+    o: np.ndarray | None = None
+    tau: np.ndarray | None = None
 
 
-def merge(node: Node, left, right, d, e, stats: list | None = None):
-    """Conquer one node from its children's SVDs (Algorithm 2 step (2))."""
+def merge(node: Node, left, right, d, e, stats: list | None = None, start=None):
+    """Conquer one node from its children's SVDs (Algorithm 2 step (2)).
+
+    start: None for the plain secular start, else a callable (d, z) -> x_hat
+    proposing each root's position in its interval (learned start).
+    """
     sig1, W1, Q1 = left
     sig2, W2, Q2 = right
     r0, m, s, k = node.r0, node.m, node.s, node.k
@@ -341,7 +351,10 @@ def merge(node: Node, left, right, d, e, stats: list | None = None):
     surv = pr.survivors
     dS = pr.d[surv]
     zS = pr.z[surv]
-    o, tau, iters = secular_roots(dS, zS)
+    if start is None:
+        o, tau, iters = secular_roots(dS, zS)
+    else:
+        o, tau, iters = learned_roots(dS, zS, start(dS, zS))
     zt = lowner_z(dS, zS, o, tau)
     UM, VM = vectors(dS, zt, o, tau)
     omega = dS[o] + tau
@@ -369,11 +382,12 @@ def merge(node: Node, left, right, d, e, stats: list | None = None):
                                 n_small_z=int(np.sum(st == DEFL_SMALL_Z)),
                                 n_zero_d=int(np.sum(st == DEFL_ZERO_D)),
                                 n_close=int(np.sum(st == DEFL_CLOSE)),
-                                counts=pr.counts, iters=iters))
+                                counts=pr.counts, iters=iters,
+                                dS=dS, zS=zS, o=o, tau=tau))
     return sig, W, Q
 
 
-def solve_node(node: Node, d, e, stats=None):
+def solve_node(node: Node, d, e, stats=None, start=None):
     """SVD of the node's m x (m+s) block: (sigma asc, W, Q)."""
     if node.is_leaf:
         r0, m, s = node.r0, node.m, node.s
@@ -381,12 +395,12 @@ def solve_node(node: Node, d, e, stats=None):
         ee = e[r0:r0 + m - 1 + s]
         sig, W, Q, _ = leaf_svd(dd, ee, s)
         return sig, W, Q
-    left = solve_node(node.left, d, e, stats)
-    right = solve_node(node.right, d, e, stats)
-    return merge(node, left, right, d, e, stats)
+    left = solve_node(node.left, d, e, stats, start)
+    right = solve_node(node.right, d, e, stats, start)
+    return merge(node, left, right, d, e, stats, start)
 
 
-def bdsdc(d, e, leaf: int = LEAF_DEFAULT, return_stats: bool = False):
+def bdsdc(d, e, leaf: int = LEAF_DEFAULT, return_stats: bool = False, start=None):
     """B = U diag(sigma) VT for the n x n upper bidiagonal (d, e).
 
     Returns (sigma descending, U, VT[, stats]).  Algorithm 2 step (3): the
@@ -402,7 +416,7 @@ def bdsdc(d, e, leaf: int = LEAF_DEFAULT, return_stats: bool = False):
     ee = np.zeros(n)
     ee[:n - 1] = e[:n - 1]
     root = build_tree(n, leaf)
-    sig, W, Q = solve_node(root, d, ee, stats)
+    sig, W, Q = solve_node(root, d, ee, stats, start)
     sigma = sig[::-1].copy()
     U = W[:, ::-1].copy()
     VT = Q[:, ::-1].T.copy()

@@ -15,6 +15,11 @@ BDC_ERR_NOMEM = -1003
 BDC_ERR_HIP = -1004
 BDC_ERR_NONFINITE = -1005
 BDC_ERR_UNSUPPORTED = -1006
+BDC_ERR_NO_MODEL = -1007
+BDC_START_PLAIN = 0
+BDC_START_LEARNED = 1
+MLP_FEATURES = 19
+MLP_PARAMS = 19 * 64 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 + 1
 
 c_int = ctypes.c_int
 c_i64 = ctypes.c_int64
@@ -31,6 +36,7 @@ class Options(ctypes.Structure):
         ("workspace_cap_bytes", ctypes.c_size_t),
         ("timing", c_int),
         ("use_graph", c_int),
+        ("start", c_int),
     ]
 
 
@@ -72,6 +78,14 @@ SIGNATURES = {
     "bdc_step_secular": (c_int, [c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "bdc_step_vectors": (c_int, [c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "bdc_step_gemm": (c_int, [c_vp, c_int, c_int, c_int, c_vp, c_int, c_vp, c_int, c_vp, c_int, c_vp]),
+    "bdc_step_secular_start": (c_int, [c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "bdc_step_features": (c_int, [c_vp, c_int, c_vp, c_vp, c_vp, c_vp]),
+    "bdc_mlp_set": (c_int, [c_vp, c_vp, c_i64]),
+    "bdc_mlp_get": (c_int, [c_vp, c_vp, c_i64]),
+    "bdc_mlp_forward": (c_int, [c_vp, c_vp, c_i64, c_vp, c_vp]),
+    "bdc_mlp_grad": (c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
+    "bdc_mlp_train": (c_int, [c_vp, c_vp, c_vp, c_vp, c_i64, c_i64, ctypes.c_float, c_vp, c_vp]),
+    "bdc_set_harvest": (c_int, [c_vp, c_vp, c_vp, c_vp, c_i64, c_vp]),
     "bdc_status_string": (c_char_p, [c_int]),
 }
 

@@ -27,7 +27,10 @@ class Solver:
 
     def __init__(self, device: int | torch.device = 0, leaf_size: int = 32, max_secular_iters: int = 64,
                  max_leaf_sweeps: int = 40, workspace_cap_bytes: int = 0, timing: bool = False,
-                 use_graph: bool = True):
+                 use_graph: bool = True, start: str = "plain", mlp_params=None):
+        """start: "plain" (midpoint) or "learned" (the MLP's proposal; the
+        parameters come from ``mlp_params`` (host float32 vector) or, when
+        that is None, from the network file shipped with the package)."""
         self.lib = _lib.load()
         dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         if dev.type != "cuda":
@@ -41,9 +44,17 @@ class Solver:
         opt.workspace_cap_bytes = workspace_cap_bytes
         opt.timing = 1 if timing else 0
         opt.use_graph = 1 if use_graph else 0
+        if start not in ("plain", "learned"):
+            raise ValueError("start must be 'plain' or 'learned'")
+        opt.start = _lib.BDC_START_LEARNED if start == "learned" else _lib.BDC_START_PLAIN
         h = ctypes.c_void_p()
         check("bdc_create", self.lib.bdc_create(ctypes.byref(h), self.device.index, ctypes.byref(opt)))
         self.handle = h
+        if mlp_params is None and start == "learned":
+            from .start_model import load_params
+            mlp_params = load_params()
+        if mlp_params is not None:
+            self.mlp_set(mlp_params)
 
     def close(self) -> None:
         if self.handle:
@@ -120,6 +131,61 @@ class Solver:
     def clear_timing(self) -> None:
         check("bdc_clear_timing", self.lib.bdc_clear_timing(self.handle))
 
+    # ---------------------------------------------------------------- learned start
+    def mlp_set(self, params) -> None:
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if p.shape != (_lib.MLP_PARAMS,):
+            raise ValueError(f"expected {_lib.MLP_PARAMS} parameters")
+        check("bdc_mlp_set", self.lib.bdc_mlp_set(self.handle, p.ctypes.data, p.shape[0]))
+
+    def mlp_get(self):
+        import numpy as np
+        p = np.empty(_lib.MLP_PARAMS, dtype=np.float32)
+        check("bdc_mlp_get", self.lib.bdc_mlp_get(self.handle, p.ctypes.data, p.shape[0]))
+        return p
+
+    def mlp_forward(self, X: torch.Tensor) -> torch.Tensor:
+        X = torch.as_tensor(X, dtype=torch.float32, device=self.device).contiguous()
+        rows = X.shape[0]
+        out = torch.empty(rows, dtype=torch.float32, device=self.device)
+        check("bdc_mlp_forward", self.lib.bdc_mlp_forward(self.handle, _ptr(X), rows, _ptr(out), self._stream()))
+        return out
+
+    def mlp_grad(self, X, y):
+        X = torch.as_tensor(X, dtype=torch.float32, device=self.device).contiguous()
+        y = torch.as_tensor(y, dtype=torch.float32, device=self.device).contiguous()
+        g = torch.empty(_lib.MLP_PARAMS, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        check("bdc_mlp_grad", self.lib.bdc_mlp_grad(self.handle, _ptr(X), _ptr(y), X.shape[0], _ptr(g), _ptr(loss),
+                                                    self._stream()))
+        return float(loss.item()), g
+
+    def mlp_train(self, X: torch.Tensor, y: torch.Tensor, idx: torch.Tensor, batch: int, lr: float):
+        """len(idx) // batch Adam steps over rows idx (device int32);
+        returns the per-step batch losses (device tensor)."""
+        steps = idx.shape[0] // batch
+        hist = torch.empty(max(steps, 1), dtype=torch.float32, device=self.device)
+        check("bdc_mlp_train", self.lib.bdc_mlp_train(self.handle, _ptr(X), _ptr(y), _ptr(idx), batch, steps,
+                                                      float(lr), _ptr(hist), self._stream()))
+        return hist[:steps]
+
+    def harvest(self, capacity: int):
+        """Start collecting training rows from later solves; returns
+        (X, y, tag, count) device buffers (count: rows seen so far)."""
+        X = torch.empty((capacity, _lib.MLP_FEATURES), dtype=torch.float32, device=self.device)
+        y = torch.empty(capacity, dtype=torch.float32, device=self.device)
+        tag = torch.empty((capacity, 3), dtype=torch.int32, device=self.device)
+        count = torch.zeros(1, dtype=torch.int64, device=self.device)
+        check("bdc_set_harvest", self.lib.bdc_set_harvest(self.handle, _ptr(X), _ptr(y), _ptr(tag), capacity,
+                                                          _ptr(count)))
+        self._harvest = (X, y, tag, count)
+        return self._harvest
+
+    def stop_harvest(self) -> None:
+        check("bdc_set_harvest", self.lib.bdc_set_harvest(self.handle, None, None, None, 0, None))
+        self._harvest = None
+
     # ---------------------------------------------------------------- steps
     def step_leaf(self, d, e, s: int):
         d = _f64(d, self.device)
@@ -166,6 +232,27 @@ class Solver:
         check("bdc_step_secular", self.lib.bdc_step_secular(self.handle, N, _ptr(d), _ptr(z), _ptr(o), _ptr(tau),
                                                             _ptr(it), self._stream()))
         return o, tau, it
+
+    def step_secular_start(self, d, z, xstart):
+        d = _f64(d, self.device)
+        z = _f64(z, self.device)
+        xs = torch.as_tensor(xstart, dtype=torch.float32, device=self.device).contiguous()
+        N = d.shape[0]
+        o = torch.empty(N, dtype=torch.int32, device=self.device)
+        tau = torch.empty(N, dtype=torch.float64, device=self.device)
+        it = torch.empty(N, dtype=torch.int32, device=self.device)
+        check("bdc_step_secular_start", self.lib.bdc_step_secular_start(
+            self.handle, N, _ptr(d), _ptr(z), _ptr(xs), _ptr(o), _ptr(tau), _ptr(it), self._stream()))
+        return o, tau, it
+
+    def step_features(self, d, z):
+        d = _f64(d, self.device)
+        z = _f64(z, self.device)
+        N = d.shape[0]
+        X = torch.empty((N, _lib.MLP_FEATURES), dtype=torch.float32, device=self.device)
+        check("bdc_step_features", self.lib.bdc_step_features(self.handle, N, _ptr(d), _ptr(z), _ptr(X),
+                                                              self._stream()))
+        return X
 
     def step_vectors(self, d, z, o, tau):
         d = _f64(d, self.device)

@@ -23,6 +23,7 @@ SOURCES = {
     "k_deflate.hip": ["-ffp-contract=off"],
     "k_secular.hip": [],
     "k_update.hip": [],
+    "k_mlp.hip": [],
     "api.cpp": [],
     "api_steps.cpp": [],
 }

@@ -26,8 +26,10 @@ namespace {
 
 constexpr uint32_t kMagic = 0xBDC05EEDu;
 
-enum Kind { kReset = 0, kLeaf, kPrep, kRotate, kGather, kSecular, kLowner, kVectors, kOrder, kUpdate, kFinal, kKinds };
-const char* kKindNames[kKinds] = {"reset", "leaf", "deflate", "rotate", "gather", "secular",
+enum Kind {
+  kReset = 0, kLeaf, kPrep, kRotate, kGather, kStart, kSecular, kLowner, kVectors, kOrder, kUpdate, kFinal, kKinds
+};
+const char* kKindNames[kKinds] = {"reset", "leaf", "deflate", "rotate", "gather", "start", "secular",
                                   "lowner", "vectors", "order", "update_gemm", "final"};
 
 struct Level {
@@ -80,6 +82,14 @@ struct bdc_handle_s {
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
+  // learned start: FP32 parameters and Adam moments (one allocation), the
+  // per-workgroup gradient partials of a training step, and harvest buffers
+  float* mlp = nullptr;  // params | m | v
+  int adam_t = 0;
+  float* part = nullptr;  // parts x params | parts losses
+  int part_cap = 0;
+  Harvest hv{};
+  bool harvest = false;
 };
 
 namespace {
@@ -217,8 +227,8 @@ int ensure_workspace(bdc_handle_t h, int64_t tn, int64_t tn2, int nnodes) {
   const size_t N1 = (size_t)std::max<int64_t>(tn, 1), N2 = (size_t)std::max<int64_t>(tn2, 1);
   const size_t nd_ = (size_t)std::max(nnodes, 1);
   size_t bytes = 4 * align_up(N2 * 8) + 8 * align_up(N1 * 8) + align_up(2 * N1 * 8) +
-                 19 * align_up(N1 * 4) + 2 * align_up(2 * N1 * 4) + align_up(nd_ * sizeof(NodeState)) +
-                 align_up(sizeof(Ctl));
+                 19 * align_up(N1 * 4) + 2 * align_up(2 * N1 * 4) + align_up(N1 * 4) +
+                 align_up(nd_ * sizeof(NodeState)) + align_up(sizeof(Ctl));
   if (h->opt.workspace_cap_bytes && bytes > h->opt.workspace_cap_bytes) return BDC_ERR_NOMEM;
   if (h->arena) {
     if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
@@ -275,6 +285,7 @@ int ensure_workspace(bdc_handle_t h, int64_t tn, int64_t tn2, int nnodes) {
   w.iters = (int32_t*)take(N1 * 4);
   w.rot_pos = (int32_t*)take(2 * N1 * 4);
   w.rot_col = (int32_t*)take(2 * N1 * 4);
+  w.xs = (float*)take(N1 * 4);
   w.st = (NodeState*)take(nd_ * sizeof(NodeState));
   w.ctl = (Ctl*)take(sizeof(Ctl));
   h->cap_n = tn;
@@ -324,6 +335,8 @@ int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, do
   w.GV = VT;
   w.max_secular_iters = h->opt.max_secular_iters;
   w.max_leaf_sweeps = h->opt.max_leaf_sweeps;
+  const bool learned = h->opt.start == BDC_START_LEARNED;
+  if (!learned) w.xs = nullptr;
   {
     Timer t(h, st, kReset);
     launch_reset(w.ctl, w.st, p.nnodes, st);
@@ -336,7 +349,12 @@ int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, do
     { Timer t(h, st, kPrep); launch_prep(L.dev, L.nnodes, L.max_m, w, st); }
     { Timer t(h, st, kRotate); launch_rotate(L.dev, L.nnodes, L.max_m, w, st); }
     { Timer t(h, st, kGather); launch_gather(L.dev, L.nnodes, L.max_m, w, st); }
+    if (learned) {
+      Timer t(h, st, kStart);
+      launch_start(L.dev, L.nnodes, L.max_m, w, h->mlp, st);
+    }
     { Timer t(h, st, kSecular); launch_secular(L.dev, L.nnodes, L.max_m, w, st); }
+    if (h->harvest) launch_harvest(L.dev, L.nnodes, L.max_m, w, h->hv, st);
     { Timer t(h, st, kLowner); launch_lowner(L.dev, L.nnodes, L.max_m, w, st); }
     { Timer t(h, st, kVectors); launch_vectors(L.dev, L.nnodes, L.max_m, w, st); }
     { Timer t(h, st, kOrder); launch_order(L.dev, L.nnodes, L.max_m, w, st); }
@@ -358,6 +376,7 @@ int solve(bdc_handle_t h, int64_t batch, const int64_t* sizes, const double* d, 
           double* sigma, double* U, double* VT, hipStream_t st) {
   DeviceGuard g(h->device);
   if (!g.ok) return BDC_ERR_HIP;
+  if (h->opt.start == BDC_START_LEARNED && !h->mlp) return BDC_ERR_NO_MODEL;
   int rc = make_plan(h, sizes, batch);
   if (rc != BDC_OK) return rc;
   rc = ensure_workspace(h, h->plan.total_n, h->plan.total_n2, h->plan.nnodes);
@@ -368,7 +387,7 @@ int solve(bdc_handle_t h, int64_t batch, const int64_t* sizes, const double* d, 
     launch_reset(h->w.ctl, h->w.st, 0, st);
     return hipGetLastError() == hipSuccess ? BDC_OK : BDC_ERR_HIP;
   }
-  if (h->opt.timing || !h->opt.use_graph) return run_plan(h, d, e, sigma, U, VT, st);
+  if (h->opt.timing || !h->opt.use_graph || h->harvest) return run_plan(h, d, e, sigma, U, VT, st);
   // replay the captured sequence when the plan and the buffers are the same
   const void* key[5] = {d, e, sigma, U, VT};
   bool same = h->gexec != nullptr;
@@ -421,6 +440,7 @@ void bdc_default_options(bdc_options_t* opt) {
   opt->workspace_cap_bytes = 0;
   opt->timing = 0;
   opt->use_graph = 1;
+  opt->start = BDC_START_PLAIN;
 }
 
 int bdc_create(bdc_handle_t* handle, int device, const bdc_options_t* opt) {
@@ -432,6 +452,7 @@ int bdc_create(bdc_handle_t* handle, int device, const bdc_options_t* opt) {
   if (o.leaf_size < 4 || o.leaf_size > kMaxLeaf) return -3;
   if (o.max_secular_iters < 2 || o.max_secular_iters > 64) return -3;
   if (o.max_leaf_sweeps < 1 || o.max_leaf_sweeps > 1000) return -3;
+  if (o.start != BDC_START_PLAIN && o.start != BDC_START_LEARNED) return -3;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return BDC_ERR_NO_DEVICE;
   if (device < 0 || device >= count) return BDC_ERR_NO_DEVICE;
@@ -452,6 +473,8 @@ int bdc_destroy(bdc_handle_t h) {
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     free_plan(h->plan);
     if (h->arena) (void)hipFree(h->arena);
+    if (h->mlp) (void)hipFree(h->mlp);
+    if (h->part) (void)hipFree(h->part);
     for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
   }
   h->magic = 0;
@@ -578,6 +601,135 @@ int bdc_clear_timing(bdc_handle_t h) {
   return BDC_OK;
 }
 
+// ---- learned start ---------------------------------------------------------
+
+int bdc_mlp_set(bdc_handle_t h, const float* params, int64_t count) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  if (!params) return -2;
+  if (count != BDC_MLP_PARAMS) return -3;
+  DeviceGuard g(h->device);
+  if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
+  if (!h->mlp && hipMalloc(&h->mlp, sizeof(float) * 3 * BDC_MLP_PARAMS) != hipSuccess) {
+    h->mlp = nullptr;
+    return BDC_ERR_NOMEM;
+  }
+  if (hipMemcpy(h->mlp, params, sizeof(float) * BDC_MLP_PARAMS, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(h->mlp + BDC_MLP_PARAMS, 0, sizeof(float) * 2 * BDC_MLP_PARAMS) != hipSuccess)
+    return BDC_ERR_HIP;
+  h->adam_t = 0;
+  return BDC_OK;
+}
+
+int bdc_mlp_get(bdc_handle_t h, float* params, int64_t count) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  if (!params) return -2;
+  if (count != BDC_MLP_PARAMS) return -3;
+  if (!h->mlp) return BDC_ERR_NO_MODEL;
+  DeviceGuard g(h->device);
+  if (h->have_call && hipStreamSynchronize(h->last_stream) != hipSuccess) return BDC_ERR_HIP;
+  if (hipMemcpy(params, h->mlp, sizeof(float) * BDC_MLP_PARAMS, hipMemcpyDeviceToHost) != hipSuccess)
+    return BDC_ERR_HIP;
+  return BDC_OK;
+}
+
+int bdc_mlp_forward(bdc_handle_t h, const float* X, int64_t rows, float* xhat, bdc_stream_t stream) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  if (rows < 0 || rows > (int64_t)INT32_MAX - 64) return -3;
+  if (rows > 0 && !X) return -2;
+  if (rows > 0 && !xhat) return -4;
+  if (!h->mlp) return BDC_ERR_NO_MODEL;
+  DeviceGuard g(h->device);
+  launch_mlp_forward(h->mlp, X, (int)rows, xhat, (hipStream_t)stream);
+  if (hipGetLastError() != hipSuccess) return BDC_ERR_HIP;
+  h->last_stream = (hipStream_t)stream;
+  h->have_call = true;
+  return BDC_OK;
+}
+
+namespace {
+int ensure_parts(bdc_handle_t h, int rows) {
+  const int parts = mlp_parts(rows);
+  if (parts <= h->part_cap) return BDC_OK;
+  if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
+  if (h->part) (void)hipFree(h->part);
+  h->part = nullptr;
+  h->part_cap = 0;
+  if (hipMalloc(&h->part, sizeof(float) * (size_t)parts * (BDC_MLP_PARAMS + 1)) != hipSuccess) {
+    h->part = nullptr;
+    return BDC_ERR_NOMEM;
+  }
+  h->part_cap = parts;
+  return BDC_OK;
+}
+}  // namespace
+
+int bdc_mlp_grad(bdc_handle_t h, const float* X, const float* y, int64_t rows, float* grad, float* loss,
+                 bdc_stream_t stream) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  if (!X) return -2;
+  if (!y) return -3;
+  if (rows < 1 || rows > (int64_t)1 << 24) return -4;
+  if (!grad) return -5;
+  if (!h->mlp) return BDC_ERR_NO_MODEL;
+  DeviceGuard g(h->device);
+  int rc = ensure_parts(h, (int)rows);
+  if (rc != BDC_OK) return rc;
+  const int parts = mlp_parts((int)rows);
+  float* part_loss = h->part + (size_t)h->part_cap * BDC_MLP_PARAMS;
+  hipStream_t st = (hipStream_t)stream;
+  launch_mlp_grad(h->mlp, X, y, nullptr, (int)rows, h->part, part_loss, st);
+  launch_adam(h->mlp, h->mlp + BDC_MLP_PARAMS, h->mlp + 2 * BDC_MLP_PARAMS, h->part, parts, part_loss, grad, loss,
+              0, 0.0f, 1.0f / (float)rows, st);
+  if (hipGetLastError() != hipSuccess) return BDC_ERR_HIP;
+  h->last_stream = st;
+  h->have_call = true;
+  return BDC_OK;
+}
+
+int bdc_mlp_train(bdc_handle_t h, const float* X, const float* y, const int32_t* idx, int64_t batch,
+                  int64_t steps, float lr, float* loss_hist, bdc_stream_t stream) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  if (!X) return -2;
+  if (!y) return -3;
+  if (!idx) return -4;
+  if (batch < 1 || batch > (int64_t)1 << 24) return -5;
+  if (steps < 0 || steps > (int64_t)1 << 30) return -6;
+  if (!(lr > 0.0f) || !(lr < 1.0f)) return -7;
+  if (!h->mlp) return BDC_ERR_NO_MODEL;
+  DeviceGuard g(h->device);
+  int rc = ensure_parts(h, (int)batch);
+  if (rc != BDC_OK) return rc;
+  const int parts = mlp_parts((int)batch);
+  float* part_loss = h->part + (size_t)h->part_cap * BDC_MLP_PARAMS;
+  hipStream_t st = (hipStream_t)stream;
+  for (int64_t s = 0; s < steps; ++s) {
+    launch_mlp_grad(h->mlp, X, y, idx + s * batch, (int)batch, h->part, part_loss, st);
+    launch_adam(h->mlp, h->mlp + BDC_MLP_PARAMS, h->mlp + 2 * BDC_MLP_PARAMS, h->part, parts, part_loss, nullptr,
+                loss_hist ? loss_hist + s : nullptr, ++h->adam_t, lr, 1.0f / (float)batch, st);
+  }
+  if (hipGetLastError() != hipSuccess) return BDC_ERR_HIP;
+  h->last_stream = st;
+  h->have_call = true;
+  return BDC_OK;
+}
+
+int bdc_set_harvest(bdc_handle_t h, float* X, float* y, int32_t* tag, int64_t capacity,
+                    unsigned long long* count) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  if (!X) {
+    h->harvest = false;
+    h->hv = Harvest{};
+    return BDC_OK;
+  }
+  if (!y) return -3;
+  if (!tag) return -4;
+  if (capacity < 0) return -5;
+  if (!count) return -6;
+  h->hv = Harvest{X, y, tag, capacity, count};
+  h->harvest = true;
+  return BDC_OK;
+}
+
 const char* bdc_status_string(int status) {
   switch (status) {
     case BDC_OK: return "ok";
@@ -587,6 +739,7 @@ const char* bdc_status_string(int status) {
     case BDC_ERR_HIP: return "HIP runtime error";
     case BDC_ERR_NONFINITE: return "input holds Inf or NaN";
     case BDC_ERR_UNSUPPORTED: return "unsupported option";
+    case BDC_ERR_NO_MODEL: return "learned start selected but no network parameters were set";
     default: return status < 0 ? "invalid argument" : "iteration caps reached";
   }
 }

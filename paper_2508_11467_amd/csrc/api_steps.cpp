@@ -213,16 +213,16 @@ int bdc_step_deflate(bdc_handle_t h, int m, int s, const double* sig, const doub
   return BDC_OK;
 }
 
-int bdc_step_secular(bdc_handle_t h, int N, const double* d, const double* z, int32_t* o, double* tau,
-                     int32_t* iters, bdc_stream_t stream) {
+int bdc_step_secular_start(bdc_handle_t h, int N, const double* d, const double* z, const float* xstart,
+                           int32_t* o, double* tau, int32_t* iters, bdc_stream_t stream) {
   int dev, msi, mls;
   if (bdc::handle_info(h, &dev, &msi, &mls) != BDC_OK) return BDC_ERR_INVALID_HANDLE;
   if (N < 1) return -2;
   if (!d) return -3;
   if (!z) return -4;
-  if (!o) return -5;
-  if (!tau) return -6;
-  if (!iters) return -7;
+  if (!o) return -6;
+  if (!tau) return -7;
+  if (!iters) return -8;
   Guard g(dev);
   hipStream_t st = (hipStream_t)stream;
   Tmp t;
@@ -236,6 +236,7 @@ int bdc_step_secular(bdc_handle_t h, int N, const double* d, const double* z, in
   w.o = o;
   w.tau = tau;
   w.iters = iters;
+  w.xs = const_cast<float*>(xstart);  // read only by the secular kernel
   w.max_secular_iters = msi;
   std::vector<double> zh(N);
   if (hipMemcpy(zh.data(), z, sizeof(double) * N, hipMemcpyDeviceToHost) != hipSuccess) return BDC_ERR_HIP;
@@ -252,6 +253,25 @@ int bdc_step_secular(bdc_handle_t h, int N, const double* d, const double* z, in
     return BDC_ERR_HIP;
   launch_reset(w.ctl, w.st, 1, st);
   launch_secular(nd_dev, 1, N, w, st);
+  return finish(st);
+}
+
+int bdc_step_secular(bdc_handle_t h, int N, const double* d, const double* z, int32_t* o, double* tau,
+                     int32_t* iters, bdc_stream_t stream) {
+  const int rc = bdc_step_secular_start(h, N, d, z, nullptr, o, tau, iters, stream);
+  return rc <= -6 && rc >= -8 ? rc + 1 : rc;  // argument positions of this signature
+}
+
+int bdc_step_features(bdc_handle_t h, int N, const double* d, const double* z, float* X, bdc_stream_t stream) {
+  int dev, msi, mls;
+  if (bdc::handle_info(h, &dev, &msi, &mls) != BDC_OK) return BDC_ERR_INVALID_HANDLE;
+  if (N < 1) return -2;
+  if (!d) return -3;
+  if (!z) return -4;
+  if (!X) return -5;
+  Guard g(dev);
+  hipStream_t st = (hipStream_t)stream;
+  launch_features(d, z, N, X, st);
   return finish(st);
 }
 

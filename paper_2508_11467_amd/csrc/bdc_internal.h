@@ -110,10 +110,21 @@ struct Work {
   int32_t* rot_pos;  // rotations: sorted positions (2 per rotation)
   int32_t* rot_col;  //   physical columns (2 per rotation)
   double* rot_cs;    //   (c, s)
+  float* xs;         // proposed start of each root in its interval (learned
+                     // start), nullptr for the plain start
   NodeState* st;
   Ctl* ctl;
   int max_secular_iters;
   int max_leaf_sweeps;
+};
+
+// Caller buffers that collect training rows of the learned start.
+struct Harvest {
+  float* X;          // rows x BDC_MLP_FEATURES
+  float* y;          // position of the computed root in its interval
+  int32_t* tag;      // rows x 3: (problem offset + node r0, node m, root index)
+  int64_t capacity;  // rows that fit; later rows are counted, not written
+  unsigned long long* count;
 };
 
 // ---- launchers (defined next to their kernels) ----
@@ -133,6 +144,18 @@ void launch_final(const int64_t* prob_n, const int64_t* prob_vec, const int64_t*
                   hipStream_t st);
 // device and iteration options of a handle (BDC_OK or BDC_ERR_INVALID_HANDLE)
 int handle_info(bdc_handle_t h, int* device, int* max_secular_iters, int* max_leaf_sweeps);
+
+void launch_start(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, const float* params,
+                  hipStream_t st);
+void launch_harvest(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, const Harvest& hv,
+                    hipStream_t st);
+void launch_features(const double* d, const double* z, int N, float* X, hipStream_t st);
+void launch_mlp_forward(const float* params, const float* X, int rows, float* xhat, hipStream_t st);
+int mlp_parts(int rows);
+void launch_mlp_grad(const float* params, const float* X, const float* y, const int32_t* idx, int rows,
+                     float* part, float* part_loss, hipStream_t st);
+void launch_adam(float* params, float* m, float* v, const float* part, int nparts, const float* part_loss,
+                 float* grad_out, float* loss_out, int adam_t, float lr, float inv_rows, hipStream_t st);
 
 void launch_gemm_plain(int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                        double* C, int ldc, hipStream_t st);

@@ -3,7 +3,11 @@
 //   k_secular  roots of the secular equation (eq. M-svd-val), one lane per
 //              root.  The paper solves them on CPU threads with LAPACK's
 //              lasd4; here each root is bracketed, its origin pole chosen by
-//              the sign of f at the interval midpoint (in omega^2), and the
+//              the sign of f at the interval midpoint (in omega^2) -- or,
+//              with the learned start, by the half of the interval holding
+//              the proposed position, where the first evaluation is made and
+//              from which an iterate that crosses the midpoint is moved to
+//              the other pole's frame -- and the
 //              iteration uses R.-C. Li's two-pole "middle way" rational model
 //              matched in value and slope, with bisection whenever a step
 //              leaves the bracket.  A root is stored as omega = d[o] + tau so
@@ -99,6 +103,7 @@ __global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ no
   const double* __restrict__ d = w.sd + vo;
   const double* __restrict__ z = w.sz + vo;
   const int maxit = w.max_secular_iters;
+  const bool learned = w.xs != nullptr;
   const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
   // this wavefront's quarter of the poles
   const int Q = (N + kSecWaves - 1) / kSecWaves;
@@ -117,7 +122,7 @@ __global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ no
     const bool last = (i == N - 1);
     const int lp = active ? (last ? N - 2 : i) : 0;  // left model pole
     const int rp = lp + 1;
-    double dl = 0.0, dr = 0.0, ov = 0.0, tau = 0.0, lo = 0.0, hi = 0.0, mu = 0.0, base_v = 0.0;
+    double dl = 0.0, dr = 0.0, ov = 0.0, tau = 0.0, lo = 0.0, hi = 0.0, mu = 0.0, base_v = 0.0, h = 0.0;
     int o = 0, iters = 0, capped = 0;
     bool need = active && N > 1;
     bool first = true;
@@ -125,11 +130,41 @@ __global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ no
     if (need) {
       dl = d[lp];
       dr = d[rp];
-      // first evaluation: the midpoint in omega^2 of the root's interval
-      base_v = last ? dr : dl;
-      mu = last ? 0.5 * rho : 0.5 * (dr - dl) * (dr + dl);
-      ov = base_v;
-      tau = mu / (base_v + sqrt(base_v * base_v + mu));
+      if (learned) {
+        // first evaluation at the proposed position x of the interval; its
+        // half (split at the midpoint in omega^2) gives the origin pole
+        const double x = fmin(fmax((double)w.xs[vo + i], 0x1p-20), 1.0 - 0x1p-20);
+        first = false;
+        if (last) {
+          h = rho / (dr + sqrt(dr * dr + rho));
+          o = rp;
+          tau = x * h;
+          lo = 0.0;
+          hi = h;
+        } else {
+          h = dr - dl;
+          mu = 0.5 * (dr - dl) * (dr + dl);
+          const double t0 = x * h;
+          if (t0 * (2.0 * dl + t0) > mu) {
+            o = rp;
+            tau = (x - 1.0) * h;
+            lo = -h;
+            hi = 0.0;
+          } else {
+            o = lp;
+            tau = t0;
+            lo = 0.0;
+            hi = h;
+          }
+        }
+        ov = d[o];
+      } else {
+        // first evaluation: the midpoint in omega^2 of the root's interval
+        base_v = last ? dr : dl;
+        mu = last ? 0.5 * rho : 0.5 * (dr - dl) * (dr + dl);
+        ov = base_v;
+        tau = mu / (base_v + sqrt(base_v * base_v + mu));
+      }
     }
     for (;;) {
       if (wv == 0) {
@@ -245,6 +280,25 @@ __global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ no
           // a step at the rounding level is accepted without another evaluation
           if (fabs(tn - tau) <= 2.0 * kEps * fabs(tn)) conv = true;
           tau = tn;
+          if (learned && !last) {
+            // an iterate that crossed the midpoint is re-referenced to the
+            // other pole and evaluated there before it may stop
+            if (o == lp && tau * (2.0 * dl + tau) > mu) {
+              o = rp;
+              ov = dr;
+              tau -= h;
+              lo -= h;
+              hi -= h;
+              conv = false;
+            } else if (o == rp && tau * (2.0 * dr + tau) < -mu) {
+              o = lp;
+              ov = dl;
+              tau += h;
+              lo += h;
+              hi += h;
+              conv = false;
+            }
+          }
         }
         if (!conv && iters >= maxit) capped = 1;
         need = !conv && iters < maxit;

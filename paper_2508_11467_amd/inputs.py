@@ -25,6 +25,14 @@ def seed_for(config: int, spectrum: int = 0) -> int:
     return BASE_SEED + 100 * config + spectrum
 
 
+def split_seed(config: int, spectrum: int, split: str, k: int) -> int:
+    """Seed of the k-th problem of a training ("train") or held-out ("valid")
+    set drawn like a configuration; never equal to a configuration's own
+    seed."""
+    base = {"train": 1_000_000, "valid": 500_000_000}[split]
+    return BASE_SEED + 100 * config + spectrum + base * (k + 1)
+
+
 def _rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 

@@ -1,0 +1,262 @@
+"""Learned secular start on the GPU against the oracle: features, the BF16
+network's forward pass and gradient, the Adam step, the secular iteration
+from a proposed start, harvested training rows, and whole solves."""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import learned as L
+from paper_2508_11467_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def solver(gpu):
+    from paper_2508_11467_amd.api import Solver
+    s = Solver(0)
+    yield s
+    s.close()
+
+
+def _problem(g, N, spread="uniform"):
+    if spread == "uniform":
+        dd = np.sort(g.uniform(0.0, 1.0, N - 1))
+    else:
+        dd = np.sort(10.0 ** g.uniform(-6, 0, N - 1))
+    d = np.concatenate([[0.0], dd])
+    z = g.standard_normal(N) * 10.0 ** g.uniform(-3, 0, N)
+    return d, z
+
+
+@pytest.mark.parametrize("N,spread", [(1, "uniform"), (2, "uniform"), (9, "graded"), (100, "uniform"),
+                                      (700, "graded"), (3000, "uniform")])
+def test_features_match_oracle(solver, N, spread):
+    g = np.random.default_rng(N)
+    d, z = _problem(g, N, spread)
+    X = solver.step_features(d, z).cpu().numpy()
+    ref = L.features(d, z)
+    # FP64 on both sides, then rounded to FP32 on the GPU
+    assert np.max(np.abs(X - ref)) <= 1e-6 * (1.0 + np.max(np.abs(ref)))
+
+
+def _bf16_tolerances(x_gpu, x_ref):
+    d = np.abs(x_gpu - x_ref)
+    return float(np.max(d)), float(np.mean(d))
+
+
+def test_forward_matches_oracle(solver):
+    """Same rounding points as the oracle's bfloat16 mode; a value that lands
+    on a bfloat16 rounding boundary may round the other way after FP32 vs FP64
+    arithmetic, which moves the output by about one bfloat16 unit of one
+    activation."""
+    g = np.random.default_rng(3)
+    p = L.mlp_init(4) + 0.02 * g.standard_normal(L.NPARAMS)
+    p32 = p.astype(np.float32)
+    X = g.uniform(-2, 2, (1000, L.NFEAT)).astype(np.float32)
+    solver.mlp_set(p32)
+    xg = solver.mlp_forward(X).cpu().numpy().astype(np.float64)
+    ref16, _ = L.mlp_forward(p32.astype(np.float64), X.astype(np.float64), "bf16")
+    ref64, _ = L.mlp_forward(p32.astype(np.float64), X.astype(np.float64), "f64")
+    mx, mean = _bf16_tolerances(xg, ref16)
+    assert mx <= 2e-3 and mean <= 1e-4, (mx, mean)
+    assert np.max(np.abs(xg - ref64)) <= 0.05
+
+
+def test_gradient_matches_oracle(solver):
+    g = np.random.default_rng(5)
+    p = (L.mlp_init(6) + 0.02 * g.standard_normal(L.NPARAMS)).astype(np.float32)
+    X = g.uniform(-2, 2, (777, L.NFEAT)).astype(np.float32)   # 13 workgroups, ragged last
+    y = g.uniform(0, 1, 777).astype(np.float32)
+    solver.mlp_set(p)
+    loss, grad = solver.mlp_grad(X, y)
+    grad = grad.cpu().numpy().astype(np.float64)
+    l16, g16 = L.mlp_loss_grad(p.astype(np.float64), X.astype(np.float64), y.astype(np.float64), "bf16")
+    l64, g64 = L.mlp_loss_grad(p.astype(np.float64), X.astype(np.float64), y.astype(np.float64), "f64")
+    assert abs(loss - l16) <= 1e-3 * l16
+    # bfloat16 gradient operands: a few units of 2^-9 per back-propagated layer
+    assert np.linalg.norm(grad - g16) <= 1e-2 * np.linalg.norm(g16)
+    assert np.linalg.norm(grad - g64) <= 5e-2 * np.linalg.norm(g64)
+    # every parameter block receives a gradient of the right size
+    for a, b in [(0, 1216), (1216, 1280), (1280, 5376), (5376, 5440), (5440, 9536), (9536, 9600),
+                 (9600, 9664), (9664, 9665)]:
+        assert np.linalg.norm(grad[a:b] - g16[a:b]) <= 3e-2 * np.linalg.norm(g16[a:b]) + 1e-7
+
+
+def test_adam_step(solver):
+    """One training step equals Adam's update computed on the host from the
+    GPU's own gradient."""
+    import torch
+    g = np.random.default_rng(7)
+    p = (L.mlp_init(8)).astype(np.float32)
+    X = g.uniform(-2, 2, (256, L.NFEAT)).astype(np.float32)
+    y = g.uniform(0, 1, 256).astype(np.float32)
+    solver.mlp_set(p)
+    _, grad = solver.mlp_grad(X, y)
+    grad = grad.cpu().numpy()
+    Xt = torch.from_numpy(X).cuda()
+    yt = torch.from_numpy(y).cuda()
+    idx = torch.arange(256, dtype=torch.int32, device="cuda")
+    lr = 1e-3
+    solver.mlp_train(Xt, yt, idx, 256, lr)
+    p1 = solver.mlp_get()
+    m = 0.1 * grad
+    v = 0.001 * grad * grad
+    mh = m / (1 - 0.9)
+    vh = v / (1 - 0.999)
+    ref = p - lr * mh / (np.sqrt(vh) + 1e-8)
+    assert np.max(np.abs(p1 - ref)) <= 1e-6 + 1e-5 * np.max(np.abs(lr * mh / (np.sqrt(vh) + 1e-8)))
+
+
+def test_training_lowers_the_loss(solver):
+    import torch
+    from paper_2508_11467_amd.start_model import init_params
+    X, y, tag, count = solver.harvest(60000)
+    for k in range(30):
+        d, e = inputs.uniform(256, inputs.split_seed(1, 0, "valid", 900 + k))
+        solver.svd(d, e)
+    solver.stop_harvest()
+    rows = int(count.item())
+    assert 5000 < rows <= 60000
+    X, y = X[:rows], y[:rows]
+    solver.mlp_set(init_params(1))
+    l0, _ = solver.mlp_grad(X, y)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    for ep in range(20):
+        idx = torch.randperm(rows, generator=gen, device="cuda").to(torch.int32)
+        solver.mlp_train(X, y, idx[: (rows // 512) * 512], 512, 2e-3)
+    l1, _ = solver.mlp_grad(X, y)
+    assert l1 < 0.5 * l0, (l0, l1)
+
+
+@pytest.mark.parametrize("how", ["labels", "random", "ends"])
+def test_learned_secular_matches_oracle(solver, how):
+    g = np.random.default_rng(17)
+    for N, spread in [(2, "uniform"), (33, "graded"), (300, "uniform"), (1000, "graded")]:
+        d, z = _problem(g, N, spread)
+        o0, t0, _ = oracle.secular_roots(d, z)
+        x = {"labels": lambda: L.labels(d, z, o0, t0), "random": lambda: g.uniform(0, 1, N),
+             "ends": lambda: (g.uniform(0, 1, N) < 0.5).astype(np.float64)}[how]()
+        x = x.astype(np.float32)
+        o, tau, it = [a.cpu().numpy() for a in solver.step_secular_start(d, z, x)]
+        oo, to, io = L.learned_roots(d, z, x.astype(np.float64))
+        same = o == oo
+        assert np.mean(same) >= 0.98
+        # the same root to the stopping tolerance, tau relative to its pole
+        assert np.all(np.abs(tau[same] - to[same]) <= 1e-12 * np.abs(to[same]))
+        om, omo = d[o] + tau, d[oo] + to
+        assert np.max(np.abs(om - omo)) <= 1e-14 * omo[-1]
+        # summation order differs (four partial sums on the GPU), so an
+        # evaluation count may differ by one now and then
+        assert np.mean(np.abs(it - io)) <= 0.1 and np.max(np.abs(it - io)) <= 2
+
+
+def test_harvest_matches_oracle(solver):
+    """Rows collected from a whole n = 256 solve against the oracle's merges,
+    matched by (node, root) tag."""
+    d, e = inputs.workload("n256_uniform")
+    X, y, tag, count = solver.harvest(4096)
+    solver.svd(d, e)
+    solver.stop_harvest()
+    rows = int(count.item())
+    X, y, tag = X[:rows].cpu().numpy(), y[:rows].cpu().numpy(), tag[:rows].cpu().numpy()
+    _, _, _, st = oracle.bdsdc(d, e, return_stats=True)
+    ref = {}
+    for m in st:
+        if m.N < 2:
+            continue
+        F = L.features(m.dS, m.zS)
+        lab = L.labels(m.dS, m.zS, m.o, m.tau)
+        for i in range(m.N):
+            ref[(m.r0, m.m, i)] = (F[i], lab[i])
+    assert rows == len(ref)
+    matched = 0
+    for r in range(rows):
+        key = tuple(int(v) for v in tag[r])
+        assert key in ref
+        f, lab = ref[key]
+        assert np.max(np.abs(X[r] - f)) <= 1e-5 * (1 + np.max(np.abs(f)))
+        assert abs(y[r] - lab) <= 1e-6
+        matched += 1
+    assert matched == rows
+
+
+def test_no_model_is_an_error(gpu):
+    import ctypes
+    import torch
+    from paper_2508_11467_amd import _lib
+    lib = _lib.load()
+    opt = _lib.Options()
+    lib.bdc_default_options(ctypes.byref(opt))
+    opt.start = _lib.BDC_START_LEARNED
+    h = ctypes.c_void_p()
+    assert lib.bdc_create(ctypes.byref(h), 0, ctypes.byref(opt)) == 0
+    try:
+        n = 10
+        d = torch.ones(n, dtype=torch.float64, device="cuda")
+        e = torch.ones(n - 1, dtype=torch.float64, device="cuda")
+        s = torch.empty(n, dtype=torch.float64, device="cuda")
+        U = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        V = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        rc = lib.bdc_svd(h, n, d.data_ptr(), e.data_ptr(), s.data_ptr(), U.data_ptr(), V.data_ptr(), None)
+        assert rc == _lib.BDC_ERR_NO_MODEL
+    finally:
+        lib.bdc_destroy(h)
+
+
+def _solve_checks(s, d, e):
+    import torch
+    n = len(d)
+    sig, U, VT = s.svd(torch.from_numpy(d), torch.from_numpy(e))
+    info, st = s.info()
+    assert info == 0
+    return sig.cpu().numpy(), U.cpu().numpy(), VT.cpu().numpy(), st
+
+
+def test_untrained_network_keeps_the_tolerances(gpu):
+    """Any proposal is safe: the safeguarded iteration still converges."""
+    from paper_2508_11467_amd.api import Solver
+    from paper_2508_11467_amd.start_model import init_params
+    s = Solver(0, start="learned", mlp_params=init_params(3))
+    try:
+        for d, e in [inputs.uniform(1500, 41), inputs.workload("n4096_graded")]:
+            sig, U, VT, st = _solve_checks(s, d, e)
+            ref, _, _ = oracle.bdsdc(d, e)
+            B = oracle.dense(d, e)
+            n = len(d)
+            assert np.max(np.abs(sig - ref)) <= 1e-13 * ref[0]
+            assert np.linalg.norm(B - (U * sig) @ VT) <= 1e-12 * np.linalg.norm(B)
+            assert np.max(np.abs(U.T @ U - np.eye(n))) <= 1e-12
+            assert np.max(np.abs(VT @ VT.T - np.eye(n))) <= 1e-12
+    finally:
+        s.close()
+
+
+def test_trained_network_cuts_iterations(gpu):
+    """The shipped network against the plain start on a held-out N(0,1)
+    bidiagonal (a spectrum it was not trained on): same tolerances, fewer
+    evaluations of the secular function per root."""
+    from paper_2508_11467_amd.api import Solver
+    d, e = inputs.normal(4096, inputs.split_seed(3, 0, "valid", 77))
+    plain = Solver(0)
+    learned = Solver(0, start="learned")
+    try:
+        s0, U0, V0, st0 = _solve_checks(plain, d, e)
+        s1, U1, V1, st1 = _solve_checks(learned, d, e)
+    finally:
+        plain.close()
+        learned.close()
+    ref, _, _ = oracle.bdsdc(d, e)
+    B = oracle.dense(d, e)
+    n = len(d)
+    assert np.max(np.abs(s1 - ref)) <= 1e-13 * ref[0]
+    assert np.linalg.norm(B - (U1 * s1) @ V1) <= 1e-12 * np.linalg.norm(B)
+    assert np.max(np.abs(U1.T @ U1 - np.eye(n))) <= 1e-12
+    assert np.max(np.abs(V1 @ V1.T - np.eye(n))) <= 1e-12
+    ip = st0["secular_evals"] / st0["roots"]
+    il = st1["secular_evals"] / st1["roots"]
+    print(f"secular evaluations per root: plain {ip:.3f}, learned {il:.3f}")
+    assert st0["roots"] == st1["roots"]
+    assert il <= 0.9 * ip
