@@ -13,6 +13,10 @@ already resident in HBM.  Prints one JSON line.
             bound (MFMA FP64 peak, HBM bandwidth, or FP64 vector ALU)
   cpu_baseline  the CPU oracle timed on a bounded sample of the same
             workload family on this host
+  learned   the same workload with the learned secular start (the MLP's
+            proposal as each root's first point): time and secular
+            evaluations per root next to the plain start's; config5 repeats
+            the comparison at n = 32768 (d, e iid N(0,1))
 """
 
 from __future__ import annotations
@@ -49,6 +53,8 @@ def parse():
     ap.add_argument("--workload", default="n16384_normal", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=4096, help="size of the CPU oracle sample")
+    ap.add_argument("--no-config5", action="store_true", help="skip the n = 32768 plain/learned comparison")
+    ap.add_argument("--no-ozaki", action="store_true", help="skip the split-precision comparison")
     return ap.parse_args()
 
 
@@ -68,6 +74,74 @@ def kernel_work(kind: str, stats: dict, n: int, launches: int):
     if kind == "leaf":
         return "alu", stats["leaf_flops"] / max(launches, 1), "TFLOP/s", PEAK_FP64_VALU
     return "hbm", 0.0, "GB/s", PEAK_HBM
+
+
+def time_solver(solver, dt, et, out, steps: int, warmup: int) -> float:
+    import torch
+    for _ in range(warmup):
+        solver.svd(dt, et, out=out)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        solver.svd(dt, et, out=out)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def accuracy(d, e, sig, U, VT) -> dict:
+    """Residual ||B V - U S||_F / ||B||_F and orthogonality of U and V, on the
+    GPU in FP64."""
+    import numpy as np
+    import torch
+    n = len(d)
+    dev = sig.device
+    dt = torch.from_numpy(d).to(dev)
+    et = torch.from_numpy(np.concatenate([e, [0.0]])).to(dev)
+    V = VT.T
+    BV = dt[:, None] * V
+    BV[:-1] += et[:-1, None] * V[1:]
+    nb = math.sqrt(float(np.sum(d * d) + np.sum(e * e)))
+    res = float(torch.linalg.norm(BV - U * sig[None, :])) / nb
+    del BV
+    Uc = U.contiguous()
+    G = Uc.T.contiguous() @ Uc
+    G.diagonal().sub_(1.0)
+    ou = float(torch.max(torch.abs(G)))
+    del G, Uc
+    Vc = VT.contiguous()
+    G = Vc @ Vc.T.contiguous()
+    G.diagonal().sub_(1.0)
+    ov = float(torch.max(torch.abs(G)))
+    del G, Vc
+    torch.cuda.empty_cache()
+    return {"residual": res, "orth_U": ou, "orth_V": ov}
+
+
+def plain_vs_learned(d, e, steps: int, warmup: int) -> dict:
+    """ms per solve and secular evaluations per root with each start."""
+    import torch
+
+    from paper_2508_11467_amd.api import Solver
+    n = len(d)
+    dev = torch.device("cuda:0")
+    dt = torch.from_numpy(d).to(dev)
+    et = torch.from_numpy(e).to(dev)
+    out = (torch.empty(n, dtype=torch.float64, device=dev), torch.empty((n, n), dtype=torch.float64, device=dev),
+           torch.empty((n, n), dtype=torch.float64, device=dev))
+    res = {}
+    for start in ("plain", "learned"):
+        s = Solver(0, start=start)
+        ms = time_solver(s, dt, et, out, steps, warmup)
+        info, st = s.info()
+        s.close()
+        res[start] = {"ms_per_step": ms, "secular_iters_per_root": st["secular_evals"] / max(st["roots"], 1),
+                      "roots": st["roots"], "info": info}
+    del out
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(n: int):
@@ -127,6 +201,27 @@ def main():
     ms = start.elapsed_time(stop) / args.steps
     info, stats = solver.info()
     solver.close()
+
+    sig_fp64 = sig.clone()
+    acc_fp64 = accuracy(d, e, sig, ub.T, vb.T)
+
+    # the same solves with split-precision update products
+    ozaki = None
+    if not args.no_ozaki:
+        osv = Solver(0, gemm="ozaki")
+        ms_oz = time_solver(osv, dt, et, (sig, ub, vb), args.steps, args.warmup)
+        info_o, _ = osv.info()
+        osv.close()
+        ozaki = {"ms_per_step": ms_oz, "value": (8.0 / 3.0) * n ** 3 / (ms_oz * 1e-3) / 1e9, "slices": 7,
+                 "min_kept_values": 256, "info": info_o,
+                 "sigma_max_rel_diff_vs_fp64": float(torch.max(torch.abs(sig - sig_fp64)) / sig_fp64[0]),
+                 **accuracy(d, e, sig, ub.T, vb.T)}
+
+    # the same solves with the learned start
+    ls = Solver(0, start="learned")
+    ms_learned = time_solver(ls, dt, et, (sig, ub, vb), args.steps, args.warmup)
+    info_l, stats_l = ls.info()
+    ls.close()
 
     # timed region 2: the same steps launched kernel by kernel, each launch
     # bracketed by HIP events on the solve's stream (per-kernel durations)
@@ -191,6 +286,23 @@ def main():
         "ms_per_step_kernel_by_kernel": ms_events,
         "roofline": roofline,
     }
+    line["accuracy"] = acc_fp64
+    if ozaki is not None:
+        line["ozaki"] = ozaki
+    line["learned"] = {
+        "ms_per_step": ms_learned,
+        "value": nominal / (ms_learned * 1e-3) / 1e9,
+        "secular_iters_per_root": stats_l["secular_evals"] / max(stats_l["roots"], 1),
+        "secular_iters_per_root_plain": iters_per_root,
+        "roots": stats_l["roots"],
+        "info": info_l,
+    }
+    if not args.no_config5 and args.workload == "n16384_normal":
+        del sig, ub, vb
+        torch.cuda.empty_cache()
+        d5, e5 = inputs.workload("n32768_normal")
+        line["config5"] = {"workload": WORKLOADS["n32768_normal"][0],
+                           **plain_vs_learned(d5, e5, max(2, args.steps // 3), 1)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_n)
     print(json.dumps(line), flush=True)

@@ -55,6 +55,14 @@ enum {
   BDC_START_LEARNED = 1 /* first evaluation at the position proposed by the MLP */
 };
 
+/* Arithmetic of the vector-update products (options.gemm). */
+enum {
+  BDC_GEMM_FP64 = 0, /* FP64 matrix cores (the paper's FP64 products) */
+  BDC_GEMM_OZAKI = 1 /* split precision: bfloat16 digit slices on the bfloat16 matrix
+                        cores, FP32 accumulation, FP64 combination (single-problem
+                        solves; batched solves keep FP64) */
+};
+
 /* Size of the learned-start network: 19 features -> 64 -> 64 -> 64 -> 1. */
 #define BDC_MLP_FEATURES 19
 #define BDC_MLP_HIDDEN 64
@@ -73,6 +81,11 @@ typedef struct {
   int start;                  /* BDC_START_PLAIN (default) or BDC_START_LEARNED (needs
                                  bdc_mlp_set first; same stopping rule, only the
                                  first point of each root's iteration changes) */
+  int gemm;                   /* BDC_GEMM_FP64 (default) or BDC_GEMM_OZAKI */
+  int ozaki_slices;           /* slices per operand, 5..7 (default 7: terms dropped
+                                 below 2^-54 relative to |row| |column|) */
+  int ozaki_min_n;            /* merges with at least this many kept values use the
+                                 split products, >= 128 (default 256); smaller ones FP64 */
 } bdc_options_t;
 
 void bdc_default_options(bdc_options_t* opt);
@@ -253,6 +266,15 @@ int bdc_mlp_train(bdc_handle_t handle, const float* X, const float* y, const int
  * while collecting.  X = NULL stops collecting. */
 int bdc_set_harvest(bdc_handle_t handle, float* X, float* y, int32_t* tag, int64_t capacity,
                     unsigned long long* count);
+
+/* C (M x N, ldc) = A (M x K, lda) * B (K x N, ldb), column-major FP64, through
+ * the split-precision kernels of BDC_GEMM_OZAKI with `slices` slices (5..7):
+ * every row of A and column of B scaled by a power of two and cut into 8-bit
+ * digits held exactly in bfloat16, digit products with p + q <= slices - 1
+ * summed on the bfloat16 matrix cores in FP32 (exactly for the three leading
+ * weights) and combined in FP64. */
+int bdc_step_gemm_ozaki(bdc_handle_t handle, int slices, int M, int N, int K, const double* A, int lda,
+                        const double* B, int ldb, double* C, int ldc, bdc_stream_t stream);
 
 const char* bdc_status_string(int status);
 

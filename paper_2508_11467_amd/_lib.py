@@ -18,6 +18,8 @@ BDC_ERR_UNSUPPORTED = -1006
 BDC_ERR_NO_MODEL = -1007
 BDC_START_PLAIN = 0
 BDC_START_LEARNED = 1
+BDC_GEMM_FP64 = 0
+BDC_GEMM_OZAKI = 1
 MLP_FEATURES = 19
 MLP_PARAMS = 19 * 64 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 + 1
 
@@ -37,6 +39,9 @@ class Options(ctypes.Structure):
         ("timing", c_int),
         ("use_graph", c_int),
         ("start", c_int),
+        ("gemm", c_int),
+        ("ozaki_slices", c_int),
+        ("ozaki_min_n", c_int),
     ]
 
 
@@ -86,6 +91,7 @@ SIGNATURES = {
     "bdc_mlp_grad": (c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
     "bdc_mlp_train": (c_int, [c_vp, c_vp, c_vp, c_vp, c_i64, c_i64, ctypes.c_float, c_vp, c_vp]),
     "bdc_set_harvest": (c_int, [c_vp, c_vp, c_vp, c_vp, c_i64, c_vp]),
+    "bdc_step_gemm_ozaki": (c_int, [c_vp, c_int, c_int, c_int, c_int, c_vp, c_int, c_vp, c_int, c_vp, c_int, c_vp]),
     "bdc_status_string": (c_char_p, [c_int]),
 }
 

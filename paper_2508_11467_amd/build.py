@@ -24,6 +24,7 @@ SOURCES = {
     "k_secular.hip": [],
     "k_update.hip": [],
     "k_mlp.hip": [],
+    "k_ozaki.hip": [],
     "api.cpp": [],
     "api_steps.cpp": [],
 }

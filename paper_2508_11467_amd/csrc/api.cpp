@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -27,10 +28,11 @@ namespace {
 constexpr uint32_t kMagic = 0xBDC05EEDu;
 
 enum Kind {
-  kReset = 0, kLeaf, kPrep, kRotate, kGather, kStart, kSecular, kLowner, kVectors, kOrder, kUpdate, kFinal, kKinds
+  kReset = 0, kLeaf, kPrep, kRotate, kGather, kStart, kSecular, kLowner, kVectors, kOrder, kUpdate, kUpdateOz,
+  kFinal, kKinds
 };
 const char* kKindNames[kKinds] = {"reset", "leaf", "deflate", "rotate", "gather", "start", "secular",
-                                  "lowner", "vectors", "order", "update_gemm", "final"};
+                                  "lowner", "vectors", "order", "update_gemm", "update_ozaki", "final"};
 
 struct Level {
   int nnodes = 0;
@@ -84,7 +86,10 @@ struct bdc_handle_s {
   size_t pool_used = 0;
   // learned start: FP32 parameters and Adam moments (one allocation), the
   // per-workgroup gradient partials of a training step, and harvest buffers
+  void* oz_arena = nullptr;  // split-precision slice planes (single-problem solves)
+  size_t oz_bytes = 0;
   float* mlp = nullptr;  // params | m | v
+  unsigned short* mlp_pk = nullptr;  // inference layout, repacked at each learned solve
   int adam_t = 0;
   float* part = nullptr;  // parts x params | parts losses
   int part_cap = 0;
@@ -294,6 +299,50 @@ int ensure_workspace(bdc_handle_t h, int64_t tn, int64_t tn2, int nnodes) {
   return BDC_OK;
 }
 
+// Slice planes of the split-precision products for one problem of size n:
+// per side (U, V) the row-split left operands and the column-split right
+// operands of the top and bottom halves, each `slices` bfloat16 planes of
+// n rows x P (P >= n + 32, a multiple of 8), and an exponent per plane row.
+int ensure_ozaki(bdc_handle_t h, int64_t n) {
+  const int S = h->opt.ozaki_slices;
+  const int64_t P = ((n + 32 + 7) / 8) * 8;
+  const size_t plane = (size_t)n * P;
+  const size_t bytes = 6 * align_up((size_t)S * plane * 2) + 6 * align_up((size_t)n * 4);
+  if (h->oz_arena && h->oz_bytes >= bytes && h->w.oz.P == P && h->w.oz.S == S) return BDC_OK;
+  if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
+  drop_graph(h);
+  if (h->oz_arena) (void)hipFree(h->oz_arena);
+  h->oz_arena = nullptr;
+  h->oz_bytes = 0;
+  if (h->opt.workspace_cap_bytes && h->arena_bytes + bytes > h->opt.workspace_cap_bytes) return BDC_ERR_NOMEM;
+  if (hipMalloc(&h->oz_arena, bytes) != hipSuccess) {
+    h->oz_arena = nullptr;
+    return BDC_ERR_NOMEM;
+  }
+  h->oz_bytes = bytes;
+  char* b = (char*)h->oz_arena;
+  auto take = [&](size_t nbytes) {
+    char* r = b;
+    b += align_up(nbytes);
+    return (void*)r;
+  };
+  OzWork& oz = h->w.oz;
+  for (int side = 0; side < 2; ++side) {
+    oz.A[side] = (unsigned short*)take((size_t)S * plane * 2);
+    oz.Bt[side] = (unsigned short*)take((size_t)S * plane * 2);
+    oz.Bb[side] = (unsigned short*)take((size_t)S * plane * 2);
+  }
+  for (int side = 0; side < 2; ++side) {
+    oz.Ea[side] = (int*)take((size_t)n * 4);
+    oz.Ebt[side] = (int*)take((size_t)n * 4);
+    oz.Ebb[side] = (int*)take((size_t)n * 4);
+  }
+  oz.plane = (int64_t)plane;
+  oz.P = P;
+  oz.S = S;
+  return BDC_OK;
+}
+
 hipEvent_t next_event(bdc_handle_t h) {
   if (h->pool_used == h->pool.size()) {
     hipEvent_t e;
@@ -336,10 +385,17 @@ int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, do
   w.max_secular_iters = h->opt.max_secular_iters;
   w.max_leaf_sweeps = h->opt.max_leaf_sweeps;
   const bool learned = h->opt.start == BDC_START_LEARNED;
-  if (!learned) w.xs = nullptr;
+  w.xs = nullptr;
+  w.mlp_pk = learned ? h->mlp_pk : nullptr;
+  const bool ozaki = h->opt.gemm == BDC_GEMM_OZAKI && p.nprob == 1 && h->oz_arena;
+  w.oz.min_n = ozaki ? h->opt.ozaki_min_n : INT32_MAX;
   {
     Timer t(h, st, kReset);
     launch_reset(w.ctl, w.st, p.nnodes, st);
+  }
+  if (learned) {
+    Timer t(h, st, kStart);
+    launch_mlp_pack(h->mlp, h->mlp_pk, st);
   }
   {
     Timer t(h, st, kLeaf);
@@ -349,16 +405,16 @@ int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, do
     { Timer t(h, st, kPrep); launch_prep(L.dev, L.nnodes, L.max_m, w, st); }
     { Timer t(h, st, kRotate); launch_rotate(L.dev, L.nnodes, L.max_m, w, st); }
     { Timer t(h, st, kGather); launch_gather(L.dev, L.nnodes, L.max_m, w, st); }
-    if (learned) {
-      Timer t(h, st, kStart);
-      launch_start(L.dev, L.nnodes, L.max_m, w, h->mlp, st);
-    }
     { Timer t(h, st, kSecular); launch_secular(L.dev, L.nnodes, L.max_m, w, st); }
     if (h->harvest) launch_harvest(L.dev, L.nnodes, L.max_m, w, h->hv, st);
     { Timer t(h, st, kLowner); launch_lowner(L.dev, L.nnodes, L.max_m, w, st); }
     { Timer t(h, st, kVectors); launch_vectors(L.dev, L.nnodes, L.max_m, w, st); }
     { Timer t(h, st, kOrder); launch_order(L.dev, L.nnodes, L.max_m, w, st); }
     { Timer t(h, st, kUpdate); launch_update(L.dev, L.nnodes, L.max_m, w, st); }
+    if (ozaki && L.max_m >= w.oz.min_n) {
+      Timer t(h, st, kUpdateOz);
+      launch_update_ozaki(L.dev, L.nnodes, L.max_m, w, st);
+    }
   }
   {
     Timer t(h, st, kFinal);
@@ -376,11 +432,15 @@ int solve(bdc_handle_t h, int64_t batch, const int64_t* sizes, const double* d, 
           double* sigma, double* U, double* VT, hipStream_t st) {
   DeviceGuard g(h->device);
   if (!g.ok) return BDC_ERR_HIP;
-  if (h->opt.start == BDC_START_LEARNED && !h->mlp) return BDC_ERR_NO_MODEL;
+  if (h->opt.start == BDC_START_LEARNED && (!h->mlp || !h->mlp_pk)) return BDC_ERR_NO_MODEL;
   int rc = make_plan(h, sizes, batch);
   if (rc != BDC_OK) return rc;
   rc = ensure_workspace(h, h->plan.total_n, h->plan.total_n2, h->plan.nnodes);
   if (rc != BDC_OK) return rc;
+  if (h->opt.gemm == BDC_GEMM_OZAKI && batch == 1 && sizes[0] > h->opt.ozaki_min_n) {
+    rc = ensure_ozaki(h, sizes[0]);
+    if (rc != BDC_OK) return rc;
+  }
   if (h->plan.total_n == 0) {
     h->last_stream = st;
     h->have_call = true;
@@ -441,6 +501,9 @@ void bdc_default_options(bdc_options_t* opt) {
   opt->timing = 0;
   opt->use_graph = 1;
   opt->start = BDC_START_PLAIN;
+  opt->gemm = BDC_GEMM_FP64;
+  opt->ozaki_slices = 7;
+  opt->ozaki_min_n = 256;
 }
 
 int bdc_create(bdc_handle_t* handle, int device, const bdc_options_t* opt) {
@@ -453,6 +516,8 @@ int bdc_create(bdc_handle_t* handle, int device, const bdc_options_t* opt) {
   if (o.max_secular_iters < 2 || o.max_secular_iters > 64) return -3;
   if (o.max_leaf_sweeps < 1 || o.max_leaf_sweeps > 1000) return -3;
   if (o.start != BDC_START_PLAIN && o.start != BDC_START_LEARNED) return -3;
+  if (o.gemm != BDC_GEMM_FP64 && o.gemm != BDC_GEMM_OZAKI) return -3;
+  if (!oz_supported(o.ozaki_slices) || o.ozaki_min_n < 128) return -3;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return BDC_ERR_NO_DEVICE;
   if (device < 0 || device >= count) return BDC_ERR_NO_DEVICE;
@@ -473,7 +538,9 @@ int bdc_destroy(bdc_handle_t h) {
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     free_plan(h->plan);
     if (h->arena) (void)hipFree(h->arena);
+    if (h->oz_arena) (void)hipFree(h->oz_arena);
     if (h->mlp) (void)hipFree(h->mlp);
+    if (h->mlp_pk) (void)hipFree(h->mlp_pk);
     if (h->part) (void)hipFree(h->part);
     for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
   }
@@ -611,6 +678,10 @@ int bdc_mlp_set(bdc_handle_t h, const float* params, int64_t count) {
   if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
   if (!h->mlp && hipMalloc(&h->mlp, sizeof(float) * 3 * BDC_MLP_PARAMS) != hipSuccess) {
     h->mlp = nullptr;
+    return BDC_ERR_NOMEM;
+  }
+  if (!h->mlp_pk && hipMalloc(&h->mlp_pk, mlp_pack_bytes()) != hipSuccess) {
+    h->mlp_pk = nullptr;
     return BDC_ERR_NOMEM;
   }
   if (hipMemcpy(h->mlp, params, sizeof(float) * BDC_MLP_PARAMS, hipMemcpyHostToDevice) != hipSuccess ||

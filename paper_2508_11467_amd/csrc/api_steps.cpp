@@ -4,6 +4,8 @@
 // checking each stage against an independent implementation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -77,6 +79,7 @@ Work make_work(Tmp& t, int64_t n) {
   w.rot_col = t.alloc<int32_t>(2 * N1);
   w.st = t.alloc<NodeState>(1);
   w.ctl = t.alloc<Ctl>(1);
+  w.oz.min_n = INT32_MAX;
   w.max_secular_iters = 64;
   w.max_leaf_sweeps = 40;
   return w;
@@ -260,6 +263,34 @@ int bdc_step_secular(bdc_handle_t h, int N, const double* d, const double* z, in
                      int32_t* iters, bdc_stream_t stream) {
   const int rc = bdc_step_secular_start(h, N, d, z, nullptr, o, tau, iters, stream);
   return rc <= -6 && rc >= -8 ? rc + 1 : rc;  // argument positions of this signature
+}
+
+int bdc_step_gemm_ozaki(bdc_handle_t h, int slices, int M, int N, int K, const double* A, int lda,
+                        const double* B, int ldb, double* C, int ldc, bdc_stream_t stream) {
+  int dev, msi, mls;
+  if (bdc::handle_info(h, &dev, &msi, &mls) != BDC_OK) return BDC_ERR_INVALID_HANDLE;
+  if (!oz_supported(slices)) return -2;
+  if (M < 0) return -3;
+  if (N < 0) return -4;
+  if (K < 0) return -5;
+  if (M > 0 && K > 0 && !A) return -6;
+  if (lda < std::max(1, M)) return -7;
+  if (K > 0 && N > 0 && !B) return -8;
+  if (ldb < std::max(1, K)) return -9;
+  if (M > 0 && N > 0 && !C) return -10;
+  if (ldc < std::max(1, M)) return -11;
+  if (M == 0 || N == 0) return BDC_OK;
+  Guard g(dev);
+  hipStream_t st = (hipStream_t)stream;
+  Tmp t;
+  const int64_t P = std::max<int64_t>(32, ((int64_t)K + 31) / 32 * 32);
+  unsigned short* sa = t.alloc<unsigned short>((size_t)slices * M * P);
+  unsigned short* sb = t.alloc<unsigned short>((size_t)slices * N * P);
+  int* ea = t.alloc<int>(M);
+  int* eb = t.alloc<int>(N);
+  if (!t.ok) return BDC_ERR_NOMEM;
+  launch_gemm_ozaki_plain(slices, M, N, K, A, lda, B, ldb, C, ldc, sa, sb, ea, eb, P, st);
+  return finish(st);
 }
 
 int bdc_step_features(bdc_handle_t h, int N, const double* d, const double* z, float* X, bdc_stream_t stream) {

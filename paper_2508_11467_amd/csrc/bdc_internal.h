@@ -69,6 +69,22 @@ struct Ctl {
   unsigned long long leaf_rot_flops;
 };
 
+// Split-precision update products: bfloat16 slice planes per side (0 U,
+// 1 V) of the row-split left operands (A) and the column-split right operands
+// of the top and bottom halves (Bt, Bb), with their power-of-two exponents.
+struct OzWork {
+  unsigned short* A[2];
+  unsigned short* Bt[2];
+  unsigned short* Bb[2];
+  int* Ea[2];
+  int* Ebt[2];
+  int* Ebb[2];
+  int64_t plane;  // elements per slice plane
+  int64_t P;      // row stride of a plane
+  int S;          // slices per operand
+  int min_n;      // merges with at least this many kept values use it (INT32_MAX: off)
+};
+
 // Device pointers of one call (passed to every kernel by value).
 struct Work {
   const double* d;  // inputs, packed per problem at vec_off
@@ -110,8 +126,10 @@ struct Work {
   int32_t* rot_pos;  // rotations: sorted positions (2 per rotation)
   int32_t* rot_col;  //   physical columns (2 per rotation)
   double* rot_cs;    //   (c, s)
-  float* xs;         // proposed start of each root in its interval (learned
-                     // start), nullptr for the plain start
+  float* xs;         // caller-given start of each root in its interval, or nullptr
+  const unsigned short* mlp_pk;  // packed network for the in-kernel learned start,
+                                 // or nullptr
+  OzWork oz;
   NodeState* st;
   Ctl* ctl;
   int max_secular_iters;
@@ -145,8 +163,8 @@ void launch_final(const int64_t* prob_n, const int64_t* prob_vec, const int64_t*
 // device and iteration options of a handle (BDC_OK or BDC_ERR_INVALID_HANDLE)
 int handle_info(bdc_handle_t h, int* device, int* max_secular_iters, int* max_leaf_sweeps);
 
-void launch_start(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, const float* params,
-                  hipStream_t st);
+size_t mlp_pack_bytes();
+void launch_mlp_pack(const float* params, unsigned short* packed, hipStream_t st);
 void launch_harvest(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, const Harvest& hv,
                     hipStream_t st);
 void launch_features(const double* d, const double* z, int N, float* X, hipStream_t st);
@@ -156,6 +174,12 @@ void launch_mlp_grad(const float* params, const float* X, const float* y, const 
                      float* part, float* part_loss, hipStream_t st);
 void launch_adam(float* params, float* m, float* v, const float* part, int nparts, const float* part_loss,
                  float* grad_out, float* loss_out, int adam_t, float lr, float inv_rows, hipStream_t st);
+
+int oz_supported(int slices);
+void launch_update_ozaki(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
+void launch_gemm_ozaki_plain(int slices, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
+                             double* C, int ldc, unsigned short* sa, unsigned short* sb, int* ea, int* eb, int64_t P,
+                             hipStream_t st);
 
 void launch_gemm_plain(int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                        double* C, int ldc, hipStream_t st);

@@ -1,9 +1,8 @@
 // Learned start of the secular iteration: a 19 -> 64 -> 64 -> 64 -> 1 MLP
 // proposes each root's fractional position in its interval.
 //
-//   k_start    inside a solve, per merge level: the features of 64 roots per
-//              workgroup (from the kept values, z and rho of the merge),
-//              the forward pass, and the proposals written for k_secular
+//   k_mlp_pack packs the parameters for inference (bfloat16, transposed);
+//              the secular kernel computes features and proposals itself
 //   k_harvest  after k_secular: features, the computed root's position and a
 //              (merge, root) tag appended to caller buffers, as training data
 //   k_features the features of one secular problem (d, z) given directly
@@ -23,56 +22,13 @@
 // vector: W1 19x64, b1, W2 64x64, b2, W3 64x64, b3, W4 64, b4; W row-major
 // in x out) and rounded when staged in LDS.
 //
-// Features (FP64, then FP32), for root i of a merge with kept values
-// 0 = d_0 < ... < d_{N-1}, z and rho = sum z^2: the interval (lo, hi) with
-// width h and w2 = hi^2 - lo^2 (interior: lo = d_i, hi = d_{i+1},
-// w2 = h (hi + lo); last: lo = d_{N-1}, hi = sqrt(lo^2 + rho),
-// h = rho / (lo + hi), w2 = rho); for the 4 poles j <= i and the 4 poles
-// j > i the gap (d_j - lo)/h (clamped to >= -4 and <= 5) and the strength
-// log2(z_j^2 / w2)/32 (clamped to [-2, 2]); a missing pole has gap -4 or 5
-// and strength -2; feature 16 is log2(rho / w2)/32 clamped to [-2, 2].
-// Features 17 and 18 describe the far field (f without those 8 poles) at the
-// interval's midpoint lam = lo^2 + w2/2: asinh(v)/8 and asinh(s w2)/8
-// (clamped to [-4, 4]) with v = 1 + sum z_j^2/(d_j^2 - lam) and s = sum
-// z_j^2/(d_j^2 - lam)^2 over the far poles.  The sum takes O(sqrt N) terms:
-// poles are cut into blocks of B (least power of two >= 4 with B^2 >= N and
-// 512 B >= N); a block that holds one of the root's 8 poles is summed term by
-// term in ascending order, every other block contributes one monopole term
-// Z_k/(D_k - lam) (Z_k = sum z_j^2, D_k = sum z_j^2 d_j^2 / Z_k, ascending).
+// Features: see mlp_device.h.
 #include "bdc_internal.h"
 #include "block_util.h"
+#include "mlp_device.h"
 
 namespace bdc {
 namespace {
-
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int kRows = 64;     // rows (roots) per workgroup
-constexpr int kF = 19;        // features
-constexpr int kFP = 32;       // features padded to two k-steps of 16
-constexpr int kH = 64;        // hidden width
-constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kF * kH, kOffW2 = kOffB1 + kH, kOffB2 = kOffW2 + kH * kH,
-              kOffW3 = kOffB2 + kH, kOffB3 = kOffW3 + kH * kH, kOffW4 = kOffB3 + kH, kOffB4 = kOffW4 + kH,
-              kParams = kOffB4 + 1;
-static_assert(kParams == BDC_MLP_PARAMS, "parameter layout");
-
-// float -> bfloat16 bits, round to nearest, ties to even
-__device__ inline unsigned short bf16_bits(float x) {
-  unsigned int u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ inline float bf16_val(unsigned short b) { return __uint_as_float(((unsigned int)b) << 16); }
-
-constexpr float kGc = 0.7978845608028654f;  // sqrt(2/pi)
-constexpr float kGa = 0.044715f;
-__device__ inline float gelu_f(float x) { return 0.5f * x * (1.0f + tanhf(kGc * (x + kGa * x * x * x))); }
-__device__ inline float gelu_d(float x) {
-  const float t = tanhf(kGc * (x + kGa * x * x * x));
-  return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * kGc * (1.0f + 3.0f * kGa * x * x);
-}
 
 // Weights of the network staged in LDS (bfloat16 bits; biases FP32).
 struct MlpLds {
@@ -172,145 +128,10 @@ __device__ void forward_tile(const MlpLds& W, ActLds& A, float (*pre)[kRows * kH
   __syncthreads();
 }
 
-__device__ inline float logistic(float v) { return 1.0f / (1.0f + expf(-v)); }
-
-__device__ inline float clampd(double v, double lo, double hi) { return (float)fmin(fmax(v, lo), hi); }
-
-__device__ inline float strength(double zj, double w2) {
-  const double c = (zj * zj) / w2;
-  if (c == 0.0) return -2.0f;
-  if (isinf(c)) return 2.0f;
-  return clampd(log2(c) / 32.0, -2.0, 2.0);
-}
-
-constexpr int kMaxBlocks = 512;  // far-field blocks (B is chosen so that nb <= 512)
-
-__device__ inline int far_block(int N) {
-  int B = 4;
-  while ((int64_t)B * B < N || 512 * (int64_t)B < N) B *= 2;
-  return B;
-}
-
-// Far-field block moments of a secular problem, by the whole workgroup.
-struct FarLds {
-  double Z[kMaxBlocks];
-  double D[kMaxBlocks];
-};
-
-__device__ void far_moments(const double* __restrict__ d, const double* __restrict__ z, int N, int B, FarLds& F) {
-  const int nb = (N + B - 1) / B;
-  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
-    double zs = 0.0, ms = 0.0;
-    const int j1 = min(N, (k + 1) * B);
-    for (int j = k * B; j < j1; ++j) {
-      const double zz = z[j] * z[j];
-      zs += zz;
-      ms += zz * (d[j] * d[j]);
-    }
-    F.Z[k] = zs;
-    F.D[k] = zs > 0.0 ? ms / zs : 0.0;
-  }
-}
-
-__device__ inline float asinh8(double x) { return (float)fmin(fmax(asinh(x) / 8.0, -4.0), 4.0); }
-
-// Features of root i (FP64 arithmetic, FP32 results).
-__device__ void root_features(const double* __restrict__ d, const double* __restrict__ z, int N, double rho, int i,
-                              int B, const FarLds& FL, float* f) {
-  const double lo = d[i];
-  double h, w2;
-  if (i < N - 1) {
-    const double hi = d[i + 1];
-    h = hi - lo;
-    w2 = h * (hi + lo);
-  } else {
-    const double hi = sqrt(lo * lo + rho);
-    h = rho / (lo + hi);
-    w2 = rho;
-  }
-  for (int q = 0; q < 4; ++q) {
-    int j = i - q;
-    if (j >= 0) {
-      f[2 * q] = (float)fmax((d[j] - lo) / h, -4.0);
-      f[2 * q + 1] = strength(z[j], w2);
-    } else {
-      f[2 * q] = -4.0f;
-      f[2 * q + 1] = -2.0f;
-    }
-    j = i + 1 + q;
-    if (j < N) {
-      f[8 + 2 * q] = (float)fmin((d[j] - lo) / h, 5.0);
-      f[9 + 2 * q] = strength(z[j], w2);
-    } else {
-      f[8 + 2 * q] = 5.0f;
-      f[9 + 2 * q] = -2.0f;
-    }
-  }
-  f[16] = clampd(log2(rho / w2) / 32.0, -2.0, 2.0);
-  // far field at the midpoint (in omega^2) of the interval
-  const double lam = lo * lo + 0.5 * w2;
-  double v = 1.0, sl = 0.0;
-  const int nb = (N + B - 1) / B;
-  for (int k = 0; k < nb; ++k) {
-    const int j0 = k * B, j1 = min(N, (k + 1) * B);
-    if (j1 > i - 3 && j0 <= i + 4) {
-      for (int j = j0; j < j1; ++j) {
-        if (j >= i - 3 && j <= i + 4) continue;
-        const double den = d[j] * d[j] - lam;
-        const double t = (z[j] * z[j]) / den;
-        v += t;
-        sl += t / den;
-      }
-    } else if (FL.Z[k] > 0.0) {
-      const double den = FL.D[k] - lam;
-      const double t = FL.Z[k] / den;
-      v += t;
-      sl += t / den;
-    }
-  }
-  f[17] = asinh8(v);
-  f[18] = asinh8(sl * w2);
-}
-
-// ---------------------------------------------------------------- k_start
-__global__ __launch_bounds__(256) void k_start(const NodeDesc* __restrict__ nodes, Work w,
-                                               const float* __restrict__ params) {
-  __shared__ MlpLds W;
-  __shared__ ActLds A;
-  __shared__ FarLds FL;
-  const NodeDesc nd = nodes[blockIdx.x];
-  const int N = w.st[nd.id].N;
-  if (N < 2 || (int)blockIdx.y * kRows >= N) return;  // uniform over the workgroup
-  const double rho = w.st[nd.id].rho;
-  const int64_t vo = nd.vec_off + nd.r0;
-  const double* __restrict__ d = w.sd + vo;
-  const double* __restrict__ z = w.sz + vo;
-  const int B = far_block(N);
-  stage_weights(params, W);
-  far_moments(d, z, N, B, FL);
-  __syncthreads();
-  for (int base = blockIdx.y * kRows; base < N; base += gridDim.y * kRows) {
-    if (threadIdx.x < kRows) {
-      const int i = base + threadIdx.x;
-      float f[kF];
-      if (i < N) root_features(d, z, N, rho, i, B, FL, f);
-      else
-        for (int q = 0; q < kF; ++q) f[q] = 0.0f;
-      for (int q = 0; q < kFP; ++q) A.a0[threadIdx.x * kFP + q] = q < kF ? bf16_bits(f[q]) : 0;
-    }
-    __syncthreads();
-    forward_tile(W, A, nullptr);
-    if (threadIdx.x < kRows) {
-      const int i = base + threadIdx.x;
-      if (i < N) w.xs[vo + i] = logistic(A.out[threadIdx.x]);
-    }
-    __syncthreads();
-  }
-}
-
 // ---------------------------------------------------------------- k_harvest
-__global__ __launch_bounds__(64) void k_harvest(const NodeDesc* __restrict__ nodes, Work w, Harvest hv) {
-  __shared__ FarLds FL;
+__global__ __launch_bounds__(256) void k_harvest(const NodeDesc* __restrict__ nodes, Work w, Harvest hv) {
+  __shared__ FeatLds FL;
+  __shared__ unsigned long long s_slot;
   const NodeDesc nd = nodes[blockIdx.x];
   const int N = w.st[nd.id].N;
   if (N < 2 || (int)blockIdx.y * kRows >= N) return;
@@ -321,38 +142,39 @@ __global__ __launch_bounds__(64) void k_harvest(const NodeDesc* __restrict__ nod
   const int B = far_block(N);
   far_moments(d, z, N, B, FL);
   __syncthreads();
-  const int lane = threadIdx.x;
+  const int t = threadIdx.x;
   for (int base = blockIdx.y * kRows; base < N; base += gridDim.y * kRows) {
     const int cnt = min(kRows, N - base);
-    unsigned long long slot = 0;
-    if (lane == 0) slot = atomicAdd(hv.count, (unsigned long long)cnt);
-    slot = __shfl(slot, 0, 64);
-    const int i = base + lane;
-    if (i < N && slot + lane < (unsigned long long)hv.capacity) {
-      const int64_t row = (int64_t)slot + lane;
-      float f[kF];
-      root_features(d, z, N, rho, i, B, FL, f);
-      for (int q = 0; q < kF; ++q) hv.X[row * kF + q] = f[q];
+    if (t == 0) s_slot = atomicAdd(hv.count, (unsigned long long)cnt);
+    __syncthreads();
+    const unsigned long long slot = s_slot;
+    const int64_t cap = hv.capacity;
+    block_features(d, z, N, rho, base, B, FL, [&](int r, int q, float v) {
+      if (slot + r < (unsigned long long)cap) hv.X[((int64_t)slot + r) * kF + q] = v;
+    });
+    const int i = base + t;
+    if (t < kRows && i < N && slot + t < (unsigned long long)cap) {
+      const int64_t row = (int64_t)slot + t;
       // position of the computed root in its interval
       const double tau = w.tau[vo + i];
       const int o = w.o[vo + i];
-      double h;
-      if (i < N - 1) h = d[i + 1] - d[i];
-      else h = rho / (d[i] + sqrt(d[i] * d[i] + rho));
-      double x = (o == i) ? tau / h : 1.0 + tau / h;
+      double lo, h, w2;
+      interval_of(d, N, rho, i, lo, h, w2);
+      const double x = (o == i) ? tau / h : 1.0 + tau / h;
       hv.y[row] = clampd(x, 0.0, 1.0);
       hv.tag[3 * row + 0] = (int32_t)vo;
       hv.tag[3 * row + 1] = nd.m;
       hv.tag[3 * row + 2] = i;
     }
+    __syncthreads();
   }
 }
 
 // Features of one secular problem given directly (rho = sum z^2 summed in
 // ascending order).
-__global__ __launch_bounds__(64) void k_features(const double* __restrict__ d, const double* __restrict__ z, int N,
-                                                 float* __restrict__ X) {
-  __shared__ FarLds FL;
+__global__ __launch_bounds__(256) void k_features(const double* __restrict__ d, const double* __restrict__ z, int N,
+                                                  float* __restrict__ X) {
+  __shared__ FeatLds FL;
   __shared__ double s_rho;
   if (threadIdx.x == 0) {
     double r = 0.0;
@@ -362,11 +184,32 @@ __global__ __launch_bounds__(64) void k_features(const double* __restrict__ d, c
   const int B = far_block(N);
   far_moments(d, z, N, B, FL);
   __syncthreads();
-  const int i = blockIdx.x * kRows + threadIdx.x;
-  if (i < N) {
-    float f[kF];
-    root_features(d, z, N, s_rho, i, B, FL, f);
-    for (int q = 0; q < kF; ++q) X[(int64_t)i * kF + q] = f[q];
+  const int base = blockIdx.x * kRows;
+  block_features(d, z, N, s_rho, base, B, FL,
+                 [&](int r, int q, float v) { X[(int64_t)(base + r) * kF + q] = v; });
+}
+
+// Parameters -> inference layout (bfloat16 transposed weights, FP32 biases).
+__global__ __launch_bounds__(256) void k_mlp_pack(const float* __restrict__ p, unsigned short* __restrict__ pk) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < kPkHalf + kPkBias; q += gridDim.x * blockDim.x) {
+    if (q < kPkW2) {
+      const int o = (q - kPkW1) / kFP, i = (q - kPkW1) % kFP;
+      pk[q] = i < kF ? bf16_bits(p[kOffW1 + i * kH + o]) : 0;
+    } else if (q < kPkW3) {
+      const int o = (q - kPkW2) / kH, i = (q - kPkW2) % kH;
+      pk[q] = bf16_bits(p[kOffW2 + i * kH + o]);
+    } else if (q < kPkW4) {
+      const int o = (q - kPkW3) / kH, i = (q - kPkW3) % kH;
+      pk[q] = bf16_bits(p[kOffW3 + i * kH + o]);
+    } else if (q < kPkHalf) {
+      const int o = (q - kPkW4) / kH, i = (q - kPkW4) % kH;
+      pk[q] = o == 0 ? bf16_bits(p[kOffW4 + i]) : 0;
+    } else {
+      const int b = q - kPkHalf;
+      const float v = b < kH ? p[kOffB1 + b] : b < 2 * kH ? p[kOffB2 + b - kH] : b < 3 * kH ? p[kOffB3 + b - 2 * kH]
+                                                                                       : p[kOffB4];
+      ((float*)(pk + kPkHalf))[b] = v;
+    }
   }
 }
 
@@ -516,23 +359,22 @@ inline int grid_y(int nnodes, int units, int cap_total) {
 
 }  // namespace
 
-void launch_start(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, const float* params,
-                  hipStream_t st) {
-  if (nnodes <= 0) return;
-  const int gy = grid_y(nnodes, (max_m + kRows - 1) / kRows, 4096);
-  hipLaunchKernelGGL(k_start, dim3(nnodes, gy), dim3(256), 0, st, nodes, w, params);
-}
-
 void launch_harvest(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, const Harvest& hv,
                     hipStream_t st) {
   if (nnodes <= 0) return;
   const int gy = grid_y(nnodes, (max_m + kRows - 1) / kRows, 4096);
-  hipLaunchKernelGGL(k_harvest, dim3(nnodes, gy), dim3(64), 0, st, nodes, w, hv);
+  hipLaunchKernelGGL(k_harvest, dim3(nnodes, gy), dim3(256), 0, st, nodes, w, hv);
 }
 
 void launch_features(const double* d, const double* z, int N, float* X, hipStream_t st) {
   if (N < 1) return;
-  hipLaunchKernelGGL(k_features, dim3((N + kRows - 1) / kRows), dim3(64), 0, st, d, z, N, X);
+  hipLaunchKernelGGL(k_features, dim3((N + kRows - 1) / kRows), dim3(256), 0, st, d, z, N, X);
+}
+
+size_t mlp_pack_bytes() { return kPackBytes; }
+
+void launch_mlp_pack(const float* params, unsigned short* packed, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_pack, dim3((kPkHalf + kPkBias + 255) / 256), dim3(256), 0, st, params, packed);
 }
 
 void launch_mlp_forward(const float* params, const float* X, int rows, float* xhat, hipStream_t st) {

@@ -25,6 +25,7 @@
 //              normalised in place.
 #include "bdc_internal.h"
 #include "block_util.h"
+#include "mlp_device.h"
 
 namespace bdc {
 namespace {
@@ -83,15 +84,43 @@ __device__ inline void sum_terms(const double* __restrict__ dj, const double* __
   }
 }
 
+// Pole staging of the secular kernel; with the in-kernel learned start the
+// network's weights and activations share its LDS (they are done with before
+// the poles are staged).
+struct PoleLds {
+  double cd[kSecWaves][kSecChunk];
+  double cz[kSecWaves][kSecChunk];
+};
+struct MlpShared {
+  FastW W;
+  FastAct A;  // A.a1 .. A.a2 also hold the feature scratch (FeatLds)
+};
+static_assert(sizeof(FeatLds) <= sizeof(FastAct::a1) + sizeof(FastAct::a2), "feature scratch");
+template <int kMode>
+struct SecLds {
+  PoleLds p;
+};
+template <>
+struct SecLds<2> {
+  union {
+    PoleLds p;
+    MlpShared m;
+  };
+};
+
+// Start of the iteration: 0 the interval midpoint, 1 a caller-given position
+// (w.xs), 2 the network's proposal computed here (w.mlp_pk).
+//
 // Secular roots of one node: 64 roots per workgroup, one per lane; the four
 // wavefronts each sum a quarter of the poles for all 64 roots (staged in LDS,
 // read by every lane at the same address), and wavefront 0 combines the
 // partial sums -- left-pole sums in ascending quarter order, right-pole sums
 // in descending order, so both stay summed from far to near -- and advances
 // each root's iteration.
+template <int kMode>
 __global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ nodes, Work w) {
-  __shared__ double cd[kSecWaves][kSecChunk];
-  __shared__ double cz[kSecWaves][kSecChunk];
+  __shared__ SecLds<kMode> L;
+  __shared__ float s_x[kSecRoots];
   __shared__ double part[kSecWaves][5][kSecRoots];
   __shared__ double b_ov[kSecRoots], b_tau[kSecRoots];
   __shared__ int b_need[kSecRoots];
@@ -103,20 +132,43 @@ __global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ no
   const double* __restrict__ d = w.sd + vo;
   const double* __restrict__ z = w.sz + vo;
   const int maxit = w.max_secular_iters;
-  const bool learned = w.xs != nullptr;
+  constexpr bool learned = kMode != 0;
   const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  double (*cd)[kSecChunk] = L.p.cd;
+  double (*cz)[kSecChunk] = L.p.cz;
   // this wavefront's quarter of the poles
   const int Q = (N + kSecWaves - 1) / kSecWaves;
   const int q0 = min(N, wv * Q), q1 = min(N, q0 + Q);
   const bool resident = (q1 - q0) <= kSecChunk;  // the quarter fits in LDS once
+  const bool run = (int)blockIdx.y * kSecRoots < N;
 
-  if (resident && (int)blockIdx.y * kSecRoots < N) {
+  if (kMode != 2 && resident && run) {
     for (int j = q0 + lane; j < q1; j += 64) {
       cd[wv][j - q0] = d[j];
       cz[wv][j - q0] = z[j] * z[j];
     }
   }
   for (int base = blockIdx.y * kSecRoots; base < N; base += gridDim.y * kSecRoots) {
+    if constexpr (kMode == 2) {
+      // the network's proposals for roots base .. base+63, then the poles
+      __syncthreads();
+      if (N > 1) {
+        FeatLds& F = *reinterpret_cast<FeatLds*>(L.m.A.a1);
+        const int B = far_block(N);
+        stage_packed(w.mlp_pk, L.m.W);
+        for (int q = t; q < kRows * kFP; q += blockDim.x) L.m.A.a0[q] = 0;
+        far_moments(d, z, N, B, F);
+        __syncthreads();
+        block_features(d, z, N, rho, base, B, F,
+                       [&](int r, int q, float v) { L.m.A.a0[r * kFP + q] = bf16_bits(v); });
+        forward_fast(L.m.W, L.m.A, s_x);
+      }
+      if (resident)
+        for (int j = q0 + lane; j < q1; j += 64) {
+          cd[wv][j - q0] = d[j];
+          cz[wv][j - q0] = z[j] * z[j];
+        }
+    }
     const int i = base + lane;
     const bool active = i < N;
     const bool last = (i == N - 1);
@@ -133,7 +185,8 @@ __global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ no
       if (learned) {
         // first evaluation at the proposed position x of the interval; its
         // half (split at the midpoint in omega^2) gives the origin pole
-        const double x = fmin(fmax((double)w.xs[vo + i], 0x1p-20), 1.0 - 0x1p-20);
+        const float xp = kMode == 2 ? s_x[lane] : w.xs[vo + i];
+        const double x = fmin(fmax((double)xp, 0x1p-20), 1.0 - 0x1p-20);
         first = false;
         if (last) {
           h = rho / (dr + sqrt(dr * dr + rho));
@@ -414,7 +467,10 @@ inline int grid_y(int nnodes, int units, int cap_total) {
 void launch_secular(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {
   if (nnodes <= 0) return;
   const int gy = grid_y(nnodes, (max_m + kSecRoots - 1) / kSecRoots, 4096);
-  hipLaunchKernelGGL(k_secular, dim3(nnodes, gy), dim3(kSecRoots * kSecWaves), 0, st, nodes, w);
+  const dim3 grid(nnodes, gy), block(kSecRoots * kSecWaves);
+  if (w.mlp_pk) hipLaunchKernelGGL(k_secular<2>, grid, block, 0, st, nodes, w);
+  else if (w.xs) hipLaunchKernelGGL(k_secular<1>, grid, block, 0, st, nodes, w);
+  else hipLaunchKernelGGL(k_secular<0>, grid, block, 0, st, nodes, w);
 }
 
 void launch_lowner(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {

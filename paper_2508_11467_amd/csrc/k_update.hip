@@ -286,6 +286,7 @@ __global__ __launch_bounds__(256) void k_update(const NodeDesc* __restrict__ nod
   const NodeState st = w.st[nd.id];
   const int N = st.N, n1 = st.n1, n2 = st.n2;
   if ((TM <= 64) != (N <= kSmallN)) return;
+  if (N >= w.oz.min_n) return;  // done by the split-precision products
   const int m = nd.m, s = nd.s, k = nd.k, r0 = nd.r0;
   const int64_t ld = nd.ld, vo = nd.vec_off + nd.r0;
   const int sub = blockIdx.z;

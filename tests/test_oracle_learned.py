@@ -228,3 +228,23 @@ def test_learned_roots_relative_accuracy_near_poles():
     o, t, _ = L.learned_roots(d, z, np.array([0.9, 0.9, 0.9, 0.9]))
     assert np.array_equal(o, o0)
     assert np.allclose(t, t0, rtol=1e-14, atol=0)
+
+
+def test_shipped_network_cuts_oracle_iterations():
+    """The network shipped with the package, run through the oracle's
+    bfloat16 forward pass, starts the oracle's iteration on a held-out
+    N(0,1) bidiagonal: same singular values, fewer evaluations per root."""
+    import os
+    import oracle
+    from paper_2508_11467_amd import inputs
+    path = os.path.join(os.path.dirname(__file__), "..", "paper_2508_11467_amd", "data", "start_mlp.npy")
+    p = np.load(path, allow_pickle=False).astype(np.float64)
+    assert p.shape == (L.NPARAMS,)
+    d, e = inputs.normal(600, inputs.split_seed(3, 0, "valid", 5))
+    s0, _, _, st0 = oracle.bdsdc(d, e, return_stats=True)
+    s1, _, _, st1 = oracle.bdsdc(d, e, return_stats=True,
+                                 start=lambda dd, zz: L.mlp_forward(p, L.features(dd, zz), "bf16")[0])
+    assert np.max(np.abs(s1 - s0)) <= 1e-14 * s0[0]
+    ip = sum(m.iters.sum() for m in st0) / sum(m.N for m in st0)
+    il = sum(m.iters.sum() for m in st1) / sum(m.N for m in st1)
+    assert il <= 0.9 * ip, (ip, il)
