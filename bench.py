@@ -42,6 +42,7 @@ WORKLOADS = {
     "n32768_normal": ("n = 32768, d, e iid N(0,1), seed 250811967", 32768),
     "n16384_ones": ("n = 16384, d = e = 1 (no deflation, update-GEMM bound)", 16384),
     "n4096_uniform": ("n = 4096, d, e iid U(-1,1)", 4096),
+    "batch2000": ("2000 bidiagonals, sizes round(exp(U(ln 32, ln 2048))), d, e iid U(-1,1)", 0),
 }
 
 
@@ -55,6 +56,9 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=4096, help="size of the CPU oracle sample")
     ap.add_argument("--no-config5", action="store_true", help="skip the n = 32768 plain/learned comparison")
     ap.add_argument("--no-ozaki", action="store_true", help="skip the split-precision comparison")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-start comparison")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="bytes of one device-to-device copy issued first (calibrates HBM counters)")
     return ap.parse_args()
 
 
@@ -74,6 +78,20 @@ def kernel_work(kind: str, stats: dict, n: int, launches: int):
     if kind == "leaf":
         return "alu", stats["leaf_flops"] / max(launches, 1), "TFLOP/s", PEAK_FP64_VALU
     return "hbm", 0.0, "GB/s", PEAK_HBM
+
+
+def measured_traffic(workload: str, kind: str):
+    """HBM bytes per launch of a kernel kind from the committed counter
+    summary (profiles/traffic_<workload>_<kind>.json), or None when there is
+    none or it was taken from other kernel sources than the ones built."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{kind}.json")
+    if not os.path.exists(path):
+        return None
+    from paper_2508_11467_amd.build import source_hash
+    t = json.load(open(path))
+    if t.get("source_hash") != source_hash():
+        return None
+    return t.get("traffic_bytes_per_launch")
 
 
 def time_solver(solver, dt, et, out, steps: int, warmup: int) -> float:
@@ -144,6 +162,102 @@ def plain_vs_learned(d, e, steps: int, warmup: int) -> dict:
     return res
 
 
+def batch_checks(sizes, d, e, sig, U, VT) -> dict:
+    """Worst residual and orthogonality over the problems of a batch (GPU)."""
+    import numpy as np
+    import torch
+    dev = sig.device
+    dt = torch.from_numpy(d).to(dev)
+    et = torch.from_numpy(e).to(dev)
+    off = mo = 0
+    wr = wo = 0.0
+    for n in sizes:
+        s = sig[off:off + n]
+        u = U[mo:mo + n * n].view(n, n).T
+        v = VT[mo:mo + n * n].view(n, n).T
+        V = v.T
+        BV = dt[off:off + n, None] * V
+        BV[:-1] += et[off:off + n - 1, None] * V[1:]
+        nb = torch.sqrt(torch.sum(dt[off:off + n] ** 2) + torch.sum(et[off:off + n - 1] ** 2))
+        wr = max(wr, float(torch.linalg.norm(BV - u * s[None, :]) / nb))
+        uc = u.contiguous()
+        I = torch.eye(n, dtype=torch.float64, device=dev)
+        wo = max(wo, float(torch.max(torch.abs(uc.T.contiguous() @ uc - I))),
+                 float(torch.max(torch.abs(V.contiguous() @ V.T.contiguous() - I))))
+        off += n
+        mo += n * n
+    return {"worst_residual": wr, "worst_orth": wo}
+
+
+def bench_batched(args, desc):
+    import numpy as np
+    import torch
+
+    from paper_2508_11467_amd import inputs
+    from paper_2508_11467_amd.api import Solver
+    sizes = inputs.batch_sizes(2000, 32, 2048, inputs.seed_for(4, 0)).tolist()
+    d, e = inputs.batch_uniform(sizes, inputs.seed_for(4, 1))
+    dev = torch.device("cuda:0")
+    dt = torch.from_numpy(d).to(dev)
+    et = torch.from_numpy(e).to(dev)
+    tot = sum(sizes)
+    tot2 = sum(x * x for x in sizes)
+    out = (torch.empty(tot, dtype=torch.float64, device=dev), torch.empty(tot2, dtype=torch.float64, device=dev),
+           torch.empty(tot2, dtype=torch.float64, device=dev))
+    nominal = sum((8.0 / 3.0) * x ** 3 for x in sizes)
+
+    def run(solver, steps, warmup):
+        for _ in range(warmup):
+            solver.svd_batched(sizes, dt, et, out=out)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            solver.svd_batched(sizes, dt, et, out=out)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    solver = Solver(0)
+    ms_default = run(solver, args.steps, args.warmup)
+    t0 = time.perf_counter()
+    tuned = solver.autotune(sizes, dt, et, out=out, repeats=2)
+    tune_s = time.perf_counter() - t0
+    ms = run(solver, args.steps, args.warmup)
+    info, stats = solver.info()
+    solver.close()
+    ts = Solver(0, timing=True)
+    ts.set_tuning(**tuned)
+    run(ts, 1, 1)
+    ts.clear_timing()
+    ms_events = run(ts, args.steps, 0)
+    timing = ts.timing()
+    ts.close()
+    kinds = {k: v for k, v in timing.items() if v[1] > 0}
+    dom = max(kinds, key=lambda k: kinds[k][0])
+    tot_ms, launches = kinds[dom]
+    bound, work, unit, peak = kernel_work(dom, stats, 0, launches / args.steps)
+    avg_s = tot_ms * 1e-3 / launches
+    scale = 1e9 if unit == "GB/s" else 1e12
+    line = {
+        "metric": METRIC, "value": nominal / (ms * 1e-3) / 1e9, "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "problems": len(sizes), "sum_n": tot, "leaf_size": 32},
+        "autotuned": {"tuning": tuned, "ms_per_step_default": ms_default, "tuning_seconds": tune_s},
+        "nominal_flops": nominal, "update_flops": stats["update_flops"], "roots": stats["roots"],
+        "secular_iters_per_root": stats["secular_evals"] / max(stats["roots"], 1), "info": info,
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in sorted(kinds.items())},
+        "ms_per_step_kernel_by_kernel": ms_events,
+        "roofline": {"bound": bound, "kernel": dom, "achieved": work / avg_s / scale, "peak": peak / scale,
+                     "unit": unit, "frac": work / avg_s / peak, "traffic": None, "avg_launch_ms": avg_s * 1e3,
+                     "share_of_step": tot_ms / args.steps / ms_events},
+        "checks": batch_checks(sizes, d, e, *out),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(n: int):
     import numpy as np  # noqa: F401
 
@@ -178,7 +292,15 @@ def main():
     from paper_2508_11467_amd import inputs
     from paper_2508_11467_amd.api import Solver
 
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     desc, n = WORKLOADS[args.workload]
+    if args.workload == "batch2000":
+        return bench_batched(args, desc)
     d, e = inputs.workload(args.workload)
     dev = torch.device("cuda:0")
     dt = torch.from_numpy(d).to(dev)
@@ -218,10 +340,11 @@ def main():
                  **accuracy(d, e, sig, ub.T, vb.T)}
 
     # the same solves with the learned start
-    ls = Solver(0, start="learned")
-    ms_learned = time_solver(ls, dt, et, (sig, ub, vb), args.steps, args.warmup)
-    info_l, stats_l = ls.info()
-    ls.close()
+    if not args.no_learned:
+        ls = Solver(0, start="learned")
+        ms_learned = time_solver(ls, dt, et, (sig, ub, vb), args.steps, args.warmup)
+        info_l, stats_l = ls.info()
+        ls.close()
 
     # timed region 2: the same steps launched kernel by kernel, each launch
     # bracketed by HIP events on the solve's stream (per-kernel durations)
@@ -249,6 +372,7 @@ def main():
     avg_s = tot_ms * 1e-3 / launches
     achieved = work / avg_s
     scale = 1e9 if unit == "GB/s" else 1e12
+    traffic = measured_traffic(args.workload, dom)
     roofline = {
         "bound": bound,
         "kernel": dom,
@@ -256,7 +380,7 @@ def main():
         "peak": peak / scale,
         "unit": unit,
         "frac": achieved / peak,
-        "traffic": None,
+        "traffic": traffic,
         "avg_launch_ms": avg_s * 1e3,
         "share_of_step": tot_ms / args.steps / ms_events,
     }
@@ -289,14 +413,15 @@ def main():
     line["accuracy"] = acc_fp64
     if ozaki is not None:
         line["ozaki"] = ozaki
-    line["learned"] = {
-        "ms_per_step": ms_learned,
-        "value": nominal / (ms_learned * 1e-3) / 1e9,
-        "secular_iters_per_root": stats_l["secular_evals"] / max(stats_l["roots"], 1),
-        "secular_iters_per_root_plain": iters_per_root,
-        "roots": stats_l["roots"],
-        "info": info_l,
-    }
+    if not args.no_learned:
+        line["learned"] = {
+            "ms_per_step": ms_learned,
+            "value": nominal / (ms_learned * 1e-3) / 1e9,
+            "secular_iters_per_root": stats_l["secular_evals"] / max(stats_l["roots"], 1),
+            "secular_iters_per_root_plain": iters_per_root,
+            "roots": stats_l["roots"],
+            "info": info_l,
+        }
     if not args.no_config5 and args.workload == "n16384_normal":
         del sig, ub, vb
         torch.cuda.empty_cache()

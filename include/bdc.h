@@ -227,6 +227,34 @@ int bdc_step_vectors(bdc_handle_t handle, int N, const double* d, const double* 
 int bdc_step_gemm(bdc_handle_t handle, int M, int N, int K, const double* A, int lda,
                   const double* B, int ldb, double* C, int ldc, bdc_stream_t stream);
 
+/* ---- launch tuning ---------------------------------------------------------
+ * Launch shapes of the vector-update products.  The autotuner times a small
+ * set of candidates on the caller's own problem (or batch) and keeps the
+ * fastest in the handle; results satisfy the same tolerances with any
+ * tuning. */
+typedef struct {
+  int small_n;  /* merges with at most this many kept values use 64 x 64 output
+                   tiles, larger ones 128 x 128 (32..4096; default 96) */
+  int flat;     /* 1: all tiles of a merge level in one flattened list walked by a
+                   persistent grid; 0 (default): a grid slice per merge */
+  int grid64;   /* workgroups of the 64-tile product (flat), or half the per-merge cap */
+  int grid128;  /* the same for the 128-tile product */
+  int sec_small_n; /* secular problems with at most this many roots (0..64; default 0)
+                      are solved with 8 lanes per root and no workgroup barriers */
+  float ms;     /* out (bdc_autotune): time per solve of the chosen tuning */
+} bdc_tuning_t;
+
+int bdc_get_tuning(bdc_handle_t handle, bdc_tuning_t* tuning);
+int bdc_set_tuning(bdc_handle_t handle, const bdc_tuning_t* tuning);
+/* Times every candidate tuning on bdc_svd_batched(batch, sizes, d, e, sigma,
+ * U, VT) (arguments as there; a single problem is batch = 1): one warm-up and
+ * `repeats` timed solves each, with HIP events on `stream`.  Keeps the
+ * fastest in the handle and returns it in *best.  Synchronous: waits for the
+ * stream.  The outputs hold the last solve's results. */
+int bdc_autotune(bdc_handle_t handle, int64_t batch, const int64_t* sizes, const double* d,
+                 const double* e, double* sigma, double* U, double* VT, bdc_stream_t stream,
+                 int repeats, bdc_tuning_t* best);
+
 /* ---- learned start of the secular iteration ------------------------------
  * The paper solves each secular equation with LAPACK's lasd4; this build
  * adds an optional learned first point: a 19 -> 64 -> 64 -> 64 -> 1 MLP

@@ -67,6 +67,20 @@ class Stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("small_n", c_int),
+        ("flat", c_int),
+        ("grid64", c_int),
+        ("grid128", c_int),
+        ("sec_small_n", c_int),
+        ("ms", ctypes.c_float),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "bdc_default_options": (None, [ctypes.POINTER(Options)]),
@@ -92,6 +106,10 @@ SIGNATURES = {
     "bdc_mlp_train": (c_int, [c_vp, c_vp, c_vp, c_vp, c_i64, c_i64, ctypes.c_float, c_vp, c_vp]),
     "bdc_set_harvest": (c_int, [c_vp, c_vp, c_vp, c_vp, c_i64, c_vp]),
     "bdc_step_gemm_ozaki": (c_int, [c_vp, c_int, c_int, c_int, c_int, c_vp, c_int, c_vp, c_int, c_vp, c_int, c_vp]),
+    "bdc_get_tuning": (c_int, [c_vp, ctypes.POINTER(Tuning)]),
+    "bdc_set_tuning": (c_int, [c_vp, ctypes.POINTER(Tuning)]),
+    "bdc_autotune": (c_int, [c_vp, c_i64, ctypes.POINTER(c_i64), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_int,
+                             ctypes.POINTER(Tuning)]),
     "bdc_status_string": (c_char_p, [c_int]),
 }
 

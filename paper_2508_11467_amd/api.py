@@ -101,7 +101,7 @@ class Solver:
                                           _ptr(vb), self._stream()))
         return sigma, ub.T, vb.T
 
-    def svd_batched(self, sizes, d, e):
+    def svd_batched(self, sizes, d, e, out=None):
         """Many bidiagonals in one call.  d, e packed at offsets sum(n_j);
         returns (sigma packed like d, U packed, VT packed), where problem i's
         U is ``U[mo_i : mo_i + n_i*n_i].view(n_i, n_i).T`` with
@@ -112,9 +112,12 @@ class Solver:
         e = _f64(e, self.device)
         tot = sum(sizes)
         tot2 = sum(x * x for x in sizes)
-        sigma = torch.empty(tot, dtype=torch.float64, device=self.device)
-        U = torch.empty(tot2, dtype=torch.float64, device=self.device)
-        VT = torch.empty(tot2, dtype=torch.float64, device=self.device)
+        if out is None:
+            sigma = torch.empty(tot, dtype=torch.float64, device=self.device)
+            U = torch.empty(tot2, dtype=torch.float64, device=self.device)
+            VT = torch.empty(tot2, dtype=torch.float64, device=self.device)
+        else:
+            sigma, U, VT = out
         check("bdc_svd_batched", self.lib.bdc_svd_batched(self.handle, len(sizes), arr, _ptr(d), _ptr(e),
                                                           _ptr(sigma), _ptr(U), _ptr(VT), self._stream()))
         return sigma, U, VT
@@ -138,6 +141,38 @@ class Solver:
 
     def clear_timing(self) -> None:
         check("bdc_clear_timing", self.lib.bdc_clear_timing(self.handle))
+
+    # ---------------------------------------------------------------- tuning
+    def tuning(self) -> dict:
+        t = _lib.Tuning()
+        check("bdc_get_tuning", self.lib.bdc_get_tuning(self.handle, ctypes.byref(t)))
+        d = t.as_dict()
+        d.pop("ms")
+        return d
+
+    def set_tuning(self, small_n: int, flat: int, grid64: int, grid128: int, sec_small_n: int = 0,
+                   **_ignored) -> None:
+        t = _lib.Tuning(small_n, flat, grid64, grid128, sec_small_n, 0.0)
+        check("bdc_set_tuning", self.lib.bdc_set_tuning(self.handle, ctypes.byref(t)))
+
+    def autotune(self, sizes, d, e, out=None, repeats: int = 2) -> dict:
+        """Time the candidate launch tunings on this workload (a batch given by
+        ``sizes`` with packed d, e) and keep the fastest; returns it."""
+        sizes = [int(x) for x in sizes]
+        arr = (ctypes.c_int64 * max(1, len(sizes)))(*sizes)
+        d = _f64(d, self.device)
+        e = _f64(e, self.device)
+        tot = sum(sizes)
+        tot2 = sum(x * x for x in sizes)
+        if out is None:
+            out = (torch.empty(tot, dtype=torch.float64, device=self.device),
+                   torch.empty(tot2, dtype=torch.float64, device=self.device),
+                   torch.empty(tot2, dtype=torch.float64, device=self.device))
+        best = _lib.Tuning()
+        check("bdc_autotune", self.lib.bdc_autotune(self.handle, len(sizes), arr, _ptr(d), _ptr(e), _ptr(out[0]),
+                                                    _ptr(out[1]), _ptr(out[2]), self._stream(), repeats,
+                                                    ctypes.byref(best)))
+        return best.as_dict()
 
     # ---------------------------------------------------------------- learned start
     def mlp_set(self, params) -> None:

@@ -30,6 +30,19 @@ SOURCES = {
 }
 
 
+def source_hash() -> str:
+    """SHA-256 of the kernel and ABI sources (identifies a build's kernels)."""
+    import hashlib
+    h = hashlib.sha256()
+    for d in (CSRC, INCLUDE):
+        for name in sorted(os.listdir(d)):
+            if name.endswith((".hip", ".h", ".cpp")):
+                h.update(name.encode())
+                with open(os.path.join(d, name), "rb") as f:
+                    h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def rocm() -> str:
     return os.environ.get("ROCM_PATH", "/opt/rocm")
 

@@ -95,6 +95,7 @@ struct bdc_handle_s {
   int part_cap = 0;
   Harvest hv{};
   bool harvest = false;
+  Tuning tune{96, 0, 1024, 512, 0};
 };
 
 namespace {
@@ -167,7 +168,8 @@ int make_plan(bdc_handle_t h, const int64_t* sizes, int64_t batch) {
     vo += n;
     mo += n * n;
     co += n;
-    to += ((n + 63) / 64) * ((n + 63) / 64);
+    const int64_t nt = (n + 63) / 64;
+    to += nt * ((nt + kVtTilesPerGroup - 1) / kVtTilesPerGroup);  // V^T work items
   }
   p.total_n = vo;
   p.total_n2 = mo;
@@ -233,7 +235,7 @@ int ensure_workspace(bdc_handle_t h, int64_t tn, int64_t tn2, int nnodes) {
   const size_t nd_ = (size_t)std::max(nnodes, 1);
   size_t bytes = 4 * align_up(N2 * 8) + 8 * align_up(N1 * 8) + align_up(2 * N1 * 8) +
                  19 * align_up(N1 * 4) + 2 * align_up(2 * N1 * 4) + align_up(N1 * 4) +
-                 align_up(nd_ * sizeof(NodeState)) + align_up(sizeof(Ctl));
+                 2 * align_up((nd_ + 1) * 4) + align_up(nd_ * sizeof(NodeState)) + align_up(sizeof(Ctl));
   if (h->opt.workspace_cap_bytes && bytes > h->opt.workspace_cap_bytes) return BDC_ERR_NOMEM;
   if (h->arena) {
     if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
@@ -291,6 +293,8 @@ int ensure_workspace(bdc_handle_t h, int64_t tn, int64_t tn2, int nnodes) {
   w.rot_pos = (int32_t*)take(2 * N1 * 4);
   w.rot_col = (int32_t*)take(2 * N1 * 4);
   w.xs = (float*)take(N1 * 4);
+  w.tile_off64 = (int*)take((nd_ + 1) * 4);
+  w.tile_off128 = (int*)take((nd_ + 1) * 4);
   w.st = (NodeState*)take(nd_ * sizeof(NodeState));
   w.ctl = (Ctl*)take(sizeof(Ctl));
   h->cap_n = tn;
@@ -389,6 +393,8 @@ int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, do
   w.mlp_pk = learned ? h->mlp_pk : nullptr;
   const bool ozaki = h->opt.gemm == BDC_GEMM_OZAKI && p.nprob == 1 && h->oz_arena;
   w.oz.min_n = ozaki ? h->opt.ozaki_min_n : INT32_MAX;
+  w.small_n = h->tune.small_n;
+  w.sec_small_n = h->tune.sec_small_n;
   {
     Timer t(h, st, kReset);
     launch_reset(w.ctl, w.st, p.nnodes, st);
@@ -410,7 +416,7 @@ int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, do
     { Timer t(h, st, kLowner); launch_lowner(L.dev, L.nnodes, L.max_m, w, st); }
     { Timer t(h, st, kVectors); launch_vectors(L.dev, L.nnodes, L.max_m, w, st); }
     { Timer t(h, st, kOrder); launch_order(L.dev, L.nnodes, L.max_m, w, st); }
-    { Timer t(h, st, kUpdate); launch_update(L.dev, L.nnodes, L.max_m, w, st); }
+    { Timer t(h, st, kUpdate); launch_update(L.dev, L.nnodes, L.max_m, w, h->tune, st); }
     if (ozaki && L.max_m >= w.oz.min_n) {
       Timer t(h, st, kUpdateOz);
       launch_update_ozaki(L.dev, L.nnodes, L.max_m, w, st);
@@ -480,6 +486,8 @@ int solve(bdc_handle_t h, int64_t batch, const int64_t* sizes, const double* d, 
 }
 
 }  // namespace
+
+int bdc::handle_sec_small(bdc_handle_t h) { return valid(h) ? h->tune.sec_small_n : 0; }
 
 int bdc::handle_info(bdc_handle_t h, int* device, int* max_secular_iters, int* max_leaf_sweeps) {
   if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
@@ -666,6 +674,92 @@ int bdc_clear_timing(bdc_handle_t h) {
   h->recs.clear();
   h->pool_used = 0;
   return BDC_OK;
+}
+
+// ---- launch tuning -----------------------------------------------------------
+
+namespace {
+bool tuning_valid(const bdc_tuning_t* t) {
+  return t->small_n >= 32 && t->small_n <= 4096 && (t->flat == 0 || t->flat == 1) && t->grid64 >= 1 &&
+         t->grid64 <= 65535 && t->grid128 >= 1 && t->grid128 <= 65535 && t->sec_small_n >= 0 &&
+         t->sec_small_n <= 64;
+}
+}  // namespace
+
+int bdc_get_tuning(bdc_handle_t h, bdc_tuning_t* t) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  if (!t) return -2;
+  t->small_n = h->tune.small_n;
+  t->flat = h->tune.flat;
+  t->grid64 = h->tune.grid64;
+  t->grid128 = h->tune.grid128;
+  t->sec_small_n = h->tune.sec_small_n;
+  return BDC_OK;
+}
+
+int bdc_set_tuning(bdc_handle_t h, const bdc_tuning_t* t) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  if (!t || !tuning_valid(t)) return -2;
+  DeviceGuard g(h->device);
+  if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
+  drop_graph(h);  // launch shapes are part of a captured sequence
+  h->tune = Tuning{t->small_n, t->flat, t->grid64, t->grid128, t->sec_small_n};
+  return BDC_OK;
+}
+
+int bdc_autotune(bdc_handle_t h, int64_t batch, const int64_t* sizes, const double* d, const double* e,
+                 double* sigma, double* U, double* VT, bdc_stream_t stream, int repeats, bdc_tuning_t* best) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  if (repeats < 1 || repeats > 100) return -10;
+  if (!best) return -11;
+  DeviceGuard g(h->device);
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<Tuning> cand;
+  for (int ss : {0, 64})
+    for (int sn : {64, 96, 192}) {
+      cand.push_back(Tuning{sn, 0, 1024, 512, ss});
+      for (int gm : {256, 512, 1024}) cand.push_back(Tuning{sn, 1, 2 * gm, gm, ss});
+    }
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    return BDC_ERR_HIP;
+  }
+  const Tuning keep = h->tune;
+  float best_ms = -1.0f;
+  Tuning best_t = keep;
+  int rc = BDC_OK;
+  for (const Tuning& c : cand) {
+    if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
+    drop_graph(h);
+    h->tune = c;
+    rc = bdc_svd_batched(h, batch, sizes, d, e, sigma, U, VT, stream);  // warm-up (and capture)
+    if (rc != BDC_OK) break;
+    (void)hipEventRecord(a, st);
+    for (int r = 0; r < repeats && rc == BDC_OK; ++r) rc = bdc_svd_batched(h, batch, sizes, d, e, sigma, U, VT, stream);
+    (void)hipEventRecord(b, st);
+    if (rc != BDC_OK || hipEventSynchronize(b) != hipSuccess) {
+      rc = rc != BDC_OK ? rc : BDC_ERR_HIP;
+      break;
+    }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    if (best_ms < 0.0f || ms < best_ms) {
+      best_ms = ms;
+      best_t = c;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  drop_graph(h);
+  h->tune = rc == BDC_OK ? best_t : keep;
+  best->small_n = h->tune.small_n;
+  best->flat = h->tune.flat;
+  best->grid64 = h->tune.grid64;
+  best->grid128 = h->tune.grid128;
+  best->sec_small_n = h->tune.sec_small_n;
+  best->ms = rc == BDC_OK ? best_ms / repeats : 0.0f;
+  return rc;
 }
 
 // ---- learned start ---------------------------------------------------------

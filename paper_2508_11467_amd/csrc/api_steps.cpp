@@ -80,6 +80,8 @@ Work make_work(Tmp& t, int64_t n) {
   w.st = t.alloc<NodeState>(1);
   w.ctl = t.alloc<Ctl>(1);
   w.oz.min_n = INT32_MAX;
+  w.small_n = 96;
+  w.sec_small_n = 0;
   w.max_secular_iters = 64;
   w.max_leaf_sweeps = 40;
   return w;
@@ -241,6 +243,7 @@ int bdc_step_secular_start(bdc_handle_t h, int N, const double* d, const double*
   w.iters = iters;
   w.xs = const_cast<float*>(xstart);  // read only by the secular kernel
   w.max_secular_iters = msi;
+  w.sec_small_n = bdc::handle_sec_small(h);
   std::vector<double> zh(N);
   if (hipMemcpy(zh.data(), z, sizeof(double) * N, hipMemcpyDeviceToHost) != hipSuccess) return BDC_ERR_HIP;
   double rho = 0.0;

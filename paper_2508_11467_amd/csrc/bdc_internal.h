@@ -26,6 +26,8 @@
 namespace bdc {
 
 constexpr int kMaxLeaf = 32;
+// 64-column tiles of one 64-row band of V^T handled by one final-pass workgroup
+constexpr int kVtTilesPerGroup = 16;
 // flags of a column touched by a deflation rotation
 constexpr int kRotV = 1;  // its right vector (both deflation rotations)
 constexpr int kRotU = 2;  // its left vector (close-pair rotations only)
@@ -130,6 +132,10 @@ struct Work {
   const unsigned short* mlp_pk;  // packed network for the in-kernel learned start,
                                  // or nullptr
   OzWork oz;
+  int small_n;        // update products of merges with N <= small_n use 64 x 64 tiles
+  int sec_small_n;    // secular problems with N <= sec_small_n use the 8-lane kernel
+  int* tile_off64;    // flattened tile schedule of a level (nnodes + 1 each)
+  int* tile_off128;
   NodeState* st;
   Ctl* ctl;
   int max_secular_iters;
@@ -145,6 +151,15 @@ struct Harvest {
   unsigned long long* count;
 };
 
+// Launch configuration picked by the autotuner (see bdc_tuning_t).
+struct Tuning {
+  int small_n;  // 64 x 64 tiles for merges with N <= small_n, else 128 x 128
+  int flat;     // 1: persistent grids over a flattened tile list; 0: grid per node
+  int grid64;   // workgroups of the 64-tile update (flat), or twice the per-node cap
+  int grid128;
+  int sec_small_n;  // secular problems with N <= this (at most 64) use 8 lanes per root
+};
+
 // ---- launchers (defined next to their kernels) ----
 void launch_reset(Ctl* ctl, NodeState* st, int nnodes, hipStream_t st_);
 void launch_leaf(const LeafDesc* leaves, int nleaves, const Work& w, hipStream_t st);
@@ -155,13 +170,16 @@ void launch_secular(const NodeDesc* nodes, int nnodes, int max_m, const Work& w,
 void launch_lowner(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
 void launch_vectors(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
 void launch_order(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
-void launch_update(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
+void launch_update(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, const Tuning& tu,
+                   hipStream_t st);
 void launch_final(const int64_t* prob_n, const int64_t* prob_vec, const int64_t* prob_mat,
                   const int64_t* col_off, const int64_t* tile_off, int nprob, int64_t total_cols,
                   int64_t total_tiles, const Work& w, double* sigma, double* U, double* VT,
                   hipStream_t st);
 // device and iteration options of a handle (BDC_OK or BDC_ERR_INVALID_HANDLE)
 int handle_info(bdc_handle_t h, int* device, int* max_secular_iters, int* max_leaf_sweeps);
+// the handle's secular small-problem threshold (launch tuning)
+int handle_sec_small(bdc_handle_t h);
 
 size_t mlp_pack_bytes();
 void launch_mlp_pack(const float* params, unsigned short* packed, hipStream_t st);

@@ -64,4 +64,38 @@ __device__ inline void block_exscan(int (&v)[K], int (&total)[K], int* sh) {
   __syncthreads();
 }
 
+// The same for a block of BS threads (a multiple of 64): sh holds BS*K ints.
+template <int K, int BS>
+__device__ inline void block_exscan_n(int (&v)[K], int (&total)[K], int* sh) {
+  const int t = threadIdx.x;
+  __syncthreads();
+  for (int q = 0; q < K; ++q) sh[q * BS + t] = v[q];
+  __syncthreads();
+  for (int off = 1; off < BS; off <<= 1) {
+    int add[K];
+    for (int q = 0; q < K; ++q) add[q] = t >= off ? sh[q * BS + t - off] : 0;
+    __syncthreads();
+    for (int q = 0; q < K; ++q) sh[q * BS + t] += add[q];
+    __syncthreads();
+  }
+  for (int q = 0; q < K; ++q) {
+    total[q] = sh[q * BS + BS - 1];
+    v[q] = sh[q * BS + t] - v[q];
+  }
+  __syncthreads();
+}
+
+// Block sum for BS threads; the wave sums are added in wave order.
+template <int BS>
+__device__ inline double block_sum_n(double v, double* sh /* >= BS/64 */) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int q = 0; q < BS / 64; ++q) s += sh[q];
+  return s;
+}
+
 }  // namespace bdc

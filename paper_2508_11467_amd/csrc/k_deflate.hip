@@ -157,11 +157,12 @@ __global__ __launch_bounds__(256) void k_zsort(const NodeDesc* __restrict__ node
 // candidate's value, computed in parallel; only the z accumulation along a
 // run of close pairs (kept value followed by the values merged into it) and
 // the rotations into z_1 stay sequential, one thread per run.
-__global__ __launch_bounds__(256) void k_prep(const NodeDesc* __restrict__ nodes, Work w) {
-  __shared__ double shd[8];
-  __shared__ int shi[kBlock * 6];
-  __shared__ double shl[kBlock];
-  __shared__ int shh[kBlock];
+template <int BS>
+__global__ __launch_bounds__(BS) void k_prep(const NodeDesc* __restrict__ nodes, Work w) {
+  __shared__ double shd[BS / 64];
+  __shared__ int shi[BS * 6];
+  __shared__ double shl[BS];
+  __shared__ int shh[BS];
   __shared__ int sh_cnt[4];
 
   const NodeDesc nd = nodes[blockIdx.x];
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(256) void k_prep(const NodeDesc* __restrict__ nodes
   const int64_t rb = 2 * vo;
 
   // positions 1..m-1 in contiguous segments, one per thread
-  const int per = (m - 1 + kBlock - 1) / kBlock;
+  const int per = (m - 1 + BS - 1) / BS;
   const int b0 = min(m, 1 + t * per);
   const int b1 = min(m, b0 + per);
 
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(256) void k_prep(const NodeDesc* __restrict__ nodes
   shl[t] = seg_last;
   shh[t] = seg_has;
   __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
+  for (int off = 1; off < BS; off <<= 1) {
     double lv = 0.0;
     int lh = 0;
     if (t >= off) {
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(256) void k_prep(const NodeDesc* __restrict__ nodes
       hp = 1;
     }
   }
-  block_exscan<3>(cnt, tot, shi);
+  block_exscan_n<3, BS>(cnt, tot, shi);
   const int nzero = tot[0], ncand = tot[1], nclose = tot[2];
   // pass 2: statuses, lists, rotation slots of the followers
   {
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(256) void k_prep(const NodeDesc* __restrict__ nodes
     w.ps_z[vo] = z0;
   }
   // runs of close pairs: each kept candidate absorbs the followers after it
-  for (int u = t; u < ncand; u += kBlock) {
+  for (int u = t; u < ncand; u += BS) {
     const int pp = w.cand[vo + nzero + u];
     if (w.status[vo + pp] != 0) continue;
     double zl = w.ps_z[vo + pp], dl = w.ps_d[vo + pp];
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(256) void k_prep(const NodeDesc* __restrict__ nodes
   // ---- kept values (ascending), the update order [left | d=0 | both | right]
   // and the deflated values in ascending order (the zeros of the d~0 case
   // first, then the rest in scan order)
-  const int per2 = (m + kBlock - 1) / kBlock;
+  const int per2 = (m + BS - 1) / BS;
   const int p0 = t * per2, p1 = min(m, p0 + per2);
   int cv[6] = {0, 0, 0, 0, 0, 0}, tot6[6];
   for (int pos = p0; pos < p1; ++pos) {
@@ -344,7 +345,7 @@ __global__ __launch_bounds__(256) void k_prep(const NodeDesc* __restrict__ nodes
       ++cv[5];
     }
   }
-  block_exscan<6>(cv, tot6, shi);
+  block_exscan_n<6, BS>(cv, tot6, shi);
   const int N = tot6[0], n1 = tot6[1], n2 = tot6[2], n3 = tot6[3], nz = tot6[4];
   double rho = 0.0;
   for (int pos = p0; pos < p1; ++pos) {
@@ -375,11 +376,11 @@ __global__ __launch_bounds__(256) void k_prep(const NodeDesc* __restrict__ nodes
       w.drot[vo + q] = w.ps_rot[vo + pos];
     }
   }
-  rho = block_sum(rho, shd);
+  rho = block_sum_n<BS>(rho, shd);
 
   // ---- x1 and y in place: rotate the children's null vectors (V columns
   // r0+k-1 and r0+m) by (c0, s0) over the node's rows
-  for (int row = t; row < m + s; row += kBlock) {
+  for (int row = t; row < m + s; row += BS) {
     const int64_t gr = r0 + row;
     const double q1 = row < k ? V[gr + (int64_t)(r0 + k - 1) * ld] : 0.0;
     const double q2 = (s && row >= k) ? V[gr + (int64_t)(r0 + m) * ld] : 0.0;
@@ -419,7 +420,9 @@ void launch_prep(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hi
   const int cap = 4096 / nnodes;
   if (gy > cap) gy = cap > 0 ? cap : 1;
   hipLaunchKernelGGL(k_zsort, dim3(nnodes, gy), dim3(kBlock), 0, st, nodes, w);
-  hipLaunchKernelGGL(k_prep, dim3(nnodes), dim3(kBlock), 0, st, nodes, w);
+  // large merges: 1024 threads, a quarter of the sequential segment per thread
+  if (max_m >= 2048) hipLaunchKernelGGL(k_prep<1024>, dim3(nnodes), dim3(1024), 0, st, nodes, w);
+  else hipLaunchKernelGGL(k_prep<256>, dim3(nnodes), dim3(256), 0, st, nodes, w);
 }
 
 }  // namespace bdc

@@ -23,6 +23,8 @@
 //   k_vectors  singular vectors of M~ (eq. M-svd-vec), one workgroup per root
 //              column, written in the row order of the vector update and
 //              normalised in place.
+#include <type_traits>
+
 #include "bdc_internal.h"
 #include "block_util.h"
 #include "mlp_device.h"
@@ -84,6 +86,140 @@ __device__ inline void sum_terms(const double* __restrict__ dj, const double* __
   }
 }
 
+// One root's iteration state (one lane).  The start, the origin choice, the
+// model step, the safeguard, the stopping rule and the learned start's
+// re-referencing are the same in both secular kernels.
+struct Root {
+  int i, lp, rp, o, iters, capped;
+  bool last, need, first;
+  double dl, dr, ov, tau, lo, hi, mu, base_v, h;
+
+  __device__ void init(const double* __restrict__ d, int N, double rho, double z0, int i_, bool active,
+                       bool learned, float xp) {
+    i = i_;
+    last = i == N - 1;
+    lp = active ? (last ? N - 2 : i) : 0;  // left model pole
+    rp = lp + 1;
+    dl = dr = ov = tau = lo = hi = mu = base_v = h = 0.0;
+    o = iters = capped = 0;
+    need = active && N > 1;
+    first = true;
+    if (active && N == 1) tau = fabs(z0);  // f = 1 - z^2/omega^2: omega = |z| exactly
+    if (!need) return;
+    dl = d[lp];
+    dr = d[rp];
+    if (learned) {
+      // first evaluation at the proposed position x of the interval; its
+      // half (split at the midpoint in omega^2) gives the origin pole
+      const double x = fmin(fmax((double)xp, 0x1p-20), 1.0 - 0x1p-20);
+      first = false;
+      if (last) {
+        h = rho / (dr + sqrt(dr * dr + rho));
+        o = rp;
+        tau = x * h;
+        lo = 0.0;
+        hi = h;
+      } else {
+        h = dr - dl;
+        mu = 0.5 * (dr - dl) * (dr + dl);
+        const double t0 = x * h;
+        if (t0 * (2.0 * dl + t0) > mu) {
+          o = rp;
+          tau = (x - 1.0) * h;
+          lo = -h;
+          hi = 0.0;
+        } else {
+          o = lp;
+          tau = t0;
+          lo = 0.0;
+          hi = h;
+        }
+      }
+      ov = o == rp ? dr : dl;
+    } else {
+      // first evaluation: the midpoint in omega^2 of the root's interval
+      base_v = last ? dr : dl;
+      mu = last ? 0.5 * rho : 0.5 * (dr - dl) * (dr + dl);
+      ov = base_v;
+      tau = mu / (base_v + sqrt(base_v * base_v + mu));
+    }
+  }
+
+  // After an evaluation f (E = 1 + sum |terms|) at the current point.
+  __device__ void update(double f, double dpsi, double dphi, double E, double rho, int maxit, bool learned) {
+    ++iters;
+    bool conv = fabs(f) <= 8.0 * kEps * E;
+    if (first) {
+      first = false;
+      // origin: the pole nearer the root, by the sign of f at the midpoint
+      const bool go_right = !last && f < 0.0;
+      o = (last || go_right) ? rp : lp;
+      const double wmid = base_v + tau;
+      ov = o == rp ? dr : dl;
+      if (go_right) tau = -mu / (dr + wmid);
+      if (last) {
+        lo = 0.0;
+        hi = rho / (dr + sqrt(dr * dr + rho));
+        if (f < 0.0) lo = tau;
+        else hi = tau;
+      } else if (go_right) {
+        lo = tau;
+        hi = 0.0;
+      } else {
+        lo = 0.0;
+        hi = tau;
+      }
+    } else {
+      if (f < 0.0) lo = tau;
+      else hi = tau;
+    }
+    if (!conv && iters < maxit) {
+      // two-pole rational model at the current point
+      const double Dl = ((dl - ov) - tau) * ((dl + ov) + tau);
+      const double Dr = ((dr - ov) - tau) * ((dr + ov) + tau);
+      const double c = f - Dl * dpsi - Dr * dphi;
+      const double a = (Dl + Dr) * f - Dl * Dr * (dpsi + dphi);
+      const double b = Dl * Dr * f;
+      const double disc = sqrt(fabs(a * a - 4.0 * b * c));
+      double eta;
+      if (c == 0.0) eta = b / a;
+      else if (last) eta = (a >= 0.0) ? (a + disc) / (2.0 * c) : 2.0 * b / (a - disc);
+      else eta = (a <= 0.0) ? (a - disc) / (2.0 * c) : 2.0 * b / (a + disc);
+      const double om = ov + tau;
+      const double omn = sqrt(om * om + eta);
+      double tn = tau + eta / (om + omn);
+      if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+      // a step at the rounding level is accepted without another evaluation
+      if (fabs(tn - tau) <= 2.0 * kEps * fabs(tn)) conv = true;
+      tau = tn;
+      if (learned && !last) {
+        // an iterate that crossed the midpoint is re-referenced to the
+        // other pole and evaluated there before it may stop
+        if (o == lp && tau * (2.0 * dl + tau) > mu) {
+          o = rp;
+          ov = dr;
+          tau -= h;
+          lo -= h;
+          hi -= h;
+          conv = false;
+        } else if (o == rp && tau * (2.0 * dr + tau) < -mu) {
+          o = lp;
+          ov = dl;
+          tau += h;
+          lo += h;
+          hi += h;
+          conv = false;
+        }
+      }
+    }
+    if (!conv && iters >= maxit) capped = 1;
+    need = !conv && iters < maxit;
+  }
+};
+
+// Largest secular problem the 8-lanes-per-root kernel takes.
+constexpr int kSmallSec = 64;
+
 // Pole staging of the secular kernel; with the in-kernel learned start the
 // network's weights and activations share its LDS (they are done with before
 // the poles are staged).
@@ -108,15 +244,43 @@ struct SecLds<2> {
   };
 };
 
+// The network's proposals for roots base .. base+63 into xs (all threads of
+// the workgroup; LDS of m is free afterwards).
+__device__ void learned_proposals(const Work& w, MlpShared& m, const double* __restrict__ d,
+                                  const double* __restrict__ z, int N, double rho, int base, float* xs) {
+  FeatLds& F = *reinterpret_cast<FeatLds*>(m.A.a1);
+  const int B = far_block(N);
+  stage_packed(w.mlp_pk, m.W);
+  for (int q = threadIdx.x; q < kRows * kFP; q += blockDim.x) m.A.a0[q] = 0;
+  far_moments(d, z, N, B, F);
+  __syncthreads();
+  block_features(d, z, N, rho, base, B, F, [&](int r, int q, float v) { m.A.a0[r * kFP + q] = bf16_bits(v); });
+  forward_fast(m.W, m.A, xs);
+}
+
+// Evaluation counters of a wavefront's roots.
+__device__ inline void count_roots(const Work& w, int N, int iters, int capped) {
+  int it_sum = iters, cap_sum = capped;
+  for (int off = 32; off > 0; off >>= 1) {
+    it_sum += __shfl_xor(it_sum, off, 64);
+    cap_sum += __shfl_xor(cap_sum, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&w.ctl->secular_evals, (unsigned long long)it_sum);
+    atomicAdd(&w.ctl->secular_terms, (unsigned long long)it_sum * (unsigned long long)N);
+    if (cap_sum) atomicAdd(&w.ctl->secular_capped, cap_sum);
+  }
+}
+
 // Start of the iteration: 0 the interval midpoint, 1 a caller-given position
 // (w.xs), 2 the network's proposal computed here (w.mlp_pk).
 //
-// Secular roots of one node: 64 roots per workgroup, one per lane; the four
-// wavefronts each sum a quarter of the poles for all 64 roots (staged in LDS,
-// read by every lane at the same address), and wavefront 0 combines the
-// partial sums -- left-pole sums in ascending quarter order, right-pole sums
-// in descending order, so both stay summed from far to near -- and advances
-// each root's iteration.
+// Secular roots of one node with more than kSmallSec kept values: 64 roots
+// per workgroup, one per lane; the four wavefronts each sum a quarter of the
+// poles for all 64 roots (staged in LDS, read by every lane at the same
+// address), and wavefront 0 combines the partial sums -- left-pole sums in
+// ascending quarter order, right-pole sums in descending order, so both stay
+// summed from far to near -- and advances each root's iteration.
 template <int kMode>
 __global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ nodes, Work w) {
   __shared__ SecLds<kMode> L;
@@ -127,6 +291,7 @@ __global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ no
   __shared__ int b_go;
   const NodeDesc nd = nodes[blockIdx.x];
   const int N = w.st[nd.id].N;
+  if (N <= w.sec_small_n) return;  // solved by k_secular_small
   const double rho = w.st[nd.id].rho;
   const int64_t vo = nd.vec_off + nd.r0;
   const double* __restrict__ d = w.sd + vo;
@@ -152,17 +317,7 @@ __global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ no
     if constexpr (kMode == 2) {
       // the network's proposals for roots base .. base+63, then the poles
       __syncthreads();
-      if (N > 1) {
-        FeatLds& F = *reinterpret_cast<FeatLds*>(L.m.A.a1);
-        const int B = far_block(N);
-        stage_packed(w.mlp_pk, L.m.W);
-        for (int q = t; q < kRows * kFP; q += blockDim.x) L.m.A.a0[q] = 0;
-        far_moments(d, z, N, B, F);
-        __syncthreads();
-        block_features(d, z, N, rho, base, B, F,
-                       [&](int r, int q, float v) { L.m.A.a0[r * kFP + q] = bf16_bits(v); });
-        forward_fast(L.m.W, L.m.A, s_x);
-      }
+      learned_proposals(w, L.m, d, z, N, rho, base, s_x);
       if (resident)
         for (int j = q0 + lane; j < q1; j += 64) {
           cd[wv][j - q0] = d[j];
@@ -171,60 +326,15 @@ __global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ no
     }
     const int i = base + lane;
     const bool active = i < N;
-    const bool last = (i == N - 1);
-    const int lp = active ? (last ? N - 2 : i) : 0;  // left model pole
-    const int rp = lp + 1;
-    double dl = 0.0, dr = 0.0, ov = 0.0, tau = 0.0, lo = 0.0, hi = 0.0, mu = 0.0, base_v = 0.0, h = 0.0;
-    int o = 0, iters = 0, capped = 0;
-    bool need = active && N > 1;
-    bool first = true;
-    if (active && N == 1) tau = fabs(z[0]);  // f = 1 - z^2/omega^2: omega = |z| exactly
-    if (need) {
-      dl = d[lp];
-      dr = d[rp];
-      if (learned) {
-        // first evaluation at the proposed position x of the interval; its
-        // half (split at the midpoint in omega^2) gives the origin pole
-        const float xp = kMode == 2 ? s_x[lane] : w.xs[vo + i];
-        const double x = fmin(fmax((double)xp, 0x1p-20), 1.0 - 0x1p-20);
-        first = false;
-        if (last) {
-          h = rho / (dr + sqrt(dr * dr + rho));
-          o = rp;
-          tau = x * h;
-          lo = 0.0;
-          hi = h;
-        } else {
-          h = dr - dl;
-          mu = 0.5 * (dr - dl) * (dr + dl);
-          const double t0 = x * h;
-          if (t0 * (2.0 * dl + t0) > mu) {
-            o = rp;
-            tau = (x - 1.0) * h;
-            lo = -h;
-            hi = 0.0;
-          } else {
-            o = lp;
-            tau = t0;
-            lo = 0.0;
-            hi = h;
-          }
-        }
-        ov = d[o];
-      } else {
-        // first evaluation: the midpoint in omega^2 of the root's interval
-        base_v = last ? dr : dl;
-        mu = last ? 0.5 * rho : 0.5 * (dr - dl) * (dr + dl);
-        ov = base_v;
-        tau = mu / (base_v + sqrt(base_v * base_v + mu));
-      }
-    }
+    Root R;
+    const float xp = kMode == 2 ? s_x[lane] : (kMode == 1 && active ? w.xs[vo + i] : 0.0f);
+    R.init(d, N, rho, N == 1 ? z[0] : 0.0, i, active, learned, xp);
     for (;;) {
       if (wv == 0) {
-        b_ov[lane] = ov;
-        b_tau[lane] = tau;
-        b_need[lane] = need ? 1 : 0;
-        const int any = __any(need) ? 1 : 0;
+        b_ov[lane] = R.ov;
+        b_tau[lane] = R.tau;
+        b_need[lane] = R.need ? 1 : 0;
+        const int any = __any(R.need) ? 1 : 0;
         if (lane == 0) b_go = any;
       }
       __syncthreads();
@@ -232,7 +342,8 @@ __global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ no
       // ---- partial sums of this wavefront's quarter
       const bool nd_l = b_need[lane] != 0;
       const double eov = b_ov[lane], etau = b_tau[lane];
-      Part L{0.0, 0.0, 0.0}, R{0.0, 0.0, 0.0};
+      const int lp = R.lp;
+      Part PL{0.0, 0.0, 0.0}, PR{0.0, 0.0, 0.0};
       for (int c0 = q0; c0 < q1; c0 += kSecChunk) {
         const int c1 = min(q1, c0 + kSecChunk);
         if (!resident) {
@@ -248,7 +359,7 @@ __global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ no
         if (nd_l) {
           // left poles j <= lp in this chunk, upwards
           const int le = min(c1, lp + 1);
-          if (le > c0) sum_terms(cd[wv], cz[wv], 0, 1, le - c0, eov, etau, L);
+          if (le > c0) sum_terms(cd[wv], cz[wv], 0, 1, le - c0, eov, etau, PL);
         }
       }
       for (int c1 = q1; c1 > q0; c1 -= kSecChunk) {
@@ -266,16 +377,16 @@ __global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ no
         if (nd_l) {
           // right poles j > lp in this chunk, downwards
           const int ls = max(c0, lp + 1);
-          if (c1 > ls) sum_terms(cd[wv], cz[wv], c1 - 1 - c0, -1, c1 - ls, eov, etau, R);
+          if (c1 > ls) sum_terms(cd[wv], cz[wv], c1 - 1 - c0, -1, c1 - ls, eov, etau, PR);
         }
       }
-      part[wv][0][lane] = L.s;
-      part[wv][1][lane] = L.ds;
-      part[wv][2][lane] = R.s;
-      part[wv][3][lane] = R.ds;
-      part[wv][4][lane] = L.E + R.E;
+      part[wv][0][lane] = PL.s;
+      part[wv][1][lane] = PL.ds;
+      part[wv][2][lane] = PR.s;
+      part[wv][3][lane] = PR.ds;
+      part[wv][4][lane] = PL.E + PR.E;
       __syncthreads();
-      if (wv == 0 && need) {
+      if (wv == 0 && R.need) {
         double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, E = 0.0;
         for (int q = 0; q < kSecWaves; ++q) {
           psi += part[q][0][lane];
@@ -287,96 +398,95 @@ __global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ no
           dphi += part[q][3][lane];
         }
         const double f = (1.0 + psi) + phi;
-        E = 1.0 + E;
-        ++iters;
-        bool conv = fabs(f) <= 8.0 * kEps * E;
-        if (first) {
-          first = false;
-          // origin: the pole nearer the root, by the sign of f at the midpoint
-          const bool go_right = !last && f < 0.0;
-          o = (last || go_right) ? rp : lp;
-          const double wmid = base_v + tau;
-          ov = d[o];
-          if (go_right) tau = -mu / (dr + wmid);
-          if (last) {
-            lo = 0.0;
-            hi = rho / (dr + sqrt(dr * dr + rho));
-            if (f < 0.0) lo = tau;
-            else hi = tau;
-          } else if (go_right) {
-            lo = tau;
-            hi = 0.0;
-          } else {
-            lo = 0.0;
-            hi = tau;
-          }
-        } else {
-          if (f < 0.0) lo = tau;
-          else hi = tau;
-        }
-        if (!conv && iters < maxit) {
-          // two-pole rational model at the current point
-          const double Dl = ((dl - ov) - tau) * ((dl + ov) + tau);
-          const double Dr = ((dr - ov) - tau) * ((dr + ov) + tau);
-          const double c = f - Dl * dpsi - Dr * dphi;
-          const double a = (Dl + Dr) * f - Dl * Dr * (dpsi + dphi);
-          const double b = Dl * Dr * f;
-          const double disc = sqrt(fabs(a * a - 4.0 * b * c));
-          double eta;
-          if (c == 0.0) eta = b / a;
-          else if (last) eta = (a >= 0.0) ? (a + disc) / (2.0 * c) : 2.0 * b / (a - disc);
-          else eta = (a <= 0.0) ? (a - disc) / (2.0 * c) : 2.0 * b / (a + disc);
-          const double om = ov + tau;
-          const double omn = sqrt(om * om + eta);
-          double tn = tau + eta / (om + omn);
-          if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-          // a step at the rounding level is accepted without another evaluation
-          if (fabs(tn - tau) <= 2.0 * kEps * fabs(tn)) conv = true;
-          tau = tn;
-          if (learned && !last) {
-            // an iterate that crossed the midpoint is re-referenced to the
-            // other pole and evaluated there before it may stop
-            if (o == lp && tau * (2.0 * dl + tau) > mu) {
-              o = rp;
-              ov = dr;
-              tau -= h;
-              lo -= h;
-              hi -= h;
-              conv = false;
-            } else if (o == rp && tau * (2.0 * dr + tau) < -mu) {
-              o = lp;
-              ov = dl;
-              tau += h;
-              lo += h;
-              hi += h;
-              conv = false;
-            }
-          }
-        }
-        if (!conv && iters >= maxit) capped = 1;
-        need = !conv && iters < maxit;
+        R.update(f, dpsi, dphi, 1.0 + E, rho, maxit, learned);
       }
       __syncthreads();
     }
     if (wv == 0) {
       if (active) {
-        w.o[vo + i] = o;
-        w.tau[vo + i] = tau;
-        w.iters[vo + i] = iters;
+        w.o[vo + i] = R.o;
+        w.tau[vo + i] = R.tau;
+        w.iters[vo + i] = R.iters;
       }
-      int it_sum = iters, cap_sum = capped;
-      for (int off = 32; off > 0; off >>= 1) {
-        it_sum += __shfl_xor(it_sum, off, 64);
-        cap_sum += __shfl_xor(cap_sum, off, 64);
-      }
-      if (lane == 0) {
-        atomicAdd(&w.ctl->secular_evals, (unsigned long long)it_sum);
-        atomicAdd(&w.ctl->secular_terms, (unsigned long long)it_sum * (unsigned long long)N);
-        if (cap_sum) atomicAdd(&w.ctl->secular_capped, cap_sum);
-      }
+      count_roots(w, N, R.iters, R.capped);
     }
     __syncthreads();
   }
+}
+
+// Secular roots of a node with at most kSmallSec kept values: 32 roots per
+// 256-thread workgroup, 8 lanes per root.  Lane `part` of a root sums the
+// poles j = part (mod 8) -- left poles upwards, right poles downwards -- and
+// the 8 partial sums are combined with xor shuffles inside the wavefront, so
+// an evaluation takes about N/8 dependent terms and no workgroup barrier.
+// Every lane of a root then advances the same iteration state.
+constexpr int kSmallLanes = 8;
+constexpr int kSmallRoots = 256 / kSmallLanes;
+struct SmallMlp {
+  MlpShared m;
+};
+
+__device__ inline int count_step(int first, int last, int step) {
+  return first > last ? 0 : (last - first) / step + 1;
+}
+
+template <int kMode>
+__global__ __launch_bounds__(256) void k_secular_small(const NodeDesc* __restrict__ nodes, Work w) {
+  __shared__ double cd[kSmallSec], cz[kSmallSec];
+  __shared__ float s_x[kSecRoots];
+  __shared__ typename std::conditional<kMode == 2, SmallMlp, char>::type M;
+  const NodeDesc nd = nodes[blockIdx.x];
+  const int N = w.st[nd.id].N;
+  const int base = blockIdx.y * kSmallRoots;
+  if (N > w.sec_small_n || base >= N) return;  // uniform over the workgroup
+  const double rho = w.st[nd.id].rho;
+  const int64_t vo = nd.vec_off + nd.r0;
+  const double* __restrict__ d = w.sd + vo;
+  const double* __restrict__ z = w.sz + vo;
+  constexpr bool learned = kMode != 0;
+  const int t = threadIdx.x;
+  if constexpr (kMode == 2) {
+    if (N > 1) learned_proposals(w, M.m, d, z, N, rho, 0, s_x);  // all N <= 64 roots
+  }
+  if (t < N) {
+    cd[t] = d[t];
+    cz[t] = z[t] * z[t];
+  }
+  __syncthreads();
+  const int part = t & (kSmallLanes - 1);
+  const int i = base + t / kSmallLanes;
+  const bool active = i < N;
+  Root R;
+  const float xp = kMode == 2 ? s_x[i & 63] : (kMode == 1 && active ? w.xs[vo + i] : 0.0f);
+  R.init(cd, N, rho, N == 1 ? z[0] : 0.0, i, active, learned, xp);
+  // this lane's poles: left part, part+8, .. <= lp; right from the last
+  // j = part (mod 8) down to the first above lp
+  const int nl = count_step(part, R.lp, kSmallLanes);
+  const int jr = N - 1 - ((N - 1 - part) % kSmallLanes + kSmallLanes) % kSmallLanes;
+  const int jmin = R.lp + 1 + ((part - (R.lp + 1)) % kSmallLanes + kSmallLanes) % kSmallLanes;
+  const int nr = count_step(jmin, jr, kSmallLanes);
+  while (R.need) {
+    Part PL{0.0, 0.0, 0.0}, PR{0.0, 0.0, 0.0};
+    if (nl > 0) sum_terms(cd, cz, part, kSmallLanes, nl, R.ov, R.tau, PL);
+    if (nr > 0) sum_terms(cd, cz, jr, -kSmallLanes, nr, R.ov, R.tau, PR);
+    double E = PL.E + PR.E;
+    for (int off = 1; off < kSmallLanes; off <<= 1) {
+      PL.s += __shfl_xor(PL.s, off, 64);
+      PL.ds += __shfl_xor(PL.ds, off, 64);
+      PR.s += __shfl_xor(PR.s, off, 64);
+      PR.ds += __shfl_xor(PR.ds, off, 64);
+      E += __shfl_xor(E, off, 64);
+    }
+    const double f = (1.0 + PL.s) + PR.s;
+    R.update(f, PL.ds, PR.ds, 1.0 + E, rho, w.max_secular_iters, learned);
+  }
+  const bool writer = active && part == 0;
+  if (writer) {
+    w.o[vo + i] = R.o;
+    w.tau[vo + i] = R.tau;
+    w.iters[vo + i] = R.iters;
+  }
+  count_roots(w, N, writer ? R.iters : 0, writer ? R.capped : 0);
 }
 
 __global__ __launch_bounds__(256) void k_lowner(const NodeDesc* __restrict__ nodes, Work w) {
@@ -468,9 +578,18 @@ void launch_secular(const NodeDesc* nodes, int nnodes, int max_m, const Work& w,
   if (nnodes <= 0) return;
   const int gy = grid_y(nnodes, (max_m + kSecRoots - 1) / kSecRoots, 4096);
   const dim3 grid(nnodes, gy), block(kSecRoots * kSecWaves);
-  if (w.mlp_pk) hipLaunchKernelGGL(k_secular<2>, grid, block, 0, st, nodes, w);
-  else if (w.xs) hipLaunchKernelGGL(k_secular<1>, grid, block, 0, st, nodes, w);
-  else hipLaunchKernelGGL(k_secular<0>, grid, block, 0, st, nodes, w);
+  const dim3 sgrid(nnodes, kSmallSec / kSmallRoots);
+  const bool small = w.sec_small_n > 0, big = max_m > w.sec_small_n;
+  if (w.mlp_pk) {
+    if (small) hipLaunchKernelGGL(k_secular_small<2>, sgrid, dim3(256), 0, st, nodes, w);
+    if (big) hipLaunchKernelGGL(k_secular<2>, grid, block, 0, st, nodes, w);
+  } else if (w.xs) {
+    if (small) hipLaunchKernelGGL(k_secular_small<1>, sgrid, dim3(256), 0, st, nodes, w);
+    if (big) hipLaunchKernelGGL(k_secular<1>, grid, block, 0, st, nodes, w);
+  } else {
+    if (small) hipLaunchKernelGGL(k_secular_small<0>, sgrid, dim3(256), 0, st, nodes, w);
+    if (big) hipLaunchKernelGGL(k_secular<0>, grid, block, 0, st, nodes, w);
+  }
 }
 
 void launch_lowner(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {

@@ -272,9 +272,8 @@ struct NodeStore {
   }
 };
 
-// Nodes whose kept size N is at most kSmallN use 64 x 64 tiles, larger ones
-// 128 x 128; each launch skips the nodes of the other class.
-constexpr int kSmallN = 96;
+// Nodes whose kept size N is at most w.small_n use 64 x 64 tiles, larger ones
+// 128 x 128 (tunable); each launch skips the nodes of the other class.
 
 // grid: (node, tile slot, side-half).  side-half: 0 U rows [0,k), 1 U rows
 // [k,m), 2 V rows [0,k), 3 V rows [k,m+s).  Tiles are visited with the row
@@ -285,7 +284,7 @@ __global__ __launch_bounds__(256) void k_update(const NodeDesc* __restrict__ nod
   const NodeDesc nd = nodes[blockIdx.x];
   const NodeState st = w.st[nd.id];
   const int N = st.N, n1 = st.n1, n2 = st.n2;
-  if ((TM <= 64) != (N <= kSmallN)) return;
+  if ((TM <= 64) != (N <= w.small_n)) return;
   if (N >= w.oz.min_n) return;  // done by the split-precision products
   const int m = nd.m, s = nd.s, k = nd.k, r0 = nd.r0;
   const int64_t ld = nd.ld, vo = nd.vec_off + nd.r0;
@@ -306,6 +305,99 @@ __global__ __launch_bounds__(256) void k_update(const NodeDesc* __restrict__ nod
   for (int tile = blockIdx.y; tile < ntiles; tile += gridDim.y) {
     const int tm = tile % tiles_m, tn = tile / tiles_m;
     gemm_tile<TM, TN>(sm, A, ld, B, ld, rows, N, K, tm * TM, tn * TN, store);
+  }
+}
+
+// ---- flattened schedule: all tiles of a level in one list per tile class.
+// Tiles of a node, sub-half by sub-half (0 U rows [0,k), 1 U rows [k,m),
+// 2 V rows [0,k), 3 V rows [k,m+s)), row index fastest.
+__device__ inline int sub_rows(const NodeDesc& nd, int sub) {
+  const bool isV = sub >= 2, bottom = sub & 1;
+  return bottom ? (isV ? nd.m + nd.s - nd.k : nd.m - nd.k) : nd.k;
+}
+
+template <int T>
+__device__ inline int node_tiles(const NodeDesc& nd, int N) {
+  const int tn = (N + T - 1) / T;
+  int c = 0;
+  for (int sub = 0; sub < 4; ++sub) c += ((sub_rows(nd, sub) + T - 1) / T) * tn;
+  return c;
+}
+
+// Tile offsets of the level's nodes in the 64 and 128 classes
+// (off64/off128[i] .. [i+1]); one workgroup.
+__global__ __launch_bounds__(256) void k_tile_sched(const NodeDesc* __restrict__ nodes, int nnodes, Work w) {
+  __shared__ int sh[2 * kBlock];
+  const int t = threadIdx.x;
+  const int per = (nnodes + kBlock - 1) / kBlock;
+  const int i0 = min(nnodes, t * per), i1 = min(nnodes, i0 + per);
+  int v[2] = {0, 0};
+  for (int i = i0; i < i1; ++i) {
+    const NodeDesc nd = nodes[i];
+    const int N = w.st[nd.id].N;
+    if (N >= w.oz.min_n || N == 0) continue;
+    if (N <= w.small_n) v[0] += node_tiles<64>(nd, N);
+    else v[1] += node_tiles<128>(nd, N);
+  }
+  int tot[2];
+  block_exscan<2>(v, tot, sh);
+  int o64 = v[0], o128 = v[1];
+  for (int i = i0; i < i1; ++i) {
+    w.tile_off64[i] = o64;
+    w.tile_off128[i] = o128;
+    const NodeDesc nd = nodes[i];
+    const int N = w.st[nd.id].N;
+    if (N >= w.oz.min_n || N == 0) continue;
+    if (N <= w.small_n) o64 += node_tiles<64>(nd, N);
+    else o128 += node_tiles<128>(nd, N);
+  }
+  if (t == 0) {
+    w.tile_off64[nnodes] = tot[0];
+    w.tile_off128[nnodes] = tot[1];
+  }
+}
+
+// Persistent form of k_update: a fixed grid walks the level's flattened tile
+// list of its class.
+template <int TM, int TN>
+__global__ __launch_bounds__(256) void k_update_flat(const NodeDesc* __restrict__ nodes, int nnodes, Work w) {
+  __shared__ TileSmem<TM, TN> sm;
+  const int* __restrict__ off = TM <= 64 ? w.tile_off64 : w.tile_off128;
+  const int total = off[nnodes];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    // node holding tile t: last i with off[i] <= t
+    int lo = 0, hi = nnodes;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (off[mid] <= t) lo = mid;
+      else hi = mid;
+    }
+    const NodeDesc nd = nodes[lo];
+    const NodeState st = w.st[nd.id];
+    const int N = st.N, n1 = st.n1, n2 = st.n2;
+    const int tn_count = (N + TN - 1) / TN;
+    int local = t - off[lo];
+    int sub = 0, rows = sub_rows(nd, 0);
+    for (;;) {
+      const int c = ((rows + TM - 1) / TM) * tn_count;
+      if (local < c || sub == 3) break;
+      local -= c;
+      ++sub;
+      rows = sub_rows(nd, sub);
+    }
+    const int tiles_m = (rows + TM - 1) / TM;
+    const int tm = local % tiles_m, tn = local / tiles_m;
+    const bool isV = sub >= 2, bottom = sub & 1;
+    const int kb = bottom ? n1 : 0;
+    const int ke = bottom ? N : n1 + 1 + n2;
+    const int rowoff = bottom ? nd.k : 0;
+    const int64_t ld = nd.ld, vo = nd.vec_off + nd.r0;
+    const double* G = (isV ? w.GV : w.GU) + nd.mat_off;
+    const double* Mv = (isV ? w.VM : w.UM) + nd.mat_off;
+    const double* A = G + (nd.r0 + rowoff) + (int64_t)(nd.r0 + kb) * ld;
+    const double* B = Mv + (nd.r0 + kb) + (int64_t)nd.r0 * ld;
+    NodeStore store{(isV ? w.Vw : w.Uw) + nd.mat_off, w.scol + vo, ld, nd.r0 + rowoff};
+    gemm_tile<TM, TN>(sm, A, ld, B, ld, rows, N, ke - kb, tm * TM, tn * TN, store);
   }
 }
 
@@ -355,18 +447,25 @@ __global__ __launch_bounds__(256) void k_final_u(const int64_t* __restrict__ pn,
     const int64_t n2 = n >> 1;
     double2* o2 = reinterpret_cast<double2*>(out);
     const double2* i2 = reinterpret_cast<const double2*>(in);
-    for (int64_t r2 = threadIdx.x; r2 < n2; r2 += kBlock) {
-      const int64_t r = 2 * r2;
-      double2 v = make_double2(0.0, 0.0);
-      if (r + 1 >= ul && r < uh) {
-        if (r >= ul && r + 1 < uh) {
-          v = i2[r2];
-        } else {
-          v.x = (r >= ul && r < uh) ? in[r] : 0.0;
-          v.y = (r + 1 >= ul && r + 1 < uh) ? in[r + 1] : 0.0;
+    // four 16-byte stores in flight per thread
+    for (int64_t b2 = threadIdx.x; b2 < n2; b2 += 4 * kBlock) {
+      double2 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r2 = b2 + q * kBlock, r = 2 * r2;
+        v[q] = make_double2(0.0, 0.0);
+        if (r2 < n2 && r + 1 >= ul && r < uh) {
+          if (r >= ul && r + 1 < uh) {
+            v[q] = i2[r2];
+          } else {
+            v[q].x = (r >= ul && r < uh) ? in[r] : 0.0;
+            v[q].y = (r + 1 >= ul && r + 1 < uh) ? in[r + 1] : 0.0;
+          }
         }
       }
-      o2[r2] = v;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (b2 + q * kBlock < n2) o2[b2 + q * kBlock] = v[q];
     }
     if ((n & 1) && threadIdx.x == 0) {
       const int64_t r = n - 1;
@@ -377,9 +476,11 @@ __global__ __launch_bounds__(256) void k_final_u(const int64_t* __restrict__ pn,
   }
 }
 
-// V^T: 64 x 64 tiles; reads columns of Vwork (coalesced, skipped outside
-// each column's support), writes rows of V^T as columns of the column-major
-// output (coalesced) through LDS.
+// V^T: bands of 64 output rows (singular vectors); a workgroup takes one
+// band and a range of its 64-column tiles.  A tile that no vector of the band
+// reaches (outside every support) is written as zeros directly; the others
+// read the columns of Vwork inside their supports (coalesced) and write rows
+// of V^T as columns of the column-major output (coalesced) through LDS.
 __global__ __launch_bounds__(256) void k_final_vt(const int64_t* __restrict__ pn,
                                                   const int64_t* __restrict__ pvec,
                                                   const int64_t* __restrict__ pmat,
@@ -388,6 +489,8 @@ __global__ __launch_bounds__(256) void k_final_vt(const int64_t* __restrict__ pn
   __shared__ double tileS[64][65];
   __shared__ int64_t pcs[64];
   __shared__ int lov[64], hiv[64];
+  __shared__ int s_any;
+  // global work item: (problem, band, tile group); tile_off counts items
   const int64_t gt = blockIdx.x;
   int lo = 0, hi = nprob;
   while (hi - lo > 1) {
@@ -397,10 +500,11 @@ __global__ __launch_bounds__(256) void k_final_vt(const int64_t* __restrict__ pn
   }
   const int64_t n = pn[lo], pv = pvec[lo], mo = pmat[lo];
   const int64_t nt = (n + 63) / 64;
-  const int64_t tl = gt - tile_off[lo];
-  if (tl >= nt * nt) return;
-  const int64_t t0 = (tl % nt) * 64;  // output rows of V^T (singular vector index)
-  const int64_t j0 = (tl / nt) * 64;  // output columns of V^T (coordinate index)
+  const int64_t ng = (nt + kVtTilesPerGroup - 1) / kVtTilesPerGroup;
+  const int64_t item = gt - tile_off[lo];
+  if (item >= nt * ng) return;
+  const int64_t t0 = (item % nt) * 64;  // output rows of V^T (singular vector index)
+  const int64_t g0 = (item / nt) * kVtTilesPerGroup;
   const int t = threadIdx.x;
   if (t < 64) {
     const int64_t tv = t0 + t;
@@ -417,32 +521,55 @@ __global__ __launch_bounds__(256) void k_final_vt(const int64_t* __restrict__ pn
   }
   __syncthreads();
   const double* Vw = w.Vw + mo;
-  // load: element (j, tv) = V[j0 + jj, pc(tv)]; one wavefront per 16 vectors
-  {
-    const int wv = t >> 6, jj = t & 63;
-    const int64_t j = j0 + jj;
-    for (int tt = wv; tt < 64; tt += 4) {
-      const int64_t pc = pcs[tt];
-      double v = 0.0;
-      if (pc >= 0 && j0 < hiv[tt] && j0 + 64 > lov[tt] && j < n && j >= lov[tt] && j < hiv[tt])
-        v = Vw[j + pc * n];
-      tileS[tt][jj] = v;
-    }
-  }
-  __syncthreads();
   double* out = VT + mo;
-  // store: column j of V^T, rows t0..t0+63, two rows per thread
   const bool vec = ((((uintptr_t)(out + t0)) & 15) == 0) && ((n & 1) == 0);
-  for (int e = t; e < 32 * 64; e += kBlock) {
-    const int tt = 2 * (e & 31), jj = e >> 5;
-    const int64_t tv = t0 + tt, j = j0 + jj;
-    if (j >= n) continue;
-    if (vec && tv + 1 < n) {
-      *reinterpret_cast<double2*>(out + tv + j * n) = make_double2(tileS[tt][jj], tileS[tt + 1][jj]);
-    } else {
-      if (tv < n) out[tv + j * n] = tileS[tt][jj];
-      if (tv + 1 < n) out[tv + 1 + j * n] = tileS[tt + 1][jj];
+  for (int64_t g = g0; g < min(nt, g0 + kVtTilesPerGroup); ++g) {
+    const int64_t j0 = g * 64;
+    // does any vector of the band reach columns j0 .. j0+63?
+    if (t == 0) s_any = 0;
+    __syncthreads();
+    if (t < 64 && pcs[t] >= 0 && j0 < hiv[t] && j0 + 64 > lov[t]) s_any = 1;
+    __syncthreads();
+    if (!s_any) {
+      for (int e = t; e < 32 * 64; e += kBlock) {
+        const int tt = 2 * (e & 31), jj = e >> 5;
+        const int64_t tv = t0 + tt, j = j0 + jj;
+        if (j >= n) continue;
+        if (vec && tv + 1 < n) {
+          *reinterpret_cast<double2*>(out + tv + j * n) = make_double2(0.0, 0.0);
+        } else {
+          if (tv < n) out[tv + j * n] = 0.0;
+          if (tv + 1 < n) out[tv + 1 + j * n] = 0.0;
+        }
+      }
+      continue;
     }
+    // load: element (j, tv) = V[j0 + jj, pc(tv)]; one wavefront per 16 vectors
+    {
+      const int wv = t >> 6, jj = t & 63;
+      const int64_t j = j0 + jj;
+      for (int tt = wv; tt < 64; tt += 4) {
+        const int64_t pc = pcs[tt];
+        double v = 0.0;
+        if (pc >= 0 && j0 < hiv[tt] && j0 + 64 > lov[tt] && j < n && j >= lov[tt] && j < hiv[tt])
+          v = Vw[j + pc * n];
+        tileS[tt][jj] = v;
+      }
+    }
+    __syncthreads();
+    // store: column j of V^T, rows t0..t0+63, two rows per thread
+    for (int e = t; e < 32 * 64; e += kBlock) {
+      const int tt = 2 * (e & 31), jj = e >> 5;
+      const int64_t tv = t0 + tt, j = j0 + jj;
+      if (j >= n) continue;
+      if (vec && tv + 1 < n) {
+        *reinterpret_cast<double2*>(out + tv + j * n) = make_double2(tileS[tt][jj], tileS[tt + 1][jj]);
+      } else {
+        if (tv < n) out[tv + j * n] = tileS[tt][jj];
+        if (tv + 1 < n) out[tv + 1 + j * n] = tileS[tt + 1][jj];
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -466,16 +593,24 @@ void launch_order(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, h
   hipLaunchKernelGGL(k_order, dim3(nnodes, gy), dim3(kBlock), 0, st, nodes, w);
 }
 
-void launch_update(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {
+void launch_update(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, const Tuning& tu,
+                   hipStream_t st) {
   if (nnodes <= 0) return;
+  if (tu.flat) {
+    hipLaunchKernelGGL(k_tile_sched, dim3(1), dim3(kBlock), 0, st, nodes, nnodes, w);
+    hipLaunchKernelGGL((k_update_flat<64, 64>), dim3(tu.grid64), dim3(kBlock), 0, st, nodes, nnodes, w);
+    if (max_m > w.small_n)
+      hipLaunchKernelGGL((k_update_flat<128, 128>), dim3(tu.grid128), dim3(kBlock), 0, st, nodes, nnodes, w);
+    return;
+  }
   {
-    const int tiles = ((max_m + 1 + 63) / 64) * ((std::min(max_m, kSmallN) + 63) / 64);
-    const int gy = grid_y(nnodes, tiles, 2048);
+    const int tiles = ((max_m + 1 + 63) / 64) * ((std::min(max_m, w.small_n) + 63) / 64);
+    const int gy = grid_y(nnodes, tiles, tu.grid64 * 2);
     hipLaunchKernelGGL((k_update<64, 64>), dim3(nnodes, gy, 4), dim3(kBlock), 0, st, nodes, w);
   }
-  if (max_m > kSmallN) {
+  if (max_m > w.small_n) {
     const int tiles = ((max_m + 1 + 127) / 128) * ((max_m + 127) / 128);
-    const int gy = grid_y(nnodes, tiles, 1024);
+    const int gy = grid_y(nnodes, tiles, tu.grid128 * 2);
     hipLaunchKernelGGL((k_update<128, 128>), dim3(nnodes, gy, 4), dim3(kBlock), 0, st, nodes, w);
   }
 }
@@ -483,7 +618,7 @@ void launch_update(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, 
 void launch_gemm_plain(int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                        double* C, int ldc, hipStream_t st) {
   if (M <= 0 || N <= 0) return;
-  if (N <= kSmallN) {
+  if (N <= 96) {
     int tiles = ((M + 63) / 64) * ((N + 63) / 64);
     if (tiles > 4096) tiles = 4096;
     hipLaunchKernelGGL((k_gemm_plain<64, 64>), dim3(tiles), dim3(kBlock), 0, st, M, N, K, A, lda, B, ldb, C, ldc);

@@ -115,42 +115,45 @@ __device__ inline void interval_of(const double* __restrict__ d, int N, double r
   }
 }
 
-// Features of roots base .. base+63 by a 256-thread workgroup (moments
-// already in F).  Row r's features go to out(r, q, value) for roots < N.
+// Features of roots base .. base+63 by a workgroup of 64 or 256 threads
+// (moments already in F).  Row r's features go to out(r, q, value) for
+// roots < N.
 template <class Out>
 __device__ void block_features(const double* __restrict__ d, const double* __restrict__ z, int N, double rho,
                                int base, int B, FeatLds& F, Out out) {
-  const int r = threadIdx.x & 63, part = threadIdx.x >> 6;
+  const int r = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int i = base + r;
   const int nb = (N + B - 1) / B;
   double lo = 0.0, h = 1.0, w2 = 1.0;
   if (i < N) interval_of(d, N, rho, i, lo, h, w2);
-  // far field: this thread's quarter of the blocks
-  double v = 0.0, sl = 0.0;
-  if (i < N) {
-    const double lam = lo * lo + 0.5 * w2;
-    for (int k = part; k < nb; k += 4) {
-      const int j0 = k * B, j1 = min(N, (k + 1) * B);
-      if (j1 > i - 3 && j0 <= i + 4) {
-        for (int j = j0; j < j1; ++j) {
-          if (j >= i - 3 && j <= i + 4) continue;
-          const double den = d[j] * d[j] - lam;
-          const double t = (z[j] * z[j]) / den;
+  // far field: quarter `part` of the blocks (every fourth block)
+  for (int part = wv; part < 4; part += nw) {
+    double v = 0.0, sl = 0.0;
+    if (i < N) {
+      const double lam = lo * lo + 0.5 * w2;
+      for (int k = part; k < nb; k += 4) {
+        const int j0 = k * B, j1 = min(N, (k + 1) * B);
+        if (j1 > i - 3 && j0 <= i + 4) {
+          for (int j = j0; j < j1; ++j) {
+            if (j >= i - 3 && j <= i + 4) continue;
+            const double den = d[j] * d[j] - lam;
+            const double t = (z[j] * z[j]) / den;
+            v += t;
+            sl += t / den;
+          }
+        } else if (F.Z[k] > 0.0) {
+          const double den = F.D[k] - lam;
+          const double t = F.Z[k] / den;
           v += t;
           sl += t / den;
         }
-      } else if (F.Z[k] > 0.0) {
-        const double den = F.D[k] - lam;
-        const double t = F.Z[k] / den;
-        v += t;
-        sl += t / den;
       }
     }
+    F.pv[part][r] = v;
+    F.ps[part][r] = sl;
   }
-  F.pv[part][r] = v;
-  F.ps[part][r] = sl;
   __syncthreads();
-  if (part == 0 && i < N) {
+  if (wv == 0 && i < N) {
     for (int q = 0; q < 4; ++q) {
       int j = i - q;
       if (j >= 0) {
@@ -227,29 +230,34 @@ __device__ inline void mm_fast(const unsigned short* A, int lda, const unsigned 
 // Inference of 64 rows (inputs in A.a0): the proposed positions in xout[64].
 // a1 and a2 alternate as the hidden activations (layer 3 writes a1 again).
 __device__ void forward_fast(const FastW& W, FastAct& A, float* xout) {
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r0 = wv * 16;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   for (int l = 0; l < 3; ++l) {
     const unsigned short* in = l == 0 ? A.a0 : (l == 1 ? A.a1 : A.a2);
     unsigned short* outl = l == 1 ? A.a2 : A.a1;
     const unsigned short* wt = W.w + (l == 0 ? kPkW1 : (l == 1 ? kPkW2 : kPkW3));
     const float* bl = W.b + l * kH;
     const int K = l == 0 ? kFP : kH;
-    f32x4 acc[4];
-    for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    mm_fast(in, K, wt, K, r0, K, 4, acc);
-    for (int nt = 0; nt < 4; ++nt)
-      for (int r = 0; r < 4; ++r) {
-        const int row = r0 + 4 * (lane >> 4) + r, col = nt * 16 + (lane & 15);
-        outl[row * kH + col] = bf16_bits(gelu_f(acc[nt][r] + bl[col]));
-      }
+    for (int strip = wv; strip < 4; strip += nw) {
+      const int r0 = strip * 16;
+      f32x4 acc[4];
+      for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      mm_fast(in, K, wt, K, r0, K, 4, acc);
+      for (int nt = 0; nt < 4; ++nt)
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + 4 * (lane >> 4) + r, col = nt * 16 + (lane & 15);
+          outl[row * kH + col] = bf16_bits(gelu_f(acc[nt][r] + bl[col]));
+        }
+    }
     __syncthreads();
   }
   // 64 -> 1 as column 0 of a 16-wide product
-  f32x4 acc[1] = {f32x4{0.f, 0.f, 0.f, 0.f}};
-  mm_fast(A.a1, kH, W.w + kPkW4, kH, r0, kH, 1, acc);
-  if ((lane & 15) == 0)
-    for (int r = 0; r < 4; ++r) xout[r0 + 4 * (lane >> 4) + r] = logistic(acc[0][r] + W.b[3 * kH]);
+  for (int strip = wv; strip < 4; strip += nw) {
+    const int r0 = strip * 16;
+    f32x4 acc[1] = {f32x4{0.f, 0.f, 0.f, 0.f}};
+    mm_fast(A.a1, kH, W.w + kPkW4, kH, r0, kH, 1, acc);
+    if ((lane & 15) == 0)
+      for (int r = 0; r < 4; ++r) xout[r0 + 4 * (lane >> 4) + r] = logistic(acc[0][r] + W.b[3 * kH]);
+  }
   __syncthreads();
 }
 

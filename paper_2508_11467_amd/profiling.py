@@ -1,0 +1,93 @@
+"""Summaries of rocprofv3 output for the kernels of this library.
+
+    python -m paper_2508_11467_amd.profiling stats  STATS_CSV BENCH_JSON OUT_MD TITLE COMMAND
+    python -m paper_2508_11467_amd.profiling traffic FETCH_CSV WRITE_CSV KERNELS COPY_BYTES LAUNCHES OUT_JSON
+
+``stats`` turns a ``--kernel-trace --stats`` kernel_stats.csv (and the
+bench.py line of the same run) into a Markdown table.  ``traffic`` reads the
+per-dispatch counter files of two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
+runs (KiB per dispatch), calibrates each counter with the largest copy
+kernel of the run (a device-to-device copy of COPY_BYTES bytes, issued by
+``bench.py --copy-calibration``), and writes the HBM bytes per launch of the
+named kernels (comma-separated name fragments, LAUNCHES launches of the
+group in the run) with the hash of the kernel sources they were taken from.
+"""
+
+from __future__ import annotations
+
+import csv
+import json
+import re
+import sys
+
+
+def kernel_label(name: str) -> str:
+    m = re.search(r"(k_\w+?)(?:ILi(\d+)E|\(|$)", name)
+    if m:
+        base = m.group(1)
+        tpl = re.findall(r"ILi(\d+)E(?:Li(\d+)E)?", name)
+        if tpl:
+            base += "<" + ",".join(x for x in tpl[0] if x) + ">"
+        return base
+    return name.split("(")[0][:48]
+
+
+def stats(stats_csv, bench_json, out_md, title, command):
+    rows = list(csv.DictReader(open(stats_csv)))
+    b = json.loads(open(bench_json).read().strip().splitlines()[-1]) if bench_json != "-" else None
+    out = [f"# {title}\n\n", "Command (repository root, one MI355X):\n\n", f"```\n{command}\n```\n\n",
+           "rocprofv3 `kernel_stats.csv`, all launches of the run:\n\n",
+           "| kernel | calls | total ms | avg us | min us | max us | % |\n|---|---|---|---|---|---|---|\n"]
+    for r in rows:
+        out.append(f"| {kernel_label(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                   f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |\n")
+    if b:
+        rf = b.get("roofline", {})
+        out.append(f"\nbench.py line of the same run: {b['ms_per_step']:.3f} ms per solve; roofline kernel "
+                   f"`{rf.get('kernel')}` {rf.get('avg_launch_ms', 0):.4f} ms per launch (HIP events), "
+                   f"{rf.get('achieved', 0):.1f} of {rf.get('peak')} {rf.get('unit')}.\n")
+    open(out_md, "w").write("".join(out))
+    print("".join(out))
+
+
+def _dispatches(path):
+    """(kernel name, counter value) of every dispatch in a counter_collection.csv."""
+    out = []
+    for r in csv.DictReader(open(path)):
+        name = r.get("Kernel_Name") or r.get("Kernel-Name") or r.get("KernelName") or ""
+        val = r.get("Counter_Value") or r.get("Counter-Value") or r.get("CounterValue")
+        if val is None:
+            continue
+        out.append((name, float(val)))
+    return out
+
+
+def traffic(fetch_csv, write_csv, kernels, copy_bytes, launches, out_json):
+    from .build import source_hash
+    frags = [k for k in kernels.split(",") if k]
+    res = {}
+    for tag, path in (("fetch", fetch_csv), ("write", write_csv)):
+        rows = _dispatches(path)
+        copies = [v for n, v in rows if "copyBuffer" in n or "copy" in n.lower() and "k_" not in n]
+        cal = max(copies) * 1024.0 if copies else None  # KiB -> bytes
+        tot = sum(v for n, v in rows if any(f in n for f in frags)) * 1024.0
+        scale = float(copy_bytes) / cal if cal else None
+        res[tag] = {"counter_bytes": tot, "copy_counter_bytes": cal, "scale": scale,
+                    "bytes_per_launch": tot * scale / float(launches) if scale else None}
+    out = {"kernels": frags, "launches": int(launches), "copy_bytes": int(copy_bytes),
+           "fetch": res["fetch"], "write": res["write"],
+           "traffic_bytes_per_launch": (res["fetch"]["bytes_per_launch"] or 0) + (res["write"]["bytes_per_launch"] or 0),
+           "source_hash": source_hash()}
+    json.dump(out, open(out_json, "w"), indent=1)
+    print(json.dumps(out, indent=1))
+
+
+if __name__ == "__main__":
+    cmd = sys.argv[1]
+    if cmd == "stats":
+        stats(*sys.argv[2:7])
+    elif cmd == "traffic":
+        traffic(*sys.argv[2:8])
+    else:
+        raise SystemExit(__doc__)

@@ -95,3 +95,63 @@ def test_batched_config_2000(solver):
         off += n
         mo += n * n
     assert worst_res <= 1e-12 and worst_orth <= 1e-12
+
+
+def test_flat_schedule_and_tile_classes_match(gpu):
+    """The persistent flattened schedule and other tile-class thresholds give
+    the same results as the default launch shapes."""
+    import torch
+    from paper_2508_11467_amd.api import Solver
+    sizes = [40, 900, 33, 260, 1200, 75, 31, 500]
+    d, e = inputs.batch_uniform(sizes, 91)
+    dt, et = torch.from_numpy(d).cuda(), torch.from_numpy(e).cuda()
+    ref = Solver(0)
+    alt = Solver(0)
+    try:
+        r = [x.clone() for x in ref.svd_batched(sizes, dt, et)]
+        for tune in ({"small_n": 96, "flat": 1, "grid64": 512, "grid128": 256},
+                     {"small_n": 192, "flat": 1, "grid64": 2048, "grid128": 1024},
+                     {"small_n": 64, "flat": 0, "grid64": 1024, "grid128": 512},
+                     {"small_n": 96, "flat": 0, "grid64": 1024, "grid128": 512, "sec_small_n": 64}):
+            alt.set_tuning(**tune)
+            a = alt.svd_batched(sizes, dt, et)
+            info, _ = alt.info()
+            assert info == 0
+            if tune["small_n"] == 96 and not tune.get("sec_small_n"):
+                for x, y in zip(r, a):
+                    assert torch.equal(x, y)
+            else:
+                assert torch.max(torch.abs(r[0] - a[0])) <= 1e-14 * torch.max(r[0])
+        # single-problem solves take the same tunings
+        d1, e1 = inputs.normal(3000, 12)
+        s0 = ref.svd(d1, e1)[0].clone()
+        alt.set_tuning(small_n=96, flat=1, grid64=1024, grid128=512)
+        s1 = alt.svd(d1, e1)[0]
+        assert torch.equal(s0, s1)
+    finally:
+        ref.close()
+        alt.close()
+
+
+def test_autotune_picks_a_valid_tuning(gpu):
+    import torch
+    from paper_2508_11467_amd.api import Solver
+    sizes = inputs.batch_sizes(60, 32, 600, 5).tolist()
+    d, e = inputs.batch_uniform(sizes, 6)
+    s = Solver(0)
+    try:
+        best = s.autotune(sizes, d, e, repeats=1)
+        assert best["ms"] > 0 and best["flat"] in (0, 1) and best["small_n"] in (64, 96, 192)
+        assert s.tuning() == {k: best[k] for k in ("small_n", "flat", "grid64", "grid128", "sec_small_n")}
+        sig, U, VT = s.svd_batched(sizes, torch.from_numpy(d), torch.from_numpy(e))
+        info, _ = s.info()
+        assert info == 0
+        res = unpack(sizes, sig.cpu().numpy(), U.cpu().numpy(), VT.cpu().numpy())
+        off = 0
+        for n, (sg, u, v) in zip(sizes, res):
+            B = oracle.dense(d[off:off + n], e[off:off + n - 1])
+            off += n
+            assert np.linalg.norm(B - (u * sg) @ v) <= 1e-12 * np.linalg.norm(B)
+            assert np.max(np.abs(u.T @ u - np.eye(n))) <= 1e-12
+    finally:
+        s.close()

@@ -131,8 +131,10 @@ def test_training_lowers_the_loss(solver):
     assert l1 < 0.5 * l0, (l0, l1)
 
 
+@pytest.mark.parametrize("small", [0, 64])
 @pytest.mark.parametrize("how", ["labels", "random", "ends"])
-def test_learned_secular_matches_oracle(solver, how):
+def test_learned_secular_matches_oracle(solver, how, small):
+    solver.set_tuning(small_n=96, flat=0, grid64=1024, grid128=512, sec_small_n=small)
     g = np.random.default_rng(17)
     for N, spread in [(2, "uniform"), (33, "graded"), (300, "uniform"), (1000, "graded")]:
         d, z = _problem(g, N, spread)
@@ -215,11 +217,13 @@ def _solve_checks(s, d, e):
     return sig.cpu().numpy(), U.cpu().numpy(), VT.cpu().numpy(), st
 
 
-def test_untrained_network_keeps_the_tolerances(gpu):
+@pytest.mark.parametrize("small", [0, 64])
+def test_untrained_network_keeps_the_tolerances(gpu, small):
     """Any proposal is safe: the safeguarded iteration still converges."""
     from paper_2508_11467_amd.api import Solver
     from paper_2508_11467_amd.start_model import init_params
     s = Solver(0, start="learned", mlp_params=init_params(3))
+    s.set_tuning(small_n=96, flat=0, grid64=1024, grid128=512, sec_small_n=small)
     try:
         for d, e in [inputs.uniform(1500, 41), inputs.workload("n4096_graded")]:
             sig, U, VT, st = _solve_checks(s, d, e)

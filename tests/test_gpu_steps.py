@@ -145,6 +145,8 @@ def _children(n, s, seed, kind="uniform"):
     (131, 1, 5, "uniform"), (1000, 0, 6, "uniform"), (3001, 1, 7, "uniform"),
     (64, 0, 8, "ones"), (101, 1, 9, "ones"), (40, 0, 10, "mirror"), (80, 0, 11, "mirror"),
     (300, 0, 12, "zeros"), (301, 1, 13, "zeros"),
+    # merges of at least 2048 rows take the 1024-thread deflation kernel
+    (2500, 0, 14, "zeros"), (2048, 1, 15, "ones"), (2400, 0, 16, "mirror"),
 ])
 def test_deflation_bit_exact(solver, n, s, seed, kind):
     sig1, sig2, q1, q2, alpha, beta = _children(n, s, seed, kind)
@@ -212,10 +214,23 @@ def test_secular_residual_pins_oracle():
     assert np.all(np.abs(f) <= 32 * 2.0 ** -52 * E)
 
 
-@pytest.mark.parametrize("N,seed", [(1, 0), (2, 1), (3, 2), (64, 3), (65, 4), (500, 5), (3000, 6)])
-def test_secular_matches_oracle(solver, N, seed):
+@pytest.fixture(scope="module")
+def solver8(gpu):
+    """A handle whose secular problems of up to 64 roots take the 8-lanes-per-
+    root kernel."""
+    from paper_2508_11467_amd.api import Solver
+    s = Solver(0)
+    s.set_tuning(small_n=96, flat=0, grid64=1024, grid128=512, sec_small_n=64)
+    yield s
+    s.close()
+
+
+@pytest.mark.parametrize("kernel", ["wide", "small"])
+@pytest.mark.parametrize("N,seed", [(1, 0), (2, 1), (3, 2), (9, 7), (33, 8), (64, 3), (65, 4), (500, 5),
+                                    (3000, 6)])
+def test_secular_matches_oracle(solver, solver8, kernel, N, seed):
     d, z = _arrow(N, seed)
-    o, tau, it = solver.step_secular(d, z)
+    o, tau, it = (solver if kernel == "wide" else solver8).step_secular(d, z)
     o, tau, it = o.cpu().numpy(), tau.cpu().numpy(), it.cpu().numpy()
     ro, rt, rit = oracle.secular_roots(d, z)
     w = d[o] + tau
