@@ -62,13 +62,14 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_work(kind: str, stats: dict, n: int, launches: int):
-    """(bound, algorithmic units per launch, unit, peak) of a kernel kind."""
+def kernel_work(kind: str, stats: dict, n2: float, launches: int):
+    """(bound, algorithmic units per launch, unit, peak) of a kernel kind;
+    n2 = sum of n^2 over the problems of a solve."""
     if kind == "update_gemm":
         return "mfma", stats["update_flops"] / max(launches, 1), "TFLOP/s", PEAK_FP64_MFMA
     if kind == "final":
         # write U and V^T in full; read each column's support once
-        byts = 8.0 * (2.0 * n * n + stats["final_read_elems"])
+        byts = 8.0 * (2.0 * n2 + stats["final_read_elems"])
         return "hbm", byts / max(launches, 1), "GB/s", PEAK_HBM
     if kind == "gather":
         return "hbm", stats["gather_bytes"] / max(launches, 1), "GB/s", PEAK_HBM
@@ -237,7 +238,7 @@ def bench_batched(args, desc):
     kinds = {k: v for k, v in timing.items() if v[1] > 0}
     dom = max(kinds, key=lambda k: kinds[k][0])
     tot_ms, launches = kinds[dom]
-    bound, work, unit, peak = kernel_work(dom, stats, 0, launches / args.steps)
+    bound, work, unit, peak = kernel_work(dom, stats, float(tot2), launches / args.steps)
     avg_s = tot_ms * 1e-3 / launches
     scale = 1e9 if unit == "GB/s" else 1e12
     line = {
@@ -368,7 +369,7 @@ def main():
     dom = max(kinds, key=lambda k: kinds[k][0])
     tot_ms, launches = kinds[dom]
     per_launch_launches = launches / args.steps
-    bound, work, unit, peak = kernel_work(dom, stats, n, per_launch_launches)
+    bound, work, unit, peak = kernel_work(dom, stats, float(n) * n, per_launch_launches)
     avg_s = tot_ms * 1e-3 / launches
     achieved = work / avg_s
     scale = 1e9 if unit == "GB/s" else 1e12
