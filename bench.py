@@ -139,7 +139,7 @@ def accuracy(d, e, sig, U, VT) -> dict:
     return {"residual": res, "orth_U": ou, "orth_V": ov}
 
 
-def plain_vs_learned(d, e, steps: int, warmup: int) -> dict:
+def plain_vs_learned(d, e, steps: int, warmup: int, tuning=None) -> dict:
     """ms per solve and secular evaluations per root with each start."""
     import torch
 
@@ -153,6 +153,8 @@ def plain_vs_learned(d, e, steps: int, warmup: int) -> dict:
     res = {}
     for start in ("plain", "learned"):
         s = Solver(0, start=start)
+        if tuning:
+            s.set_tuning(**tuning)
         ms = time_solver(s, dt, et, out, steps, warmup)
         info, st = s.info()
         s.close()
@@ -309,50 +311,30 @@ def main():
     sig = torch.empty(n, dtype=torch.float64, device=dev)
     ub = torch.empty((n, n), dtype=torch.float64, device=dev)
     vb = torch.empty((n, n), dtype=torch.float64, device=dev)
-    # timed region 1: the solve as a caller runs it (graph replay)
+    # timed region 1: the solve as a caller runs it (graph replay), with the
+    # default options and after the library's autotuner has picked the leaf
+    # size and launch shapes for this workload (outside the timed region)
     solver = Solver(0)
-    for _ in range(args.warmup):
-        solver.svd(dt, et, out=(sig, ub, vb))
-    torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(args.steps):
-        solver.svd(dt, et, out=(sig, ub, vb))
-    stop.record()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop) / args.steps
+    ms_default = time_solver(solver, dt, et, (sig, ub, vb), args.steps, args.warmup)
+    tuned = solver.autotune([n], dt, et, out=(sig, ub, vb), repeats=2)
+    tuning = {k: v for k, v in tuned.items() if k != "ms"}
+    ms = time_solver(solver, dt, et, (sig, ub, vb), args.steps, args.warmup)
     info, stats = solver.info()
     solver.close()
 
-    sig_fp64 = sig.clone()
-    acc_fp64 = accuracy(d, e, sig, ub.T, vb.T)
-
-    # the same solves with split-precision update products
-    ozaki = None
-    if not args.no_ozaki:
-        osv = Solver(0, gemm="ozaki")
-        ms_oz = time_solver(osv, dt, et, (sig, ub, vb), args.steps, args.warmup)
-        info_o, _ = osv.info()
-        osv.close()
-        ozaki = {"ms_per_step": ms_oz, "value": (8.0 / 3.0) * n ** 3 / (ms_oz * 1e-3) / 1e9, "slices": 7,
-                 "min_kept_values": 256, "info": info_o,
-                 "sigma_max_rel_diff_vs_fp64": float(torch.max(torch.abs(sig - sig_fp64)) / sig_fp64[0]),
-                 **accuracy(d, e, sig, ub.T, vb.T)}
-
-    # the same solves with the learned start
-    if not args.no_learned:
-        ls = Solver(0, start="learned")
-        ms_learned = time_solver(ls, dt, et, (sig, ub, vb), args.steps, args.warmup)
-        info_l, stats_l = ls.info()
-        ls.close()
+    def tuned_solver(**kw):
+        s = Solver(0, **kw)
+        s.set_tuning(**tuning)
+        return s
 
     # timed region 2: the same steps launched kernel by kernel, each launch
     # bracketed by HIP events on the solve's stream (per-kernel durations)
-    tsolver = Solver(0, timing=True)
+    tsolver = tuned_solver(timing=True)
     tsolver.svd(dt, et, out=(sig, ub, vb))
     torch.cuda.synchronize()
     tsolver.clear_timing()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
     start.record()
     for _ in range(args.steps):
         tsolver.svd(dt, et, out=(sig, ub, vb))
@@ -361,6 +343,29 @@ def main():
     ms_events = start.elapsed_time(stop) / args.steps
     timing = tsolver.timing()
     tsolver.close()
+
+    sig_fp64 = sig.clone()
+    acc_fp64 = accuracy(d, e, sig, ub.T, vb.T)
+
+    # the same solves with split-precision update products
+    ozaki = None
+    if not args.no_ozaki:
+        osv = tuned_solver(gemm="ozaki")
+        ms_oz = time_solver(osv, dt, et, (sig, ub, vb), args.steps, args.warmup)
+        info_o, _ = osv.info()
+        osv.close()
+        ozaki = {"ms_per_step": ms_oz, "value": (8.0 / 3.0) * n ** 3 / (ms_oz * 1e-3) / 1e9, "slices": 6,
+                 "min_kept_values": 256, "info": info_o,
+                 "sigma_max_rel_diff_vs_fp64": float(torch.max(torch.abs(sig - sig_fp64)) / sig_fp64[0]),
+                 **accuracy(d, e, sig, ub.T, vb.T)}
+
+    # the same solves with the learned start
+    if not args.no_learned:
+        ls = tuned_solver(start="learned")
+        ms_learned = time_solver(ls, dt, et, (sig, ub, vb), args.steps, args.warmup)
+        info_l, stats_l = ls.info()
+        ls.close()
+
     nominal = (8.0 / 3.0) * n ** 3
     value = nominal / (ms * 1e-3) / 1e9
 
@@ -399,7 +404,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "n": n, "leaf_size": 32, "secular_start": "plain"},
+        "config": {"workload": desc, "n": n, "leaf_size": tuning["leaf_size"], "secular_start": "plain",
+                   "tuning": tuning},
+        "ms_per_step_default_options": ms_default,
         "executed_update_gflops": stats["update_flops"] / (ms * 1e-3) / 1e9,
         "update_flops": stats["update_flops"],
         "nominal_flops": nominal,
@@ -428,7 +435,7 @@ def main():
         torch.cuda.empty_cache()
         d5, e5 = inputs.workload("n32768_normal")
         line["config5"] = {"workload": WORKLOADS["n32768_normal"][0],
-                           **plain_vs_learned(d5, e5, max(2, args.steps // 3), 1)}
+                           **plain_vs_learned(d5, e5, max(2, args.steps // 3), 1, tuning)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_n)
     print(json.dumps(line), flush=True)

@@ -82,8 +82,8 @@ typedef struct {
                                  bdc_mlp_set first; same stopping rule, only the
                                  first point of each root's iteration changes) */
   int gemm;                   /* BDC_GEMM_FP64 (default) or BDC_GEMM_OZAKI */
-  int ozaki_slices;           /* slices per operand, 5..7 (default 7: terms dropped
-                                 below 2^-54 relative to |row| |column|) */
+  int ozaki_slices;           /* slices per operand, 5..7 (default 6: terms dropped
+                                 below about 2^-46 relative to |row| |column|) */
   int ozaki_min_n;            /* merges with at least this many kept values use the
                                  split products, >= 128 (default 256); smaller ones FP64 */
 } bdc_options_t;
@@ -241,14 +241,17 @@ typedef struct {
   int grid128;  /* the same for the 128-tile product */
   int sec_small_n; /* secular problems with at most this many roots (0..64; default 0)
                       are solved with 8 lanes per root and no workgroup barriers */
+  int leaf_size;   /* the tree's leaf size (4..32; 0 in bdc_set_tuning keeps the
+                      handle's); the paper found 32 best on its GPUs */
   float ms;     /* out (bdc_autotune): time per solve of the chosen tuning */
 } bdc_tuning_t;
 
 int bdc_get_tuning(bdc_handle_t handle, bdc_tuning_t* tuning);
 int bdc_set_tuning(bdc_handle_t handle, const bdc_tuning_t* tuning);
-/* Times every candidate tuning on bdc_svd_batched(batch, sizes, d, e, sigma,
- * U, VT) (arguments as there; a single problem is batch = 1): one warm-up and
- * `repeats` timed solves each, with HIP events on `stream`.  Keeps the
+/* Times candidate tunings on bdc_svd_batched(batch, sizes, d, e, sigma, U,
+ * VT) (arguments as there; a single problem is batch = 1): one warm-up and
+ * `repeats` timed solves each, with HIP events on `stream`; first the leaf
+ * size (16, 24, 32), then the launch shapes with the best one.  Keeps the
  * fastest in the handle and returns it in *best.  Synchronous: waits for the
  * stream.  The outputs hold the last solve's results. */
 int bdc_autotune(bdc_handle_t handle, int64_t batch, const int64_t* sizes, const double* d,

@@ -74,6 +74,7 @@ class Tuning(ctypes.Structure):
         ("grid64", c_int),
         ("grid128", c_int),
         ("sec_small_n", c_int),
+        ("leaf_size", c_int),
         ("ms", ctypes.c_float),
     ]
 

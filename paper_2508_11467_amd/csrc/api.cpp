@@ -50,8 +50,10 @@ struct Plan {
   std::vector<NodeDesc> host_nodes;
   int nnodes = 0;
   int nprob = 0;
-  int64_t* dev_prob = nullptr;  // n, vec, mat, col_off, tile_off (nprob each)
-  int64_t total_cols = 0, total_tiles = 0;
+  int64_t* dev_prob = nullptr;  // n, vec, mat, uitem_off, vitem_off (nprob each)
+  int32_t* dev_uprob = nullptr;  // final-pass work item -> problem (U, V^T)
+  int32_t* dev_vprob = nullptr;
+  int64_t total_cols = 0, total_tiles = 0;  // final-pass work items of U and of V^T
   int root_id0 = -1;  // node id of the first problem's root merge
   void* block = nullptr;
 };
@@ -167,7 +169,7 @@ int make_plan(bdc_handle_t h, const int64_t* sizes, int64_t batch) {
     if (n > 0) build_node(leaves, by_h, mo, vo, (int32_t)n, leaf, 0, (int32_t)n, 0);
     vo += n;
     mo += n * n;
-    co += n;
+    if (n > 0) co += (n + final_u_cols(n) - 1) / final_u_cols(n);  // U work items
     const int64_t nt = (n + 63) / 64;
     to += nt * ((nt + kVtTilesPerGroup - 1) / kVtTilesPerGroup);  // V^T work items
   }
@@ -187,7 +189,8 @@ int make_plan(bdc_handle_t h, const int64_t* sizes, int64_t batch) {
   p.nnodes = id;
   size_t bytes = align_up(sizeof(LeafDesc) * std::max<size_t>(1, leaves.size())) +
                  align_up(sizeof(NodeDesc) * std::max(1, id)) +
-                 align_up(sizeof(int64_t) * 5 * std::max<int64_t>(1, batch));
+                 align_up(sizeof(int64_t) * 5 * std::max<int64_t>(1, batch)) +
+                 align_up(sizeof(int32_t) * std::max<int64_t>(1, co)) + align_up(sizeof(int32_t) * std::max<int64_t>(1, to));
   if (hipMalloc(&p.block, bytes) != hipSuccess) return BDC_ERR_NOMEM;
   char* b = (char*)p.block;
   p.dev_leaves = (LeafDesc*)b;
@@ -195,6 +198,21 @@ int make_plan(bdc_handle_t h, const int64_t* sizes, int64_t batch) {
   NodeDesc* nodes_dev = (NodeDesc*)b;
   b += align_up(sizeof(NodeDesc) * std::max(1, id));
   p.dev_prob = (int64_t*)b;
+  b += align_up(sizeof(int64_t) * 5 * std::max<int64_t>(1, batch));
+  p.dev_uprob = (int32_t*)b;
+  b += align_up(sizeof(int32_t) * std::max<int64_t>(1, co));
+  p.dev_vprob = (int32_t*)b;
+  {
+    std::vector<int32_t> up(std::max<int64_t>(1, co)), vp(std::max<int64_t>(1, to));
+    for (int64_t i = 0; i < batch; ++i) {
+      const int64_t ue = i + 1 < batch ? pcol[i + 1] : co, ve = i + 1 < batch ? ptile[i + 1] : to;
+      for (int64_t q = pcol[i]; q < ue; ++q) up[q] = (int32_t)i;
+      for (int64_t q = ptile[i]; q < ve; ++q) vp[q] = (int32_t)i;
+    }
+    if ((co > 0 && hipMemcpy(p.dev_uprob, up.data(), sizeof(int32_t) * co, hipMemcpyHostToDevice) != hipSuccess) ||
+        (to > 0 && hipMemcpy(p.dev_vprob, vp.data(), sizeof(int32_t) * to, hipMemcpyHostToDevice) != hipSuccess))
+      return BDC_ERR_HIP;
+  }
   if (!leaves.empty() &&
       hipMemcpy(p.dev_leaves, leaves.data(), sizeof(LeafDesc) * leaves.size(), hipMemcpyHostToDevice) != hipSuccess)
     return BDC_ERR_HIP;
@@ -426,7 +444,7 @@ int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, do
     Timer t(h, st, kFinal);
     const int64_t np = p.nprob;
     launch_final(p.dev_prob, p.dev_prob + np, p.dev_prob + 2 * np, p.dev_prob + 3 * np, p.dev_prob + 4 * np,
-                 p.nprob, p.total_cols, p.total_tiles, w, sigma, U, VT, st);
+                 p.dev_uprob, p.dev_vprob, p.total_cols, p.total_tiles, w, sigma, U, VT, st);
   }
   if (hipGetLastError() != hipSuccess) return BDC_ERR_HIP;
   h->last_stream = st;
@@ -510,7 +528,7 @@ void bdc_default_options(bdc_options_t* opt) {
   opt->use_graph = 1;
   opt->start = BDC_START_PLAIN;
   opt->gemm = BDC_GEMM_FP64;
-  opt->ozaki_slices = 7;
+  opt->ozaki_slices = 6;
   opt->ozaki_min_n = 256;
 }
 
@@ -682,7 +700,7 @@ namespace {
 bool tuning_valid(const bdc_tuning_t* t) {
   return t->small_n >= 32 && t->small_n <= 4096 && (t->flat == 0 || t->flat == 1) && t->grid64 >= 1 &&
          t->grid64 <= 65535 && t->grid128 >= 1 && t->grid128 <= 65535 && t->sec_small_n >= 0 &&
-         t->sec_small_n <= 64;
+         t->sec_small_n <= 64 && (t->leaf_size == 0 || (t->leaf_size >= 4 && t->leaf_size <= kMaxLeaf));
 }
 }  // namespace
 
@@ -694,6 +712,7 @@ int bdc_get_tuning(bdc_handle_t h, bdc_tuning_t* t) {
   t->grid64 = h->tune.grid64;
   t->grid128 = h->tune.grid128;
   t->sec_small_n = h->tune.sec_small_n;
+  t->leaf_size = h->opt.leaf_size;
   return BDC_OK;
 }
 
@@ -704,6 +723,7 @@ int bdc_set_tuning(bdc_handle_t h, const bdc_tuning_t* t) {
   if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
   drop_graph(h);  // launch shapes are part of a captured sequence
   h->tune = Tuning{t->small_n, t->flat, t->grid64, t->grid128, t->sec_small_n};
+  if (t->leaf_size) h->opt.leaf_size = t->leaf_size;  // the plan is rebuilt on the next solve
   return BDC_OK;
 }
 
@@ -714,51 +734,77 @@ int bdc_autotune(bdc_handle_t h, int64_t batch, const int64_t* sizes, const doub
   if (!best) return -11;
   DeviceGuard g(h->device);
   hipStream_t st = (hipStream_t)stream;
-  std::vector<Tuning> cand;
-  for (int ss : {0, 64})
-    for (int sn : {64, 96, 192}) {
-      cand.push_back(Tuning{sn, 0, 1024, 512, ss});
-      for (int gm : {256, 512, 1024}) cand.push_back(Tuning{sn, 1, 2 * gm, gm, ss});
-    }
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
     if (a) (void)hipEventDestroy(a);
     return BDC_ERR_HIP;
   }
   const Tuning keep = h->tune;
-  float best_ms = -1.0f;
-  Tuning best_t = keep;
+  const int keep_leaf = h->opt.leaf_size;
   int rc = BDC_OK;
-  for (const Tuning& c : cand) {
+  // time of one candidate (leaf size, launch shapes): a warm-up solve (plan,
+  // workspace, graph capture), then `repeats` timed ones
+  auto time_one = [&](int leaf, const Tuning& c, float& ms) {
     if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
     drop_graph(h);
+    h->opt.leaf_size = leaf;
     h->tune = c;
-    rc = bdc_svd_batched(h, batch, sizes, d, e, sigma, U, VT, stream);  // warm-up (and capture)
-    if (rc != BDC_OK) break;
+    int r = bdc_svd_batched(h, batch, sizes, d, e, sigma, U, VT, stream);
+    if (r != BDC_OK) return r;
     (void)hipEventRecord(a, st);
-    for (int r = 0; r < repeats && rc == BDC_OK; ++r) rc = bdc_svd_batched(h, batch, sizes, d, e, sigma, U, VT, stream);
+    for (int q = 0; q < repeats && r == BDC_OK; ++q) r = bdc_svd_batched(h, batch, sizes, d, e, sigma, U, VT, stream);
     (void)hipEventRecord(b, st);
-    if (rc != BDC_OK || hipEventSynchronize(b) != hipSuccess) {
-      rc = rc != BDC_OK ? rc : BDC_ERR_HIP;
-      break;
-    }
-    float ms = 0.0f;
+    if (r != BDC_OK) return r;
+    if (hipEventSynchronize(b) != hipSuccess) return (int)BDC_ERR_HIP;
+    ms = 0.0f;
     (void)hipEventElapsedTime(&ms, a, b);
+    ms /= repeats;
+    return (int)BDC_OK;
+  };
+  // 1. the tree: leaf size, with the current launch shapes
+  float best_ms = -1.0f;
+  int best_leaf = keep_leaf;
+  Tuning best_t = keep;
+  for (int leaf : {16, 24, 32}) {
+    float ms = 0.0f;
+    rc = time_one(leaf, keep, ms);
+    if (rc != BDC_OK) break;
     if (best_ms < 0.0f || ms < best_ms) {
       best_ms = ms;
-      best_t = c;
+      best_leaf = leaf;
+    }
+  }
+  // 2. launch shapes with that tree
+  if (rc == BDC_OK) {
+    std::vector<Tuning> cand;
+    for (int ss : {0, 64})
+      for (int sn : {64, 96, 192}) {
+        cand.push_back(Tuning{sn, 0, 1024, 512, ss});
+        for (int gm : {256, 512, 1024}) cand.push_back(Tuning{sn, 1, 2 * gm, gm, ss});
+      }
+    for (const Tuning& c : cand) {
+      float ms = 0.0f;
+      rc = time_one(best_leaf, c, ms);
+      if (rc != BDC_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_t = c;
+      }
     }
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
+  if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
   drop_graph(h);
   h->tune = rc == BDC_OK ? best_t : keep;
+  h->opt.leaf_size = rc == BDC_OK ? best_leaf : keep_leaf;
   best->small_n = h->tune.small_n;
   best->flat = h->tune.flat;
   best->grid64 = h->tune.grid64;
   best->grid128 = h->tune.grid128;
   best->sec_small_n = h->tune.sec_small_n;
-  best->ms = rc == BDC_OK ? best_ms / repeats : 0.0f;
+  best->leaf_size = h->opt.leaf_size;
+  best->ms = rc == BDC_OK ? best_ms : 0.0f;
   return rc;
 }
 

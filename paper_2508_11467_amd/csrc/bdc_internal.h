@@ -28,6 +28,11 @@ namespace bdc {
 constexpr int kMaxLeaf = 32;
 // 64-column tiles of one 64-row band of V^T handled by one final-pass workgroup
 constexpr int kVtTilesPerGroup = 16;
+// Columns of U written by one final-pass workgroup of a problem of size n
+// (at least 16384 contiguous doubles per workgroup for small problems).
+__host__ __device__ inline int final_u_cols(int64_t n) {
+  return n >= 16384 ? 1 : (int)(16384 / n < 64 ? 16384 / n : 64);
+}
 // flags of a column touched by a deflation rotation
 constexpr int kRotV = 1;  // its right vector (both deflation rotations)
 constexpr int kRotU = 2;  // its left vector (close-pair rotations only)
@@ -172,10 +177,13 @@ void launch_vectors(const NodeDesc* nodes, int nnodes, int max_m, const Work& w,
 void launch_order(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
 void launch_update(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, const Tuning& tu,
                    hipStream_t st);
+// Final pass: work items of U (groups of final_u_cols columns) and of V^T
+// (64-row bands x kVtTilesPerGroup column tiles), numbered per problem from
+// uitem_off / vitem_off, with item -> problem tables uprob / vprob.
 void launch_final(const int64_t* prob_n, const int64_t* prob_vec, const int64_t* prob_mat,
-                  const int64_t* col_off, const int64_t* tile_off, int nprob, int64_t total_cols,
-                  int64_t total_tiles, const Work& w, double* sigma, double* U, double* VT,
-                  hipStream_t st);
+                  const int64_t* uitem_off, const int64_t* vitem_off, const int32_t* uprob,
+                  const int32_t* vprob, int64_t total_uitems, int64_t total_vitems, const Work& w,
+                  double* sigma, double* U, double* VT, hipStream_t st);
 // device and iteration options of a handle (BDC_OK or BDC_ERR_INVALID_HANDLE)
 int handle_info(bdc_handle_t h, int* device, int* max_secular_iters, int* max_leaf_sweeps);
 // the handle's secular small-problem threshold (launch tuning)

@@ -419,24 +419,45 @@ __global__ __launch_bounds__(256) void k_gemm_plain(int M, int N, int K, const d
 }
 
 // ------------------------------------------------------------------ final
-// U: one workgroup per output column t (descending order); rows in pairs
-// with 16-byte stores when the column start is 16-byte aligned.
+// U: a work item is a group of final_u_cols(n) output columns (one column
+// for n >= 16384, up to 64 short columns otherwise), in descending order.
+// Single columns are written in row pairs with 16-byte stores (four in flight
+// per thread); a group of short columns as one contiguous range.
 __global__ __launch_bounds__(256) void k_final_u(const int64_t* __restrict__ pn,
                                                  const int64_t* __restrict__ pvec,
                                                  const int64_t* __restrict__ pmat,
-                                                 const int64_t* __restrict__ col_off, int nprob,
-                                                 Work w, double* sigma, double* U) {
-  // find the problem owning global column blockIdx.x
-  const int64_t gcol = blockIdx.x;
-  int lo = 0, hi = nprob;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (col_off[mid] <= gcol) lo = mid;
-    else hi = mid;
+                                                 const int64_t* __restrict__ uitem_off,
+                                                 const int32_t* __restrict__ uprob, Work w, double* sigma,
+                                                 double* U) {
+  __shared__ int64_t s_pc[64];
+  __shared__ int s_ul[64], s_uh[64];
+  const int64_t item = blockIdx.x;
+  const int prob = uprob[item];
+  const int64_t n = pn[prob], pv = pvec[prob], mo = pmat[prob];
+  const int G = final_u_cols(n);
+  const int64_t c0 = (item - uitem_off[prob]) * G;
+  const int cols = (int)min((int64_t)G, n - c0);
+  if (cols <= 0) return;
+  if (G > 1) {
+    const int t = threadIdx.x;
+    if (t < cols) {
+      const int64_t tcol = c0 + t, src = n - 1 - tcol;
+      const int64_t pc = w.col[pv + src];
+      s_pc[t] = pc;
+      s_ul[t] = w.ulo[pv + pc];
+      s_uh[t] = w.uhi[pv + pc];
+      sigma[pv + tcol] = w.sig[pv + src];
+    }
+    __syncthreads();
+    double* out = U + mo + c0 * n;
+    const int nn = (int)n, tot = cols * nn;
+    for (int e = t; e < tot; e += kBlock) {
+      const int col = e / nn, row = e - col * nn;
+      out[e] = (row >= s_ul[col] && row < s_uh[col]) ? w.Uw[mo + s_pc[col] * n + row] : 0.0;
+    }
+    return;
   }
-  const int64_t n = pn[lo], pv = pvec[lo], mo = pmat[lo];
-  const int64_t tcol = gcol - col_off[lo];
-  if (tcol >= n) return;
+  const int64_t tcol = c0;
   const int64_t src = n - 1 - tcol;
   const int64_t pc = w.col[pv + src];
   const int64_t ul = w.ulo[pv + pc], uh = w.uhi[pv + pc];
@@ -484,24 +505,19 @@ __global__ __launch_bounds__(256) void k_final_u(const int64_t* __restrict__ pn,
 __global__ __launch_bounds__(256) void k_final_vt(const int64_t* __restrict__ pn,
                                                   const int64_t* __restrict__ pvec,
                                                   const int64_t* __restrict__ pmat,
-                                                  const int64_t* __restrict__ tile_off, int nprob,
-                                                  Work w, double* VT) {
+                                                  const int64_t* __restrict__ vitem_off,
+                                                  const int32_t* __restrict__ vprob, Work w, double* VT) {
   __shared__ double tileS[64][65];
   __shared__ int64_t pcs[64];
   __shared__ int lov[64], hiv[64];
   __shared__ int s_any;
-  // global work item: (problem, band, tile group); tile_off counts items
+  // work item: (problem, band, tile group), numbered per problem from vitem_off
   const int64_t gt = blockIdx.x;
-  int lo = 0, hi = nprob;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (tile_off[mid] <= gt) lo = mid;
-    else hi = mid;
-  }
+  const int lo = vprob[gt];
   const int64_t n = pn[lo], pv = pvec[lo], mo = pmat[lo];
   const int64_t nt = (n + 63) / 64;
   const int64_t ng = (nt + kVtTilesPerGroup - 1) / kVtTilesPerGroup;
-  const int64_t item = gt - tile_off[lo];
+  const int64_t item = gt - vitem_off[lo];
   if (item >= nt * ng) return;
   const int64_t t0 = (item % nt) * 64;  // output rows of V^T (singular vector index)
   const int64_t g0 = (item / nt) * kVtTilesPerGroup;
@@ -630,14 +646,14 @@ void launch_gemm_plain(int M, int N, int K, const double* A, int lda, const doub
 }
 
 void launch_final(const int64_t* prob_n, const int64_t* prob_vec, const int64_t* prob_mat,
-                  const int64_t* col_off, const int64_t* tile_off, int nprob, int64_t total_cols,
-                  int64_t total_tiles, const Work& w, double* sigma, double* U, double* VT,
-                  hipStream_t st) {
-  if (nprob <= 0 || total_cols <= 0) return;
-  hipLaunchKernelGGL(k_final_u, dim3((unsigned)total_cols), dim3(kBlock), 0, st, prob_n, prob_vec,
-                     prob_mat, col_off, nprob, w, sigma, U);
-  hipLaunchKernelGGL(k_final_vt, dim3((unsigned)total_tiles), dim3(kBlock), 0, st, prob_n,
-                     prob_vec, prob_mat, tile_off, nprob, w, VT);
+                  const int64_t* uitem_off, const int64_t* vitem_off, const int32_t* uprob,
+                  const int32_t* vprob, int64_t total_uitems, int64_t total_vitems, const Work& w,
+                  double* sigma, double* U, double* VT, hipStream_t st) {
+  if (total_uitems <= 0) return;
+  hipLaunchKernelGGL(k_final_u, dim3((unsigned)total_uitems), dim3(kBlock), 0, st, prob_n, prob_vec, prob_mat,
+                     uitem_off, uprob, w, sigma, U);
+  hipLaunchKernelGGL(k_final_vt, dim3((unsigned)total_vitems), dim3(kBlock), 0, st, prob_n, prob_vec, prob_mat,
+                     vitem_off, vprob, w, VT);
 }
 
 }  // namespace bdc
