@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 output for the kernels of this library.
 
     python -m paper_2508_11467_amd.profiling stats  STATS_CSV BENCH_JSON OUT_MD TITLE COMMAND
-    python -m paper_2508_11467_amd.profiling traffic FETCH_CSV WRITE_CSV KERNELS COPY_BYTES LAUNCHES OUT_JSON
+    python -m paper_2508_11467_amd.profiling traffic FETCH_CSV WRITE_CSV KERNELS COPY_BYTES LAUNCHES|auto OUT_JSON
 
 ``stats`` turns a ``--kernel-trace --stats`` kernel_stats.csv (and the
 bench.py line of the same run) into a Markdown table.  ``traffic`` reads the
@@ -67,8 +67,11 @@ def _dispatches(path):
 
 
 def traffic(fetch_csv, write_csv, kernels, copy_bytes, launches, out_json):
+    """LAUNCHES = "auto": the number of dispatches of the first named kernel."""
     from .build import source_hash
     frags = [k for k in kernels.split(",") if k]
+    if launches == "auto":
+        launches = sum(1 for n, _ in _dispatches(write_csv) if kernel_label(n) and kernel_label(n).startswith(frags[0]))
     res = {}
     for tag, path in (("fetch", fetch_csv), ("write", write_csv)):
         rows = _dispatches(path)
