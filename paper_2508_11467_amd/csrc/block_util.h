@@ -85,6 +85,40 @@ __device__ inline void block_exscan_n(int (&v)[K], int (&total)[K], int* sh) {
   __syncthreads();
 }
 
+// Exclusive prefix sums of K counters over a block of BS threads (a multiple
+// of 64) with wavefront shuffles: a scan inside each wavefront, then the
+// wavefront totals.  sh must hold K * BS/64 ints.  Same results as
+// block_exscan_n (integer sums), with two barriers.
+template <int K, int BS>
+__device__ inline void block_exscan_w(int (&v)[K], int (&total)[K], int* sh) {
+  constexpr int NW = BS / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int inc[K];
+  for (int q = 0; q < K; ++q) {
+    int x = v[q];
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    inc[q] = x;
+  }
+  __syncthreads();
+  if (lane == 63)
+    for (int q = 0; q < K; ++q) sh[q * NW + wv] = inc[q];
+  __syncthreads();
+  for (int q = 0; q < K; ++q) {
+    int before = 0, all = 0;
+    for (int u = 0; u < NW; ++u) {
+      const int t = sh[q * NW + u];
+      if (u < wv) before += t;
+      all += t;
+    }
+    total[q] = all;
+    v[q] = before + inc[q] - v[q];
+  }
+  __syncthreads();
+}
+
 // Block sum for BS threads; the wave sums are added in wave order.
 template <int BS>
 __device__ inline double block_sum_n(double v, double* sh /* >= BS/64 */) {

@@ -198,26 +198,45 @@ __global__ __launch_bounds__(BS) void k_prep(const NodeDesc* __restrict__ nodes,
     seg_has = 1;
   }
   // previous candidate value at each segment start: right-most defined value
-  // among earlier segments (inclusive scan with "later defined wins")
-  shl[t] = seg_last;
-  shh[t] = seg_has;
-  __syncthreads();
-  for (int off = 1; off < BS; off <<= 1) {
-    double lv = 0.0;
-    int lh = 0;
-    if (t >= off) {
-      lv = shl[t - off];
-      lh = shh[t - off];
+  // among earlier segments.  Inside a wavefront a shuffle scan with "later
+  // defined wins"; across wavefronts the last defined value of the earlier
+  // ones (LDS, one entry per wavefront).
+  double dprev = 0.0;
+  int has_prev = 0;
+  {
+    const int lane = t & 63, wv = t >> 6;
+    double lv = seg_last;
+    int lh = seg_has;
+    for (int off = 1; off < 64; off <<= 1) {
+      const double ov = __shfl_up(lv, off, 64);
+      const int oh = __shfl_up(lh, off, 64);
+      if (lane >= off && !lh && oh) {
+        lv = ov;
+        lh = 1;
+      }
+    }
+    // inclusive value of this lane; the exclusive one is the previous lane's
+    double ev = __shfl_up(lv, 1, 64);
+    int eh = __shfl_up(lh, 1, 64);
+    if (lane == 0) {
+      ev = 0.0;
+      eh = 0;
+    }
+    if (lane == 63) {
+      shl[wv] = lv;
+      shh[wv] = lh;
     }
     __syncthreads();
-    if (t >= off && !shh[t] && lh) {
-      shl[t] = lv;
-      shh[t] = 1;
-    }
-    __syncthreads();
+    if (!eh)
+      for (int u = wv - 1; u >= 0; --u)
+        if (shh[u]) {
+          ev = shl[u];
+          eh = 1;
+          break;
+        }
+    dprev = ev;
+    has_prev = eh;
   }
-  double dprev = t > 0 ? shl[t - 1] : 0.0;
-  int has_prev = t > 0 ? shh[t - 1] : 0;
   __syncthreads();
   // pass 1b: close-pair followers in the segment
   {
@@ -231,7 +250,7 @@ __global__ __launch_bounds__(BS) void k_prep(const NodeDesc* __restrict__ nodes,
       hp = 1;
     }
   }
-  block_exscan_n<3, BS>(cnt, tot, shi);
+  block_exscan_w<3, BS>(cnt, tot, shi);
   const int nzero = tot[0], ncand = tot[1], nclose = tot[2];
   // pass 2: statuses, lists, rotation slots of the followers
   {
@@ -345,7 +364,7 @@ __global__ __launch_bounds__(BS) void k_prep(const NodeDesc* __restrict__ nodes,
       ++cv[5];
     }
   }
-  block_exscan_n<6, BS>(cv, tot6, shi);
+  block_exscan_w<6, BS>(cv, tot6, shi);
   const int N = tot6[0], n1 = tot6[1], n2 = tot6[2], n3 = tot6[3], nz = tot6[4];
   double rho = 0.0;
   for (int pos = p0; pos < p1; ++pos) {

@@ -340,7 +340,7 @@ __global__ __launch_bounds__(256) void k_tile_sched(const NodeDesc* __restrict__
     else v[1] += node_tiles<128>(nd, N);
   }
   int tot[2];
-  block_exscan<2>(v, tot, sh);
+  block_exscan_w<2, kBlock>(v, tot, sh);
   int o64 = v[0], o128 = v[1];
   for (int i = i0; i < i1; ++i) {
     w.tile_off64[i] = o64;
