@@ -354,7 +354,7 @@ def main():
         ms_oz = time_solver(osv, dt, et, (sig, ub, vb), args.steps, args.warmup)
         info_o, _ = osv.info()
         osv.close()
-        ozaki = {"ms_per_step": ms_oz, "value": (8.0 / 3.0) * n ** 3 / (ms_oz * 1e-3) / 1e9, "slices": 6,
+        ozaki = {"ms_per_step": ms_oz, "value": (8.0 / 3.0) * n ** 3 / (ms_oz * 1e-3) / 1e9, "slices": int(osv.options.ozaki_slices),
                  "min_kept_values": 256, "info": info_o,
                  "sigma_max_rel_diff_vs_fp64": float(torch.max(torch.abs(sig - sig_fp64)) / sig_fp64[0]),
                  **accuracy(d, e, sig, ub.T, vb.T)}

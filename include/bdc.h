@@ -82,8 +82,10 @@ typedef struct {
                                  bdc_mlp_set first; same stopping rule, only the
                                  first point of each root's iteration changes) */
   int gemm;                   /* BDC_GEMM_FP64 (default) or BDC_GEMM_OZAKI */
-  int ozaki_slices;           /* slices per operand, 5..7 (default 6: terms dropped
-                                 below about 2^-46 relative to |row| |column|) */
+  int ozaki_slices;           /* slices per operand, 5..7 (default 7: terms dropped
+                                 below about 2^-54 relative to |row| |column|; 6
+                                 leaves about 2^-46, which at n = 16384 exceeds a
+                                 1e-12 residual) */
   int ozaki_min_n;            /* merges with at least this many kept values use the
                                  split products, >= 128 (default 256); smaller ones FP64 */
 } bdc_options_t;
@@ -239,8 +241,10 @@ typedef struct {
                    persistent grid; 0 (default): a grid slice per merge */
   int grid64;   /* workgroups of the 64-tile product (flat), or half the per-merge cap */
   int grid128;  /* the same for the 128-tile product */
-  int sec_small_n; /* secular problems with at most this many roots (0..64; default 0)
-                      are solved with 8 lanes per root and no workgroup barriers */
+  int sec_small_n; /* secular problems with at most this many roots (0..256;
+                      default 256) are solved with 8 or 16 lanes per root and no
+                      workgroup barriers; larger ones with one lane per root and
+                      the poles split over four wavefronts */
   int leaf_size;   /* the tree's leaf size (4..32; 0 in bdc_set_tuning keeps the
                       handle's); the paper found 32 best on its GPUs */
   float ms;     /* out (bdc_autotune): time per solve of the chosen tuning */

@@ -28,7 +28,7 @@ class Solver:
     def __init__(self, device: int | torch.device = 0, leaf_size: int = 32, max_secular_iters: int = 64,
                  max_leaf_sweeps: int = 40, workspace_cap_bytes: int = 0, timing: bool = False,
                  use_graph: bool = True, start: str = "plain", mlp_params=None, gemm: str = "fp64",
-                 ozaki_slices: int = 6, ozaki_min_n: int = 256):
+                 ozaki_slices: int = 7, ozaki_min_n: int = 256):
         """start: "plain" (midpoint) or "learned" (the MLP's proposal; the
         parameters come from ``mlp_params`` (host float32 vector) or, when
         that is None, from the network file shipped with the package).
@@ -55,6 +55,7 @@ class Solver:
         opt.gemm = _lib.BDC_GEMM_OZAKI if gemm == "ozaki" else _lib.BDC_GEMM_FP64
         opt.ozaki_slices = ozaki_slices
         opt.ozaki_min_n = ozaki_min_n
+        self.options = opt
         h = ctypes.c_void_p()
         check("bdc_create", self.lib.bdc_create(ctypes.byref(h), self.device.index, ctypes.byref(opt)))
         self.handle = h
@@ -150,7 +151,7 @@ class Solver:
         d.pop("ms")
         return d
 
-    def set_tuning(self, small_n: int, flat: int, grid64: int, grid128: int, sec_small_n: int = 0,
+    def set_tuning(self, small_n: int, flat: int, grid64: int, grid128: int, sec_small_n: int = 256,
                    leaf_size: int = 0, **_ignored) -> None:
         t = _lib.Tuning(small_n, flat, grid64, grid128, sec_small_n, leaf_size, 0.0)
         check("bdc_set_tuning", self.lib.bdc_set_tuning(self.handle, ctypes.byref(t)))

@@ -97,7 +97,7 @@ struct bdc_handle_s {
   int part_cap = 0;
   Harvest hv{};
   bool harvest = false;
-  Tuning tune{96, 0, 1024, 512, 0};
+  Tuning tune{96, 0, 1024, 512, kSecLanesMaxN};
 };
 
 namespace {
@@ -433,7 +433,8 @@ int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, do
     if (h->harvest) launch_harvest(L.dev, L.nnodes, L.max_m, w, h->hv, st);
     { Timer t(h, st, kLowner); launch_lowner(L.dev, L.nnodes, L.max_m, w, st); }
     { Timer t(h, st, kVectors); launch_vectors(L.dev, L.nnodes, L.max_m, w, st); }
-    { Timer t(h, st, kOrder); launch_order(L.dev, L.nnodes, L.max_m, w, st); }
+    // the update launches carry the merge of roots and deflated values
+    // (k_order) as well
     { Timer t(h, st, kUpdate); launch_update(L.dev, L.nnodes, L.max_m, w, h->tune, st); }
     if (ozaki && L.max_m >= w.oz.min_n) {
       Timer t(h, st, kUpdateOz);
@@ -528,7 +529,7 @@ void bdc_default_options(bdc_options_t* opt) {
   opt->use_graph = 1;
   opt->start = BDC_START_PLAIN;
   opt->gemm = BDC_GEMM_FP64;
-  opt->ozaki_slices = 6;
+  opt->ozaki_slices = 7;
   opt->ozaki_min_n = 256;
 }
 
@@ -700,7 +701,7 @@ namespace {
 bool tuning_valid(const bdc_tuning_t* t) {
   return t->small_n >= 32 && t->small_n <= 4096 && (t->flat == 0 || t->flat == 1) && t->grid64 >= 1 &&
          t->grid64 <= 65535 && t->grid128 >= 1 && t->grid128 <= 65535 && t->sec_small_n >= 0 &&
-         t->sec_small_n <= 64 && (t->leaf_size == 0 || (t->leaf_size >= 4 && t->leaf_size <= kMaxLeaf));
+         t->sec_small_n <= kSecLanesMaxN && (t->leaf_size == 0 || (t->leaf_size >= 4 && t->leaf_size <= kMaxLeaf));
 }
 }  // namespace
 
@@ -777,7 +778,7 @@ int bdc_autotune(bdc_handle_t h, int64_t batch, const int64_t* sizes, const doub
   // 2. launch shapes with that tree
   if (rc == BDC_OK) {
     std::vector<Tuning> cand;
-    for (int ss : {0, 64})
+    for (int ss : {0, 256})
       for (int sn : {64, 96, 192}) {
         cand.push_back(Tuning{sn, 0, 1024, 512, ss});
         for (int gm : {256, 512, 1024}) cand.push_back(Tuning{sn, 1, 2 * gm, gm, ss});

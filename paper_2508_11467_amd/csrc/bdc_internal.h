@@ -28,6 +28,8 @@ namespace bdc {
 constexpr int kMaxLeaf = 32;
 // 64-column tiles of one 64-row band of V^T handled by one final-pass workgroup
 constexpr int kVtTilesPerGroup = 16;
+// largest secular problem the lanes-per-root kernel takes
+constexpr int kSecLanesMaxN = 256;
 // Columns of U written by one final-pass workgroup of a problem of size n
 // (at least 16384 contiguous doubles per workgroup for small problems).
 __host__ __device__ inline int final_u_cols(int64_t n) {
@@ -138,7 +140,7 @@ struct Work {
                                  // or nullptr
   OzWork oz;
   int small_n;        // update products of merges with N <= small_n use 64 x 64 tiles
-  int sec_small_n;    // secular problems with N <= sec_small_n use the 8-lane kernel
+  int sec_small_n;    // secular problems with N <= sec_small_n use the lanes-per-root kernel
   int* tile_off64;    // flattened tile schedule of a level (nnodes + 1 each)
   int* tile_off128;
   NodeState* st;
@@ -162,7 +164,7 @@ struct Tuning {
   int flat;     // 1: persistent grids over a flattened tile list; 0: grid per node
   int grid64;   // workgroups of the 64-tile update (flat), or twice the per-node cap
   int grid128;
-  int sec_small_n;  // secular problems with N <= this (at most 64) use 8 lanes per root
+  int sec_small_n;  // secular problems with N <= this (at most kSecLanesMaxN) use 8 or 16 lanes per root
 };
 
 // ---- launchers (defined next to their kernels) ----

@@ -147,6 +147,107 @@ __global__ __launch_bounds__(256) void k_zsort(const NodeDesc* __restrict__ node
     atomicMax(&w.st[nd.id].zmax_bits, (unsigned long long)__double_as_longlong(lmax));
 }
 
+// Rotations of the values within tol of d_1 = 0 into z_1 (one thread; all
+// near-zero values precede every candidate in the scan order, so they take
+// rotation slots 0..nzero-1).  cand[0..nzero) lists their positions.
+__device__ inline void zero_rotations(const Work& w, int64_t vo, int64_t rb, int r0, int k, int nzero,
+                                      double tol) {
+  if (threadIdx.x != 0) return;
+  double z0 = w.ps_z[vo];
+  for (int q = 0; q < nzero; ++q) {
+    const int j = w.cand[vo + q];
+    const double zj = w.ps_z[vo + j];
+    const double r = sqrt(z0 * z0 + zj * zj);
+    const double c = z0 / r, sn = zj / r;
+    w.rot_pos[rb + 2 * q] = 0;
+    w.rot_pos[rb + 2 * q + 1] = j;
+    w.rot_col[rb + 2 * q] = r0 + k - 1;
+    w.rot_col[rb + 2 * q + 1] = w.ps_col[vo + j];
+    w.rot_cs[rb + 2 * q] = c;
+    w.rot_cs[rb + 2 * q + 1] = sn;
+    z0 = r;
+    w.ps_z[vo + j] = 0.0;
+    w.ps_d[vo + j] = 0.0;
+    w.ps_rot[vo + j] = kRotV;
+  }
+  if (z0 < tol) z0 = tol;  // small z_1 is raised to tol (after the scan)
+  w.ps_z[vo] = z0;
+}
+
+// Runs of close pairs: each kept candidate (status 0) absorbs the followers
+// (status 3) after it in the candidate list cand[nzero .. nzero+ncand), one
+// thread per run; a follower's rotation slot is in sgrp[its position].
+template <int BS>
+__device__ inline void absorb_runs(const Work& w, int64_t vo, int64_t rb, int nzero, int ncand) {
+  for (int u = threadIdx.x; u < ncand; u += BS) {
+    const int pp = w.cand[vo + nzero + u];
+    if (w.status[vo + pp] != 0) continue;
+    double zl = w.ps_z[vo + pp], dl = w.ps_d[vo + pp];
+    int sup = w.ps_sup[vo + pp], rot = 0;
+    for (int v = u + 1; v < ncand; ++v) {
+      const int j = w.cand[vo + nzero + v];
+      if (w.status[vo + j] != 3) break;
+      const double zj = w.ps_z[vo + j];
+      const double r = sqrt(zl * zl + zj * zj);
+      const double c = zl / r, sn = zj / r;
+      const int q = w.sgrp[vo + j];
+      w.rot_pos[rb + 2 * q] = pp;
+      w.rot_pos[rb + 2 * q + 1] = j;
+      w.rot_col[rb + 2 * q] = w.ps_col[vo + pp];
+      w.rot_col[rb + 2 * q + 1] = w.ps_col[vo + j];
+      w.rot_cs[rb + 2 * q] = c;
+      w.rot_cs[rb + 2 * q + 1] = sn;
+      zl = r;
+      dl = w.ps_d[vo + j];
+      rot = kRotU | kRotV;
+      w.ps_z[vo + j] = 0.0;
+      w.ps_rot[vo + j] = kRotU | kRotV;
+      const int sj = w.ps_sup[vo + j];
+      if (sup != sj) {
+        sup = 2;
+        w.ps_sup[vo + j] = 2;
+      }
+    }
+    w.ps_z[vo + pp] = zl;
+    w.ps_d[vo + pp] = dl;
+    w.ps_sup[vo + pp] = sup;
+    w.ps_rot[vo + pp] = rot;
+  }
+}
+
+// x1 and y in place -- the children's null vectors (V columns r0+k-1 and
+// r0+m) rotated by (c0, s0) over the node's rows -- their row supports, and
+// the node's state (st carries the counts and rho; the scale, tol and the
+// rotation are set here).
+template <int BS>
+__device__ inline void finish_node(const NodeDesc& nd, const Work& w, const MergeHead& h, double tol,
+                                   NodeState st) {
+  const int m = nd.m, k = nd.k, s = nd.s, r0 = nd.r0;
+  const int64_t ld = nd.ld, pv = nd.vec_off;
+  double* V = w.Vw + nd.mat_off;
+  const double c0 = h.c0, s0 = h.s0;
+  for (int row = threadIdx.x; row < m + s; row += BS) {
+    const int64_t gr = r0 + row;
+    const double q1 = row < k ? V[gr + (int64_t)(r0 + k - 1) * ld] : 0.0;
+    const double q2 = (s && row >= k) ? V[gr + (int64_t)(r0 + m) * ld] : 0.0;
+    V[gr + (int64_t)(r0 + k - 1) * ld] = c0 * q1 + s0 * q2;
+    if (s) V[gr + (int64_t)(r0 + m) * ld] = -s0 * q1 + c0 * q2;
+  }
+  if (threadIdx.x == 0) {
+    w.vlo[pv + r0 + k - 1] = r0;
+    w.vhi[pv + r0 + k - 1] = r0 + m + s;
+    if (s) {
+      w.vlo[pv + r0 + m] = r0;
+      w.vhi[pv + r0 + m] = r0 + m + s;
+    }
+    st.scale = h.p;
+    st.tol = tol;
+    st.c0 = c0;
+    st.s0 = s0;
+    w.st[nd.id] = st;
+  }
+}
+
 // Deflation of one node (one workgroup).  The scan of the paper's rules over
 // positions 2..m is sequential as written, but its decisions are not: after
 // a candidate (a position whose z is not small and whose value is not within
@@ -166,12 +267,10 @@ __global__ __launch_bounds__(BS) void k_prep(const NodeDesc* __restrict__ nodes,
   __shared__ int sh_cnt[4];
 
   const NodeDesc nd = nodes[blockIdx.x];
-  const int m = nd.m, k = nd.k, s = nd.s, r0 = nd.r0;
-  const int64_t ld = nd.ld, pv = nd.vec_off, vo = nd.vec_off + nd.r0;
-  double* V = w.Vw + nd.mat_off;
+  const int m = nd.m, k = nd.k, r0 = nd.r0;
+  const int64_t vo = nd.vec_off + nd.r0;
   const int t = threadIdx.x;
   const MergeHead h = merge_head(nd, w);
-  const double p = h.p, c0 = h.c0, s0 = h.s0;
   const double zmax = __longlong_as_double((long long)w.st[nd.id].zmax_bits);
   // tol stands for eps * ||M||: 8 * 2^-52 * max(max d, max |z|)
   const double tol = 8.0 * kEps * zmax;
@@ -280,64 +379,8 @@ __global__ __launch_bounds__(BS) void k_prep(const NodeDesc* __restrict__ nodes,
   }
   __syncthreads();
 
-  // rotations into z_1 (one thread; all near-zero values precede every
-  // candidate in the scan order, so they take rotation slots 0..nzero-1)
-  if (t == 0) {
-    double z0 = w.ps_z[vo];
-    for (int q = 0; q < nzero; ++q) {
-      const int j = w.cand[vo + q];
-      const double zj = w.ps_z[vo + j];
-      const double r = sqrt(z0 * z0 + zj * zj);
-      const double c = z0 / r, sn = zj / r;
-      w.rot_pos[rb + 2 * q] = 0;
-      w.rot_pos[rb + 2 * q + 1] = j;
-      w.rot_col[rb + 2 * q] = r0 + k - 1;
-      w.rot_col[rb + 2 * q + 1] = w.ps_col[vo + j];
-      w.rot_cs[rb + 2 * q] = c;
-      w.rot_cs[rb + 2 * q + 1] = sn;
-      z0 = r;
-      w.ps_z[vo + j] = 0.0;
-      w.ps_d[vo + j] = 0.0;
-      w.ps_rot[vo + j] = kRotV;
-    }
-    if (z0 < tol) z0 = tol;  // small z_1 is raised to tol (after the scan)
-    w.ps_z[vo] = z0;
-  }
-  // runs of close pairs: each kept candidate absorbs the followers after it
-  for (int u = t; u < ncand; u += BS) {
-    const int pp = w.cand[vo + nzero + u];
-    if (w.status[vo + pp] != 0) continue;
-    double zl = w.ps_z[vo + pp], dl = w.ps_d[vo + pp];
-    int sup = w.ps_sup[vo + pp], rot = 0;
-    for (int v = u + 1; v < ncand; ++v) {
-      const int j = w.cand[vo + nzero + v];
-      if (w.status[vo + j] != 3) break;
-      const double zj = w.ps_z[vo + j];
-      const double r = sqrt(zl * zl + zj * zj);
-      const double c = zl / r, sn = zj / r;
-      const int q = w.sgrp[vo + j];
-      w.rot_pos[rb + 2 * q] = pp;
-      w.rot_pos[rb + 2 * q + 1] = j;
-      w.rot_col[rb + 2 * q] = w.ps_col[vo + pp];
-      w.rot_col[rb + 2 * q + 1] = w.ps_col[vo + j];
-      w.rot_cs[rb + 2 * q] = c;
-      w.rot_cs[rb + 2 * q + 1] = sn;
-      zl = r;
-      dl = w.ps_d[vo + j];
-      rot = kRotU | kRotV;
-      w.ps_z[vo + j] = 0.0;
-      w.ps_rot[vo + j] = kRotU | kRotV;
-      const int sj = w.ps_sup[vo + j];
-      if (sup != sj) {
-        sup = 2;
-        w.ps_sup[vo + j] = 2;
-      }
-    }
-    w.ps_z[vo + pp] = zl;
-    w.ps_d[vo + pp] = dl;
-    w.ps_sup[vo + pp] = sup;
-    w.ps_rot[vo + pp] = rot;
-  }
+  zero_rotations(w, vo, rb, r0, k, nzero, tol);
+  absorb_runs<BS>(w, vo, rb, nzero, ncand);
   if (t == 0) {
     sh_cnt[0] = ncand;
     sh_cnt[1] = nzero + nclose;
@@ -397,38 +440,301 @@ __global__ __launch_bounds__(BS) void k_prep(const NodeDesc* __restrict__ nodes,
   }
   rho = block_sum_n<BS>(rho, shd);
 
-  // ---- x1 and y in place: rotate the children's null vectors (V columns
-  // r0+k-1 and r0+m) by (c0, s0) over the node's rows
-  for (int row = t; row < m + s; row += BS) {
-    const int64_t gr = r0 + row;
-    const double q1 = row < k ? V[gr + (int64_t)(r0 + k - 1) * ld] : 0.0;
-    const double q2 = (s && row >= k) ? V[gr + (int64_t)(r0 + m) * ld] : 0.0;
-    V[gr + (int64_t)(r0 + k - 1) * ld] = c0 * q1 + s0 * q2;
-    if (s) V[gr + (int64_t)(r0 + m) * ld] = -s0 * q1 + c0 * q2;
-  }
-  if (t == 0) {
-    w.vlo[pv + r0 + k - 1] = r0;
-    w.vhi[pv + r0 + k - 1] = r0 + m + s;
-    if (s) {
-      w.vlo[pv + r0 + m] = r0;
-      w.vhi[pv + r0 + m] = r0 + m + s;
+  NodeState st = w.st[nd.id];
+  st.N = N;
+  st.n1 = n1;
+  st.n2 = n2;
+  st.n3 = n3;
+  st.nrot = sh_cnt[1];
+  st.nzero_d = sh_cnt[2];
+  st.nclose = sh_cnt[3];
+  st.nsmall_z = m - 1 - sh_cnt[0] - sh_cnt[2];
+  st.rho = rho;
+  finish_node<BS>(nd, w, h, tol, st);
+}
+
+
+// lanes below this one with their bit set in M
+__device__ inline int rank_below(uint64_t M) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(M >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)M, 0u));
+}
+
+// Exclusive prefix over the wavefronts of K wave-uniform counts c (lane 0 of
+// each wavefront publishes them); before[] gets the sum over earlier
+// wavefronts, total[] the sum over all.  sh holds K * BS/64 ints.
+template <int K, int BS>
+__device__ inline void wave_exscan(const int (&c)[K], int (&before)[K], int (&total)[K], int* sh) {
+  constexpr int NW = BS / 64;
+  const int wv = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+    for (int q = 0; q < K; ++q) sh[q * NW + wv] = c[q];
+  __syncthreads();
+  for (int q = 0; q < K; ++q) {
+    int b = 0, a = 0;
+    for (int u = 0; u < NW; ++u) {
+      const int x = sh[q * NW + u];
+      if (u < wv) b += x;
+      a += x;
     }
-    NodeState st = w.st[nd.id];
-    st.N = N;
-    st.n1 = n1;
-    st.n2 = n2;
-    st.n3 = n3;
-    st.nrot = sh_cnt[1];
-    st.nzero_d = sh_cnt[2];
-    st.nclose = sh_cnt[3];
-    st.nsmall_z = m - 1 - sh_cnt[0] - sh_cnt[2];
-    st.scale = p;
-    st.tol = tol;
-    st.c0 = c0;
-    st.s0 = s0;
-    st.rho = rho;
-    w.st[nd.id] = st;
+    before[q] = b;
+    total[q] = a;
   }
+}
+
+// The same deflation as k_prep, laid out for the memory system: position
+// pos = 64 (wv Q + q) + lane is handled by lane `lane` of wavefront wv at step
+// q, so every load and store of a step is one contiguous 64-element run, and
+// the node's z and d stay in registers between the passes.  Ranks inside a
+// step come from ballots (scan order = position order = step-major,
+// lane-minor); the previous candidate of a position is the nearest lower lane
+// of its step with a candidate, else the last candidate of the earlier steps
+// and wavefronts.  Decisions, lists and rotations are those of k_prep bit for
+// bit.  Needs m <= 64 Q BS/64.
+template <int BS, int Q>
+__global__ __launch_bounds__(BS) void k_prep_w(const NodeDesc* __restrict__ nodes, Work w) {
+  constexpr int NW = BS / 64;
+  static_assert(Q <= 32, "class bits are kept in 32-bit masks");
+  __shared__ double sh_last[NW];
+  __shared__ int sh_has[NW];
+  __shared__ int shi[6 * NW];
+  __shared__ double shd[NW];
+
+  const NodeDesc nd = nodes[blockIdx.x];
+  const int m = nd.m, k = nd.k, r0 = nd.r0;
+  const int64_t vo = nd.vec_off + nd.r0;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const MergeHead h = merge_head(nd, w);
+  const double zmax = __longlong_as_double((long long)w.st[nd.id].zmax_bits);
+  // tol stands for eps * ||M||: 8 * 2^-52 * max(max d, max |z|)
+  const double tol = 8.0 * kEps * zmax;
+  const int64_t rb = 2 * vo;
+  const int pbase = wv * 64 * Q + lane;
+
+  // ---- pass 1: classes of positions 1..m-1 (bit q of each mask), in
+  // chunks of up to 8 steps whose z and d are loaded together; with more
+  // than one chunk, d is loaded again for the close-pair pass
+  constexpr int QC = Q < 8 ? Q : 8;
+  double dq[QC];
+  uint32_t b_small = 0, b_zero = 0, b_cand = 0;
+  double wl = 0.0;  // the wavefront's last candidate value
+  int wh = 0;
+#pragma unroll
+  for (int q0 = 0; q0 < Q; q0 += QC) {
+    double zc[QC];
+#pragma unroll
+    for (int u = 0; u < QC; ++u) {
+      const int pos = pbase + 64 * (q0 + u);
+      zc[u] = pos < m ? w.ps_z[vo + pos] : 0.0;
+      dq[u] = pos < m ? w.ps_d[vo + pos] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < QC; ++u) {
+      const int q = q0 + u, pos = pbase + 64 * q;
+      if (pos < 1 || pos >= m) continue;
+      const double z = zc[u], d = dq[u];
+      if (fabs(z) < tol || z == 0.0) b_small |= 1u << q;
+      else if (d < tol || d == 0.0) b_zero |= 1u << q;
+      else b_cand |= 1u << q;
+    }
+#pragma unroll
+    for (int u = 0; u < QC; ++u) {
+      const uint64_t M = __ballot((b_cand >> (q0 + u)) & 1u);
+      const double v = __shfl(dq[u], M ? 63 - __clzll((long long)M) : 0, 64);
+      if (M) {
+        wl = v;
+        wh = 1;
+      }
+    }
+  }
+  if (lane == 0) {
+    sh_last[wv] = wl;
+    sh_has[wv] = wh;
+  }
+  __syncthreads();
+  double carry = 0.0;
+  int chas = 0;
+  for (int u = wv - 1; u >= 0; --u)
+    if (sh_has[u]) {
+      carry = sh_last[u];
+      chas = 1;
+      break;
+    }
+  // close-pair followers: d - d_prev < tol against the previous candidate
+  uint32_t b_close = 0;
+  int cnt3[3] = {0, 0, 0};  // near-zero values, candidates, followers (this wavefront)
+#pragma unroll
+  for (int q0 = 0; q0 < Q; q0 += QC) {
+    if (Q > QC) {
+#pragma unroll
+      for (int u = 0; u < QC; ++u) {
+        const int pos = pbase + 64 * (q0 + u);
+        dq[u] = pos < m ? w.ps_d[vo + pos] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < QC; ++u) {
+      const int q = q0 + u;
+      const bool c = (b_cand >> q) & 1u;
+      const uint64_t M = __ballot(c);
+      const uint64_t Mlt = M & ((1ull << lane) - 1ull);
+      const double v = __shfl(dq[u], Mlt ? 63 - __clzll((long long)Mlt) : 0, 64);
+      const double dp = Mlt ? v : carry;
+      const int hp = Mlt ? 1 : chas;
+      const bool close = c && hp && (dq[u] - dp < tol || dq[u] == dp);
+      if (close) b_close |= 1u << q;
+      const uint64_t Mz = __ballot((b_zero >> q) & 1u), Mf = __ballot(close);
+      cnt3[0] += __popcll(Mz);
+      cnt3[1] += __popcll(M);
+      cnt3[2] += __popcll(Mf);
+      const double last = __shfl(dq[u], M ? 63 - __clzll((long long)M) : 0, 64);
+      if (M) {
+        carry = last;
+        chas = 1;
+      }
+    }
+  }
+  int base3[3], tot3[3];
+  wave_exscan<3, BS>(cnt3, base3, tot3, shi);
+  const int nzero = tot3[0], ncand = tot3[1], nclose = tot3[2];
+  // statuses, lists, rotation slots of the followers
+  {
+    int bz = base3[0], bc = base3[1], bf = base3[2];
+#pragma unroll 2
+    for (int q = 0; q < Q; ++q) {
+      const int pos = pbase + 64 * q;
+      const bool sm = (b_small >> q) & 1u, zr = (b_zero >> q) & 1u, cd = (b_cand >> q) & 1u,
+                 cl = (b_close >> q) & 1u;
+      const uint64_t Mz = __ballot(zr), Mc = __ballot(cd), Mf = __ballot(cl);
+      if (sm) {
+        w.status[vo + pos] = 1;  // small z component: z_j -> 0
+        w.ps_z[vo + pos] = 0.0;
+      } else if (zr) {
+        w.status[vo + pos] = 2;  // within tol of d_1 = 0: rotated into z_1, value 0
+        w.cand[vo + bz + rank_below(Mz)] = pos;
+      } else if (cd) {
+        w.status[vo + pos] = cl ? 3 : 0;
+        w.sgrp[vo + pos] = cl ? nzero + bf + rank_below(Mf) : -1;
+        w.cand[vo + nzero + bc + rank_below(Mc)] = pos;
+      }
+      bz += __popcll(Mz);
+      bc += __popcll(Mc);
+      bf += __popcll(Mf);
+    }
+  }
+  __syncthreads();
+  zero_rotations(w, vo, rb, r0, k, nzero, tol);
+  if (nclose > 0) absorb_runs<BS>(w, vo, rb, nzero, ncand);
+  __syncthreads();
+
+  // ---- kept values (ascending), the update order [left | d=0 | both | right]
+  // and the deflated values (the zeros of the d~0 case first, then the rest,
+  // each in position order)
+  // status code per step: 0 kept, 2 zero-d, 1 other deflated, -1 none
+  auto code = [&](int q) -> int {
+    const int pos = pbase + 64 * q;
+    if (pos >= m) return -1;
+    if (((b_small | b_close) >> q) & 1u) return 1;
+    if ((b_zero >> q) & 1u) return 2;
+    return 0;  // candidates that stayed, and position 0
+  };
+  // supports of this thread's positions, 2 bits per step (loaded in chunks)
+  uint32_t supbits = 0;
+#pragma unroll
+  for (int q0 = 0; q0 < Q; q0 += QC) {
+    int sc[QC];
+#pragma unroll
+    for (int u = 0; u < QC; ++u) {
+      const int pos = pbase + 64 * (q0 + u);
+      sc[u] = pos < m ? w.ps_sup[vo + pos] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < QC; ++u) supbits |= (uint32_t)(sc[u] & 3) << (2 * (q0 + u));
+  }
+  auto supq = [&](int q) -> int { return (int)((supbits >> (2 * q)) & 3u); };
+  int cnt6[6] = {0, 0, 0, 0, 0, 0};  // kept, sup 1, sup 2, sup 3, zero-d, other
+#pragma unroll 4
+  for (int q = 0; q < Q; ++q) {
+    const int cq = code(q);
+    const int pos = pbase + 64 * q;
+    const int sup = supq(q);
+    const bool kept = cq == 0, sk = kept && pos > 0;
+    cnt6[0] += __popcll(__ballot(kept));
+    cnt6[1] += __popcll(__ballot(sk && sup == 1));
+    cnt6[2] += __popcll(__ballot(sk && sup == 2));
+    cnt6[3] += __popcll(__ballot(sk && sup == 3));
+    cnt6[4] += __popcll(__ballot(cq == 2));
+    cnt6[5] += __popcll(__ballot(cq == 1));
+  }
+  int base6[6], tot6[6];
+  wave_exscan<6, BS>(cnt6, base6, tot6, shi);
+  const int N = tot6[0], n1 = tot6[1], n2 = tot6[2], n3 = tot6[3], nz = tot6[4];
+  double rho = 0.0;
+  // the copies, four steps' loads at a time
+  constexpr int QW = Q >= 8 ? 4 : (Q < 2 ? Q : 2);
+#pragma unroll 1
+  for (int q0 = 0; q0 < Q; q0 += QW) {
+    double zc[QW], dc[QW];
+    int cc[QW], rc[QW];
+#pragma unroll
+    for (int u = 0; u < QW; ++u) {
+      const int pos = pbase + 64 * (q0 + u);
+      const bool in = pos < m;
+      zc[u] = in ? w.ps_z[vo + pos] : 0.0;
+      dc[u] = in ? w.ps_d[vo + pos] : 0.0;
+      cc[u] = in ? w.ps_col[vo + pos] : 0;
+      rc[u] = in ? w.ps_rot[vo + pos] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < QW; ++u) {
+      const int q = q0 + u;
+      const int cq = code(q);
+      const int pos = pbase + 64 * q;
+      const int sup = supq(q);
+      const bool kept = cq == 0, sk = kept && pos > 0;
+      const uint64_t M0 = __ballot(kept), M1 = __ballot(sk && sup == 1), M2 = __ballot(sk && sup == 2),
+                     M3 = __ballot(sk && sup == 3), M4 = __ballot(cq == 2), M5 = __ballot(cq == 1);
+      if (kept) {
+        const int i = base6[0] + rank_below(M0);
+        int g;
+        if (pos == 0) g = n1;
+        else if (sup == 1) g = base6[1] + rank_below(M1);
+        else if (sup == 2) g = n1 + 1 + base6[2] + rank_below(M2);
+        else g = n1 + 1 + n2 + base6[3] + rank_below(M3);
+        w.sd[vo + i] = dc[u];
+        w.sz[vo + i] = zc[u];
+        w.scol[vo + i] = cc[u];
+        w.srot[vo + i] = rc[u];
+        w.sgrp[vo + i] = g;
+        w.gsurv[vo + g] = i;
+        rho += zc[u] * zc[u];
+      } else if (cq >= 0) {
+        const int qq = cq == 2 ? base6[4] + rank_below(M4) : nz + base6[5] + rank_below(M5);
+        w.dval[vo + qq] = dc[u];
+        w.dcol[vo + qq] = cc[u];
+        w.drot[vo + qq] = rc[u];
+      }
+      base6[0] += __popcll(M0);
+      base6[1] += __popcll(M1);
+      base6[2] += __popcll(M2);
+      base6[3] += __popcll(M3);
+      base6[4] += __popcll(M4);
+      base6[5] += __popcll(M5);
+    }
+  }
+  rho = block_sum_n<BS>(rho, shd);
+
+  NodeState st = w.st[nd.id];
+  st.N = N;
+  st.n1 = n1;
+  st.n2 = n2;
+  st.n3 = n3;
+  st.nrot = nzero + nclose;
+  st.nzero_d = nzero;
+  st.nclose = nclose;
+  st.nsmall_z = m - 1 - ncand - nzero;
+  st.rho = rho;
+  finish_node<BS>(nd, w, h, tol, st);
 }
 
 }  // namespace
@@ -439,9 +745,17 @@ void launch_prep(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hi
   const int cap = 4096 / nnodes;
   if (gy > cap) gy = cap > 0 ? cap : 1;
   hipLaunchKernelGGL(k_zsort, dim3(nnodes, gy), dim3(kBlock), 0, st, nodes, w);
-  // large merges: 1024 threads, a quarter of the sequential segment per thread
-  if (max_m >= 2048) hipLaunchKernelGGL(k_prep<1024>, dim3(nnodes), dim3(1024), 0, st, nodes, w);
-  else hipLaunchKernelGGL(k_prep<256>, dim3(nnodes), dim3(256), 0, st, nodes, w);
+  // one wavefront per node up to 256 values, then 4 and 16 (4 to 16 steps
+  // per lane); beyond 16384 values the segment-per-thread kernel
+  const dim3 g(nnodes);
+  if (max_m <= 64) hipLaunchKernelGGL((k_prep_w<64, 1>), g, dim3(64), 0, st, nodes, w);
+  else if (max_m <= 128) hipLaunchKernelGGL((k_prep_w<64, 2>), g, dim3(64), 0, st, nodes, w);
+  else if (max_m <= 256) hipLaunchKernelGGL((k_prep_w<64, 4>), g, dim3(64), 0, st, nodes, w);
+  else if (max_m <= 1024) hipLaunchKernelGGL((k_prep_w<256, 4>), g, dim3(256), 0, st, nodes, w);
+  else if (max_m <= 4096) hipLaunchKernelGGL((k_prep_w<1024, 4>), g, dim3(1024), 0, st, nodes, w);
+  else if (max_m <= 8192) hipLaunchKernelGGL((k_prep_w<1024, 8>), g, dim3(1024), 0, st, nodes, w);
+  else if (max_m <= 16384) hipLaunchKernelGGL((k_prep_w<1024, 16>), g, dim3(1024), 0, st, nodes, w);
+  else hipLaunchKernelGGL(k_prep<1024>, g, dim3(1024), 0, st, nodes, w);
 }
 
 }  // namespace bdc

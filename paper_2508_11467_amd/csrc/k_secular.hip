@@ -217,8 +217,6 @@ struct Root {
   }
 };
 
-// Largest secular problem the 8-lanes-per-root kernel takes.
-constexpr int kSmallSec = 64;
 
 // Pole staging of the secular kernel; with the in-kernel learned start the
 // network's weights and activations share its LDS (they are done with before
@@ -275,23 +273,31 @@ __device__ inline void count_roots(const Work& w, int N, int iters, int capped) 
 // Start of the iteration: 0 the interval midpoint, 1 a caller-given position
 // (w.xs), 2 the network's proposal computed here (w.mlp_pk).
 //
-// Secular roots of one node with more than kSmallSec kept values: 64 roots
+// Secular roots of one node with more than sec_small_n kept values: 64 roots
 // per workgroup, one per lane; the four wavefronts each sum a quarter of the
 // poles for all 64 roots (staged in LDS, read by every lane at the same
 // address), and wavefront 0 combines the partial sums -- left-pole sums in
 // ascending quarter order, right-pole sums in descending order, so both stay
 // summed from far to near -- and advances each root's iteration.
 template <int kMode>
-__global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ nodes, Work w) {
-  __shared__ SecLds<kMode> L;
-  __shared__ float s_x[kSecRoots];
-  __shared__ double part[kSecWaves][5][kSecRoots];
-  __shared__ double b_ov[kSecRoots], b_tau[kSecRoots];
-  __shared__ int b_need[kSecRoots];
-  __shared__ int b_go;
-  const NodeDesc nd = nodes[blockIdx.x];
-  const int N = w.st[nd.id].N;
-  if (N <= w.sec_small_n) return;  // solved by k_secular_small
+struct WideLds {
+  SecLds<kMode> L;
+  float s_x[kSecRoots];
+  double part[kSecWaves][5][kSecRoots];
+  double b_ov[kSecRoots], b_tau[kSecRoots];
+  int b_need[kSecRoots];
+  int b_go;
+};
+
+template <int kMode>
+__device__ void secular_wide(const NodeDesc& nd, int N, const Work& w, WideLds<kMode>& S) {
+  SecLds<kMode>& L = S.L;
+  float* s_x = S.s_x;
+  double (*part)[5][kSecRoots] = S.part;
+  double* b_ov = S.b_ov;
+  double* b_tau = S.b_tau;
+  int* b_need = S.b_need;
+  int& b_go = S.b_go;
   const double rho = w.st[nd.id].rho;
   const int64_t vo = nd.vec_off + nd.r0;
   const double* __restrict__ d = w.sd + vo;
@@ -414,71 +420,101 @@ __global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ no
   }
 }
 
-// Secular roots of a node with at most kSmallSec kept values: 32 roots per
-// 256-thread workgroup, 8 lanes per root.  Lane `part` of a root sums the
-// poles j = part (mod 8) -- left poles upwards, right poles downwards -- and
-// the 8 partial sums are combined with xor shuffles inside the wavefront, so
-// an evaluation takes about N/8 dependent terms and no workgroup barrier.
-// Every lane of a root then advances the same iteration state.
-constexpr int kSmallLanes = 8;
-constexpr int kSmallRoots = 256 / kSmallLanes;
+// Secular roots of a node with at most kLanesMaxN kept values, L lanes per
+// root (L = 8 or 16; 256/L roots per 256-thread workgroup).  Lane `part` of a
+// root sums the poles j = part (mod L) in ascending order into left (j <= lp)
+// and right sums, so every lane of a wavefront makes the same number of steps
+// whatever its root's interval (the summation order inside a lane differs
+// from the wide kernel's far-to-near order on the right side); the L partial sums are combined with DPP row
+// permutations (no LDS, no barrier), and every lane of a root advances the
+// same iteration state.  A wavefront holds 64/L roots, so it iterates only as
+// long as the slowest of those few.
+constexpr int kLanesMaxN = kSecLanesMaxN;
 struct SmallMlp {
   MlpShared m;
 };
 
-__device__ inline int count_step(int first, int last, int step) {
-  return first > last ? 0 : (last - first) / step + 1;
+// v summed over the aligned group of L lanes (L in {8, 16}; within a DPP row)
+template <int L>
+__device__ inline double group_sum(double v) {
+  static_assert(L == 8 || L == 16, "lanes per root");
+  auto step = [](double x, auto ctrl) -> double {
+    constexpr int c = decltype(ctrl)::value;
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), c, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), c, 0xF, 0xF, false);
+    return x + __hiloint2double(hi, lo);
+  };
+  v = step(v, std::integral_constant<int, 0xB1>{});   // quad_perm [1,0,3,2]: lane ^ 1
+  v = step(v, std::integral_constant<int, 0x4E>{});   // quad_perm [2,3,0,1]: lane ^ 2
+  v = step(v, std::integral_constant<int, 0x141>{});  // row_half_mirror: the other quad of 8
+  if constexpr (L == 16) v = step(v, std::integral_constant<int, 0x140>{});  // row_mirror
+  return v;
 }
 
-template <int kMode>
-__global__ __launch_bounds__(256) void k_secular_small(const NodeDesc* __restrict__ nodes, Work w) {
-  __shared__ double cd[kSmallSec], cz[kSmallSec];
-  __shared__ float s_x[kSecRoots];
-  __shared__ typename std::conditional<kMode == 2, SmallMlp, char>::type M;
-  const NodeDesc nd = nodes[blockIdx.x];
-  const int N = w.st[nd.id].N;
-  const int base = blockIdx.y * kSmallRoots;
-  if (N > w.sec_small_n || base >= N) return;  // uniform over the workgroup
+template <int kMode, int L>
+struct LanesLds {
+  double cd[kLanesMaxN + L], cz[kLanesMaxN + L];
+  float s_x[kSecRoots];
+  typename std::conditional<kMode == 2, SmallMlp, char>::type M;
+};
+
+template <int kMode, int L>
+__device__ void secular_lanes(const NodeDesc& nd, int N, const Work& w, LanesLds<kMode, L>& S) {
+  constexpr int kRoots = 256 / L;
+  double* cd = S.cd;
+  double* cz = S.cz;
+  float* s_x = S.s_x;
+  auto& M = S.M;
+  const int base = blockIdx.y * kRoots;
+  if (base >= N) return;  // uniform over the workgroup
   const double rho = w.st[nd.id].rho;
   const int64_t vo = nd.vec_off + nd.r0;
   const double* __restrict__ d = w.sd + vo;
   const double* __restrict__ z = w.sz + vo;
   constexpr bool learned = kMode != 0;
   const int t = threadIdx.x;
+  // network proposals for the 64 roots from base rounded down to 64
   if constexpr (kMode == 2) {
-    if (N > 1) learned_proposals(w, M.m, d, z, N, rho, 0, s_x);  // all N <= 64 roots
+    if (N > 1) learned_proposals(w, M.m, d, z, N, rho, base & ~(kSecRoots - 1), s_x);
   }
-  if (t < N) {
-    cd[t] = d[t];
-    cz[t] = z[t] * z[t];
+  // poles, padded to whole steps with far poles of weight 0 (their terms are
+  // exact zeros: d^2 - omega^2 is about 2^1000, its reciprocal a normal number)
+  const int steps = (N + L - 1) / L;
+  for (int j = t; j < steps * L; j += 256) {
+    cd[j] = j < N ? d[j] : 0x1p+500;
+    cz[j] = j < N ? z[j] * z[j] : 0.0;
   }
   __syncthreads();
-  const int part = t & (kSmallLanes - 1);
-  const int i = base + t / kSmallLanes;
+  const int part = t & (L - 1);
+  const int i = base + t / L;
   const bool active = i < N;
   Root R;
-  const float xp = kMode == 2 ? s_x[i & 63] : (kMode == 1 && active ? w.xs[vo + i] : 0.0f);
+  const float xp = kMode == 2 ? s_x[i & (kSecRoots - 1)] : (kMode == 1 && active ? w.xs[vo + i] : 0.0f);
   R.init(cd, N, rho, N == 1 ? z[0] : 0.0, i, active, learned, xp);
-  // this lane's poles: left part, part+8, .. <= lp; right from the last
-  // j = part (mod 8) down to the first above lp
-  const int nl = count_step(part, R.lp, kSmallLanes);
-  const int jr = N - 1 - ((N - 1 - part) % kSmallLanes + kSmallLanes) % kSmallLanes;
-  const int jmin = R.lp + 1 + ((part - (R.lp + 1)) % kSmallLanes + kSmallLanes) % kSmallLanes;
-  const int nr = count_step(jmin, jr, kSmallLanes);
   while (R.need) {
-    Part PL{0.0, 0.0, 0.0}, PR{0.0, 0.0, 0.0};
-    if (nl > 0) sum_terms(cd, cz, part, kSmallLanes, nl, R.ov, R.tau, PL);
-    if (nr > 0) sum_terms(cd, cz, jr, -kSmallLanes, nr, R.ov, R.tau, PR);
-    double E = PL.E + PR.E;
-    for (int off = 1; off < kSmallLanes; off <<= 1) {
-      PL.s += __shfl_xor(PL.s, off, 64);
-      PL.ds += __shfl_xor(PL.ds, off, 64);
-      PR.s += __shfl_xor(PR.s, off, 64);
-      PR.ds += __shfl_xor(PR.ds, off, 64);
-      E += __shfl_xor(E, off, 64);
+    // left model poles j <= lp, right ones above (for the last root the
+    // right side is the last pole alone, below the root like the others)
+    double sL = 0.0, sR = 0.0, dL = 0.0, dR = 0.0;
+    for (int q = 0; q < steps; ++q) {
+      const int j = part + q * L;
+      const double dd = cd[j];
+      const double del = ((dd - R.ov) - R.tau) * ((dd + R.ov) + R.tau);  // d_j^2 - omega^2
+      const double r = recip(del);
+      const double tj = cz[j] * r;
+      const double tl = j <= R.lp ? tj : 0.0, tg = tj - tl;  // exact split
+      sL += tl;
+      sR += tg;
+      dL = fma(tl, r, dL);
+      dR = fma(tg, r, dR);
     }
-    const double f = (1.0 + PL.s) + PR.s;
-    R.update(f, PL.ds, PR.ds, 1.0 + E, rho, w.max_secular_iters, learned);
+    sL = group_sum<L>(sL);
+    sR = group_sum<L>(sR);
+    dL = group_sum<L>(dL);
+    dR = group_sum<L>(dR);
+    // left terms are negative and right ones positive (the last root's one
+    // right term is negative too): sum |t| = |sR| - sL
+    const double f = (1.0 + sL) + sR;
+    R.update(f, dL, dR, 1.0 + (fabs(sR) - sL), rho, w.max_secular_iters, learned);
   }
   const bool writer = active && part == 0;
   if (writer) {
@@ -487,6 +523,21 @@ __global__ __launch_bounds__(256) void k_secular_small(const NodeDesc* __restric
     w.iters[vo + i] = R.iters;
   }
   count_roots(w, N, writer ? R.iters : 0, writer ? R.capped : 0);
+}
+
+// One launch per level: a node with at most sec_small_n (<= kLanesMaxN) kept
+// values is solved by the lanes-per-root body, a larger one by the wide body;
+// the two share the workgroup's LDS.
+template <int kMode, int L>
+__global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ nodes, Work w) {
+  __shared__ union {
+    WideLds<kMode> wide;
+    LanesLds<kMode, L> lanes;
+  } S;
+  const NodeDesc nd = nodes[blockIdx.x];
+  const int N = w.st[nd.id].N;
+  if (N <= w.sec_small_n && N <= kLanesMaxN) secular_lanes<kMode, L>(nd, N, w, S.lanes);
+  else secular_wide<kMode>(nd, N, w, S.wide);
 }
 
 __global__ __launch_bounds__(256) void k_lowner(const NodeDesc* __restrict__ nodes, Work w) {
@@ -576,20 +627,23 @@ inline int grid_y(int nnodes, int units, int cap_total) {
 
 void launch_secular(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {
   if (nnodes <= 0) return;
-  const int gy = grid_y(nnodes, (max_m + kSecRoots - 1) / kSecRoots, 4096);
-  const dim3 grid(nnodes, gy), block(kSecRoots * kSecWaves);
-  const dim3 sgrid(nnodes, kSmallSec / kSmallRoots);
-  const bool small = w.sec_small_n > 0, big = max_m > w.sec_small_n;
-  if (w.mlp_pk) {
-    if (small) hipLaunchKernelGGL(k_secular_small<2>, sgrid, dim3(256), 0, st, nodes, w);
-    if (big) hipLaunchKernelGGL(k_secular<2>, grid, block, 0, st, nodes, w);
-  } else if (w.xs) {
-    if (small) hipLaunchKernelGGL(k_secular_small<1>, sgrid, dim3(256), 0, st, nodes, w);
-    if (big) hipLaunchKernelGGL(k_secular<1>, grid, block, 0, st, nodes, w);
-  } else {
-    if (small) hipLaunchKernelGGL(k_secular_small<0>, sgrid, dim3(256), 0, st, nodes, w);
-    if (big) hipLaunchKernelGGL(k_secular<0>, grid, block, 0, st, nodes, w);
-  }
+  // 8 lanes per root while the merges are at most 64 values, else 16
+  const bool l8 = max_m <= 64;
+  const int small_max = std::min(std::min(w.sec_small_n, kLanesMaxN), max_m);
+  const int ys = (small_max + (l8 ? 32 : 16) - 1) / (l8 ? 32 : 16);
+  const int yw = max_m > small_max ? (max_m + kSecRoots - 1) / kSecRoots : 0;
+  const int gy = grid_y(nnodes, std::max(ys, yw), 4096 + nnodes * ys);
+  const dim3 grid(nnodes, gy), block(256);
+  const int mode = w.mlp_pk ? 2 : (w.xs ? 1 : 0);
+#define BDC_LAUNCH_SEC(M)                                                                        \
+  do {                                                                                           \
+    if (l8) hipLaunchKernelGGL((k_secular<M, 8>), grid, block, 0, st, nodes, w);                 \
+    else hipLaunchKernelGGL((k_secular<M, 16>), grid, block, 0, st, nodes, w);                   \
+  } while (0)
+  if (mode == 2) BDC_LAUNCH_SEC(2);
+  else if (mode == 1) BDC_LAUNCH_SEC(1);
+  else BDC_LAUNCH_SEC(0);
+#undef BDC_LAUNCH_SEC
 }
 
 void launch_lowner(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {

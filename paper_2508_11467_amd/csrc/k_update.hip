@@ -119,8 +119,7 @@ __device__ inline double root_value(const double* d, const int* o, const double*
   return d[o[i]] + tau[i];
 }
 
-__global__ __launch_bounds__(256) void k_order(const NodeDesc* __restrict__ nodes, Work w) {
-  const NodeDesc nd = nodes[blockIdx.x];
+__device__ inline void order_node(const NodeDesc& nd, const Work& w) {
   const NodeState st = w.st[nd.id];
   const int N = st.N, m = nd.m, s = nd.s, r0 = nd.r0, D = nd.m - st.N;
   const int64_t pv = nd.vec_off, vo = nd.vec_off + nd.r0;
@@ -173,6 +172,10 @@ __global__ __launch_bounds__(256) void k_order(const NodeDesc* __restrict__ node
   }
 }
 
+__global__ __launch_bounds__(256) void k_order(const NodeDesc* __restrict__ nodes, Work w) {
+  order_node(nodes[blockIdx.x], w);
+}
+
 // ------------------------------------------------------------------ GEMM
 // TM x TN output tile per 256-thread workgroup: four wavefronts in 2 x 2, each
 // owning a (TM/2) x (TN/2) block as (TM/32) x (TN/32) v_mfma_f64_16x16x4f64
@@ -194,6 +197,10 @@ __device__ inline void gemm_tile(TileSmem<TM, TN>& sm, const double* __restrict_
   constexpr int FA = TM * TK / kBlock;  // A elements per thread per slab
   constexpr int FB = TN * TK / kBlock;
   constexpr int BM = TM / 32, BN = TN / 32;  // 16x16 blocks per wavefront
+  // slabs in flight: the merges' products are short (K is the kept size of a
+  // half), so the 64-tile form loads up to four slabs before the first is
+  // used and pays the memory latency once for K <= 64
+  constexpr int P = TM <= 64 ? 4 : 1;
   const int t = threadIdx.x, wv = t >> 6, l = t & 63;
   const int wm = wv & 1, wn = wv >> 1;
   const int li = l & 15, lk = l >> 4;
@@ -202,50 +209,58 @@ __device__ inline void gemm_tile(TileSmem<TM, TN>& sm, const double* __restrict_
   for (int a = 0; a < BM; ++a)
 #pragma unroll
     for (int b = 0; b < BN; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-  double ra[FA], rb[FB];
-  auto load = [&](int k0) {
+  double ra[P][FA], rb[P][FB];
+  auto load = [&](double (&xa)[FA], double (&xb)[FB], int k0) {
 #pragma unroll
     for (int q = 0; q < FA; ++q) {
       const int e = t + kBlock * q;
       const int r = e % TM, kk = e / TM;
       const int gr = tm0 + r, gk = k0 + kk;
-      ra[q] = (gr < M && gk < K) ? A[gr + (int64_t)gk * lda] : 0.0;
+      xa[q] = (gr < M && gk < K) ? A[gr + (int64_t)gk * lda] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < FB; ++q) {
       const int e = t + kBlock * q;
       const int kk = e % TK, c = e / TK;
       const int gk = k0 + kk, gc = tn0 + c;
-      rb[q] = (gk < K && gc < N) ? B[gk + (int64_t)gc * ldb] : 0.0;
+      xb[q] = (gk < K && gc < N) ? B[gk + (int64_t)gc * ldb] : 0.0;
     }
   };
-  if (K > 0) load(0);
-  for (int k0 = 0; k0 < K; k0 += TK) {
-    __syncthreads();
+  const int nslab = (K + TK - 1) / TK;
 #pragma unroll
-    for (int q = 0; q < FA; ++q) {
-      const int e = t + kBlock * q;
-      sm.A[(e / TM) * TM + e % TM] = ra[q];
-    }
+  for (int p = 0; p < P; ++p)
+    if (p < nslab) load(ra[p], rb[p], p * TK);
+  for (int s0 = 0; s0 < nslab; s0 += P) {
 #pragma unroll
-    for (int q = 0; q < FB; ++q) {
-      const int e = t + kBlock * q;
-      sm.B[(e % TK) * TN + e / TK] = rb[q];
-    }
-    __syncthreads();
-    if (k0 + TK < K) load(k0 + TK);
+    for (int p = 0; p < P; ++p) {
+      const int sl = s0 + p;
+      if (sl >= nslab) break;
+      __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < TK; kk += 4) {
-      double af[BM], bf[BN];
+      for (int q = 0; q < FA; ++q) {
+        const int e = t + kBlock * q;
+        sm.A[(e / TM) * TM + e % TM] = ra[p][q];
+      }
 #pragma unroll
-      for (int a = 0; a < BM; ++a) af[a] = sm.A[(kk + lk) * TM + wm * (TM / 2) + a * 16 + li];
+      for (int q = 0; q < FB; ++q) {
+        const int e = t + kBlock * q;
+        sm.B[(e % TK) * TN + e / TK] = rb[p][q];
+      }
+      __syncthreads();
+      if (sl + P < nslab) load(ra[p], rb[p], (sl + P) * TK);
 #pragma unroll
-      for (int b = 0; b < BN; ++b) bf[b] = sm.B[(kk + lk) * TN + wn * (TN / 2) + b * 16 + li];
+      for (int kk = 0; kk < TK; kk += 4) {
+        double af[BM], bf[BN];
 #pragma unroll
-      for (int a = 0; a < BM; ++a)
+        for (int a = 0; a < BM; ++a) af[a] = sm.A[(kk + lk) * TM + wm * (TM / 2) + a * 16 + li];
 #pragma unroll
-        for (int b = 0; b < BN; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < BN; ++b) bf[b] = sm.B[(kk + lk) * TN + wn * (TN / 2) + b * 16 + li];
+#pragma unroll
+        for (int a = 0; a < BM; ++a)
+#pragma unroll
+          for (int b = 0; b < BN; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+      }
     }
   }
   // D[i][j] of a 16x16 block sits in lane j + 16 * (i % 4), register i / 4
@@ -276,12 +291,18 @@ struct NodeStore {
 // 128 x 128 (tunable); each launch skips the nodes of the other class.
 
 // grid: (node, tile slot, side-half).  side-half: 0 U rows [0,k), 1 U rows
-// [k,m), 2 V rows [0,k), 3 V rows [k,m+s).  Tiles are visited with the row
+// [k,m), 2 V rows [0,k), 3 V rows [k,m+s); the 64-tile launch has a fifth
+// slice z = 4 whose workgroups do k_order's work (it touches none of the
+// products' data), saving a launch per level.  Tiles are visited with the row
 // index fastest, so the workgroups on one XCD (every 8th) share B panels.
 template <int TM, int TN>
 __global__ __launch_bounds__(256) void k_update(const NodeDesc* __restrict__ nodes, Work w) {
   __shared__ TileSmem<TM, TN> sm;
   const NodeDesc nd = nodes[blockIdx.x];
+  if (blockIdx.z == 4) {  // the 64-tile launch also carries the node's k_order work
+    order_node(nd, w);
+    return;
+  }
   const NodeState st = w.st[nd.id];
   const int N = st.N, n1 = st.n1, n2 = st.n2;
   if ((TM <= 64) != (N <= w.small_n)) return;
@@ -613,6 +634,7 @@ void launch_update(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, 
                    hipStream_t st) {
   if (nnodes <= 0) return;
   if (tu.flat) {
+    launch_order(nodes, nnodes, max_m, w, st);
     hipLaunchKernelGGL(k_tile_sched, dim3(1), dim3(kBlock), 0, st, nodes, nnodes, w);
     hipLaunchKernelGGL((k_update_flat<64, 64>), dim3(tu.grid64), dim3(kBlock), 0, st, nodes, nnodes, w);
     if (max_m > w.small_n)
@@ -622,7 +644,7 @@ void launch_update(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, 
   {
     const int tiles = ((max_m + 1 + 63) / 64) * ((std::min(max_m, w.small_n) + 63) / 64);
     const int gy = grid_y(nnodes, tiles, tu.grid64 * 2);
-    hipLaunchKernelGGL((k_update<64, 64>), dim3(nnodes, gy, 4), dim3(kBlock), 0, st, nodes, w);
+    hipLaunchKernelGGL((k_update<64, 64>), dim3(nnodes, gy, 5), dim3(kBlock), 0, st, nodes, w);
   }
   if (max_m > w.small_n) {
     const int tiles = ((max_m + 1 + 127) / 128) * ((max_m + 127) / 128);

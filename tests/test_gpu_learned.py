@@ -131,7 +131,7 @@ def test_training_lowers_the_loss(solver):
     assert l1 < 0.5 * l0, (l0, l1)
 
 
-@pytest.mark.parametrize("small", [0, 64])
+@pytest.mark.parametrize("small", [0, 256])
 @pytest.mark.parametrize("how", ["labels", "random", "ends"])
 def test_learned_secular_matches_oracle(solver, how, small):
     solver.set_tuning(small_n=96, flat=0, grid64=1024, grid128=512, sec_small_n=small)
@@ -217,7 +217,7 @@ def _solve_checks(s, d, e):
     return sig.cpu().numpy(), U.cpu().numpy(), VT.cpu().numpy(), st
 
 
-@pytest.mark.parametrize("small", [0, 64])
+@pytest.mark.parametrize("small", [0, 256])
 def test_untrained_network_keeps_the_tolerances(gpu, small):
     """Any proposal is safe: the safeguarded iteration still converges."""
     from paper_2508_11467_amd.api import Solver

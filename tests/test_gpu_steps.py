@@ -172,6 +172,60 @@ def test_deflation_bit_exact(solver, n, s, seed, kind):
         assert (c, sn) == (cs[0], cs[1])
 
 
+def _synthetic_children(n, s, seed):
+    """Merge inputs drawn directly (no child SVDs, so any size is cheap): a
+    fifth of the right child's values copied from the left child (close
+    pairs), values at the rounding level (d ~ 0), a quarter of each child's
+    null-vector entries scaled by 1e-17 (small z)."""
+    g = np.random.default_rng(seed)
+    k = n // 2
+    m2 = n - k
+    sig1 = np.sort(g.uniform(0, 2, k - 1))
+    sig2 = g.uniform(0, 2, m2)
+    shared = g.choice(m2, size=min(m2, k - 1) // 5, replace=False)
+    sig2[shared] = sig1[g.choice(k - 1, size=shared.size, replace=False)]
+    sig1[:3] = [0.0, 1e-18, 3e-17]
+    sig2[:2] = [0.0, 2e-17]
+    sig1 = np.sort(sig1)
+    sig2 = np.sort(sig2)
+    q1 = g.normal(size=k)
+    q1 /= np.linalg.norm(q1)
+    q2 = g.normal(size=m2 + s)
+    q2 /= np.linalg.norm(q2)
+    q1[g.choice(k - 1, size=k // 4, replace=False)] *= 1e-17
+    q2[g.choice(m2, size=m2 // 4, replace=False)] *= 1e-17
+    return sig1, sig2, q1, q2, g.uniform(-1, 1), g.uniform(-1, 1)
+
+
+# sizes through every launch shape of the deflation kernel: one wavefront
+# (up to 64, 128, 256 values), 4 wavefronts, 16 wavefronts with 4, 8 and 16
+# steps per lane, and beyond 16384 values
+@pytest.mark.parametrize("n,s,seed", [
+    (40, 0, 21), (100, 1, 22), (250, 0, 23), (700, 1, 24), (1900, 0, 25), (3500, 1, 26),
+    (6000, 0, 27), (12000, 1, 28), (16384, 0, 29), (20000, 0, 30),
+])
+def test_deflation_bit_exact_synthetic(solver, n, s, seed):
+    sig1, sig2, q1, q2, alpha, beta = _synthetic_children(n, s, seed)
+    pr = oracle.merge_prep(sig1, sig2, q1, q2, alpha, beta, s)
+    assert set(np.unique(pr.status[1:]).tolist()) == {0, 1, 2, 3}
+    sig = np.concatenate([sig1, [0.0], sig2])
+    got = solver.step_deflate(n, s, sig, q1, q2, alpha, beta)
+    assert got["tol"] == pr.tol
+    assert np.array_equal(got["perm"], pr.perm)
+    assert np.array_equal(got["d"], pr.d)
+    assert np.array_equal(got["z"], pr.z)
+    st = got["status"].copy()
+    st[0] = 0
+    assert np.array_equal(st, pr.status)
+    assert got["N"] == len(pr.survivors)
+    assert got["counts"] == pr.counts
+    assert got["rot_pos"].shape[0] == len(pr.rots)
+    pos = np.array([(p, j) for _, p, j, _, _ in pr.rots])
+    cs = np.array([(c, sn) for _, _, _, c, sn in pr.rots])
+    assert np.array_equal(got["rot_pos"], pos)
+    assert np.array_equal(got["rot_cs"], cs)
+
+
 def test_deflation_exercises_all_cases(solver):
     """The bit-exact cases above cover every deflation branch."""
     seen = set()
@@ -215,22 +269,28 @@ def test_secular_residual_pins_oracle():
 
 
 @pytest.fixture(scope="module")
-def solver8(gpu):
-    """A handle whose secular problems of up to 64 roots take the 8-lanes-per-
-    root kernel."""
+def solver_lanes(gpu):
+    """A handle whose secular problems of up to 256 roots take the
+    lanes-per-root kernel (8 lanes up to 64 values, else 16)."""
     from paper_2508_11467_amd.api import Solver
     s = Solver(0)
-    s.set_tuning(small_n=96, flat=0, grid64=1024, grid128=512, sec_small_n=64)
+    s.set_tuning(small_n=96, flat=0, grid64=1024, grid128=512, sec_small_n=256)
     yield s
     s.close()
 
 
-@pytest.mark.parametrize("kernel", ["wide", "small"])
-@pytest.mark.parametrize("N,seed", [(1, 0), (2, 1), (3, 2), (9, 7), (33, 8), (64, 3), (65, 4), (500, 5),
-                                    (3000, 6)])
-def test_secular_matches_oracle(solver, solver8, kernel, N, seed):
+@pytest.mark.parametrize("kernel", ["wide", "lanes"])
+@pytest.mark.parametrize("N,seed", [(1, 0), (2, 1), (3, 2), (9, 7), (33, 8), (64, 3), (65, 4), (130, 9),
+                                    (256, 10), (257, 11), (500, 5), (3000, 6)])
+def test_secular_matches_oracle(solver, solver_lanes, kernel, N, seed):
     d, z = _arrow(N, seed)
-    o, tau, it = (solver if kernel == "wide" else solver8).step_secular(d, z)
+    s = solver if kernel == "wide" else solver_lanes
+    keep = s.tuning()
+    s.set_tuning(small_n=96, flat=0, grid64=1024, grid128=512, sec_small_n=0 if kernel == "wide" else 256)
+    try:
+        o, tau, it = s.step_secular(d, z)
+    finally:
+        s.set_tuning(**{k: keep[k] for k in ("small_n", "flat", "grid64", "grid128", "sec_small_n")})
     o, tau, it = o.cpu().numpy(), tau.cpu().numpy(), it.cpu().numpy()
     ro, rt, rit = oracle.secular_roots(d, z)
     w = d[o] + tau
