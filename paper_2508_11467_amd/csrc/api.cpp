@@ -253,7 +253,8 @@ int ensure_workspace(bdc_handle_t h, int64_t tn, int64_t tn2, int nnodes) {
   const size_t nd_ = (size_t)std::max(nnodes, 1);
   size_t bytes = 4 * align_up(N2 * 8) + 8 * align_up(N1 * 8) + align_up(2 * N1 * 8) +
                  19 * align_up(N1 * 4) + 2 * align_up(2 * N1 * 4) + align_up(N1 * 4) +
-                 2 * align_up((nd_ + 1) * 4) + align_up(nd_ * sizeof(NodeState)) + align_up(sizeof(Ctl));
+                 2 * align_up((nd_ + 1) * 4) + align_up(nd_ * sizeof(NodeState)) + align_up(sizeof(Ctl)) +
+                 align_up(2 * N1 * sizeof(int4));
   if (h->opt.workspace_cap_bytes && bytes > h->opt.workspace_cap_bytes) return BDC_ERR_NOMEM;
   if (h->arena) {
     if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
@@ -315,6 +316,7 @@ int ensure_workspace(bdc_handle_t h, int64_t tn, int64_t tn2, int nnodes) {
   w.tile_off128 = (int*)take((nd_ + 1) * 4);
   w.st = (NodeState*)take(nd_ * sizeof(NodeState));
   w.ctl = (Ctl*)take(sizeof(Ctl));
+  w.fin = (int4*)take(2 * N1 * sizeof(int4));
   h->cap_n = tn;
   h->cap_n2 = tn2;
   h->cap_nodes = nnodes;
@@ -444,8 +446,13 @@ int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, do
   {
     Timer t(h, st, kFinal);
     const int64_t np = p.nprob;
-    launch_final(p.dev_prob, p.dev_prob + np, p.dev_prob + 2 * np, p.dev_prob + 3 * np, p.dev_prob + 4 * np,
-                 p.dev_uprob, p.dev_vprob, p.total_cols, p.total_tiles, w, sigma, U, VT, st);
+    // a single problem whose size is a multiple of 8 chunks (4096) takes the
+    // XCD-aligned 4 KB-chunk form
+    if (np == 1 && p.sizes[0] % (8 * kFinalChunk) == 0)
+      launch_final_single(p.sizes[0], w, sigma, U, VT, st);
+    else
+      launch_final(p.dev_prob, p.dev_prob + np, p.dev_prob + 2 * np, p.dev_prob + 3 * np, p.dev_prob + 4 * np,
+                   p.dev_uprob, p.dev_vprob, p.total_cols, p.total_tiles, w, sigma, U, VT, st);
   }
   if (hipGetLastError() != hipSuccess) return BDC_ERR_HIP;
   h->last_stream = st;

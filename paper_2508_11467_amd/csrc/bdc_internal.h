@@ -30,6 +30,8 @@ constexpr int kMaxLeaf = 32;
 constexpr int kVtTilesPerGroup = 16;
 // largest secular problem the lanes-per-root kernel takes
 constexpr int kSecLanesMaxN = 256;
+// doubles per 4 KB output chunk of the single-problem final pass
+constexpr int kFinalChunk = 512;
 // Columns of U written by one final-pass workgroup of a problem of size n
 // (at least 16384 contiguous doubles per workgroup for small problems).
 __host__ __device__ inline int final_u_cols(int64_t n) {
@@ -136,6 +138,7 @@ struct Work {
   int32_t* rot_col;  //   physical columns (2 per rotation)
   double* rot_cs;    //   (c, s)
   float* xs;         // caller-given start of each root in its interval, or nullptr
+  int4* fin;         // final pass of a single problem: per output index, (column, lo, hi) of U then of V
   const unsigned short* mlp_pk;  // packed network for the in-kernel learned start,
                                  // or nullptr
   OzWork oz;
@@ -182,6 +185,7 @@ void launch_update(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, 
 // Final pass: work items of U (groups of final_u_cols columns) and of V^T
 // (64-row bands x kVtTilesPerGroup column tiles), numbered per problem from
 // uitem_off / vitem_off, with item -> problem tables uprob / vprob.
+void launch_final_single(int64_t n, const Work& w, double* sigma, double* U, double* VT, hipStream_t st);
 void launch_final(const int64_t* prob_n, const int64_t* prob_vec, const int64_t* prob_mat,
                   const int64_t* uitem_off, const int64_t* vitem_off, const int32_t* uprob,
                   const int32_t* vprob, int64_t total_uitems, int64_t total_vitems, const Work& w,

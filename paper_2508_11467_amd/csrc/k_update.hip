@@ -4,8 +4,9 @@
 //              list in order.  Columns touched are first zero-filled outside
 //              their support so the rotated columns are dense over the node.
 //   k_gather   copies the kept columns, in update order [left-only | d = 0 |
-//              mixed | right-only], into the compact GU / GV blocks.  Deflated
-//              columns are not moved at all.
+//              mixed | right-only], into the compact GU / GV blocks (a node's
+//              columns as one flattened element range).  Deflated columns are
+//              not moved at all.
 //   k_order    merges the roots with the deflated values (Algorithm 2 step
 //              (3)'s sort, done per node), records each sorted position's
 //              physical column and updates the supports.
@@ -78,38 +79,64 @@ __global__ __launch_bounds__(256) void k_rotate(const NodeDesc* __restrict__ nod
 }
 
 // ------------------------------------------------------------------ gather
+// The node's kept columns in update order, both sides, as one flattened
+// range of N (m + s) elements (column g, row r) -> g (m + s) + r; a workgroup
+// takes slabs of kGatherSlab consecutive elements (four per thread, loads
+// issued before the stores), so that few long columns and many short ones
+// alike fill the workgroups.  U rows run to m, V rows to m + s.
+constexpr int kGatherSlab = 4 * kBlock;
+
 __global__ __launch_bounds__(256) void k_gather(const NodeDesc* __restrict__ nodes, Work w) {
   const NodeDesc nd = nodes[blockIdx.x];
   const int N = w.st[nd.id].N;
   const int m = nd.m, s = nd.s, r0 = nd.r0, k = nd.k;
+  const int R = m + s;
   const int64_t ld = nd.ld, pv = nd.vec_off, vo = nd.vec_off + nd.r0;
   const double* U = w.Uw + nd.mat_off;
   const double* V = w.Vw + nd.mat_off;
   double* GU = w.GU + nd.mat_off;
   double* GV = w.GV + nd.mat_off;
-  for (int g = blockIdx.y; g < N; g += gridDim.y) {
-    const int i = w.gsurv[vo + g];
-    double* gu = GU + r0 + (int64_t)(r0 + g) * ld;
-    double* gv = GV + r0 + (int64_t)(r0 + g) * ld;
-    if (i == 0) {
-      // d = 0 position: left vector e_{k-1} (the middle row), right vector x1
-      const int64_t pc = r0 + k - 1;
-      for (int row = threadIdx.x; row < m; row += kBlock) gu[row] = (row == k - 1) ? 1.0 : 0.0;
-      for (int row = threadIdx.x; row < m + s; row += kBlock) gv[row] = V[(r0 + row) + pc * ld];
-    } else {
-      const int64_t pc = w.scol[vo + i];
-      const int rf = w.srot[vo + i];
-      const bool fu = (rf & kRotU) != 0, fv = (rf & kRotV) != 0;
-      const int ul = fu ? r0 : w.ulo[pv + pc], uh = fu ? r0 + m : w.uhi[pv + pc];
-      const int vl = fv ? r0 : w.vlo[pv + pc], vh = fv ? r0 + m + s : w.vhi[pv + pc];
-      for (int row = threadIdx.x; row < m; row += kBlock) {
-        const int gr = r0 + row;
-        gu[row] = (gr >= ul && gr < uh) ? U[gr + pc * ld] : 0.0;
+  const int64_t total = (int64_t)N * R;
+  const int64_t units = (total + kGatherSlab - 1) / kGatherSlab;
+  const double inv_r = 1.0 / (double)R;
+  for (int64_t u = blockIdx.y; u < units; u += gridDim.y) {
+    double xu[4], xv[4];
+    int gq[4], rq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t e = u * kGatherSlab + q * kBlock + threadIdx.x;
+      gq[q] = -1;
+      rq[q] = 0;
+      xu[q] = xv[q] = 0.0;
+      if (e >= total) continue;
+      int g = (int)((double)e * inv_r);
+      if ((int64_t)g * R > e) --g;
+      else if ((int64_t)(g + 1) * R <= e) ++g;
+      const int row = (int)(e - (int64_t)g * R);
+      gq[q] = g;
+      rq[q] = row;
+      const int i = w.gsurv[vo + g];
+      const int gr = r0 + row;
+      if (i == 0) {
+        // d = 0 position: left vector e_{k-1} (the middle row), right vector x1
+        xu[q] = (row == k - 1) ? 1.0 : 0.0;
+        xv[q] = V[gr + (int64_t)(r0 + k - 1) * ld];
+      } else {
+        const int64_t pc = w.scol[vo + i];
+        const int rf = w.srot[vo + i];
+        const bool fu = (rf & kRotU) != 0, fv = (rf & kRotV) != 0;
+        const int ul = fu ? r0 : w.ulo[pv + pc], uh = fu ? r0 + m : w.uhi[pv + pc];
+        const int vl = fv ? r0 : w.vlo[pv + pc], vh = fv ? r0 + m + s : w.vhi[pv + pc];
+        xu[q] = (row < m && gr >= ul && gr < uh) ? U[gr + pc * ld] : 0.0;
+        xv[q] = (gr >= vl && gr < vh) ? V[gr + pc * ld] : 0.0;
       }
-      for (int row = threadIdx.x; row < m + s; row += kBlock) {
-        const int gr = r0 + row;
-        gv[row] = (gr >= vl && gr < vh) ? V[gr + pc * ld] : 0.0;
-      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (gq[q] < 0) continue;
+      const int64_t off = r0 + rq[q] + (int64_t)(r0 + gq[q]) * ld;
+      if (rq[q] < m) GU[off] = xu[q];
+      GV[off] = xv[q];
     }
   }
 }
@@ -197,10 +224,9 @@ __device__ inline void gemm_tile(TileSmem<TM, TN>& sm, const double* __restrict_
   constexpr int FA = TM * TK / kBlock;  // A elements per thread per slab
   constexpr int FB = TN * TK / kBlock;
   constexpr int BM = TM / 32, BN = TN / 32;  // 16x16 blocks per wavefront
-  // slabs in flight: the merges' products are short (K is the kept size of a
-  // half), so the 64-tile form loads up to four slabs before the first is
-  // used and pays the memory latency once for K <= 64
-  constexpr int P = TM <= 64 ? 4 : 1;
+  // slabs of registers in flight: one ahead of the slab being multiplied
+  // (deeper prefetch measured slower here: the registers cost occupancy)
+  constexpr int P = 1;
   const int t = threadIdx.x, wv = t >> 6, l = t & 63;
   const int wm = wv & 1, wn = wv >> 1;
   const int li = l & 15, lk = l >> 4;
@@ -610,6 +636,139 @@ __global__ __launch_bounds__(256) void k_final_vt(const int64_t* __restrict__ pn
   }
 }
 
+
+// ---- single problem: 4 KB chunks, XCD-aligned
+// Per output index tv (descending values): the source column of the tv-th
+// largest value with its row supports in U and in V; sigma written here.
+__global__ __launch_bounds__(256) void k_final_meta(int64_t n, Work w, double* sigma) {
+  const int64_t tv = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (tv >= n) return;
+  const int64_t src = n - 1 - tv;
+  const int pc = w.col[src];
+  w.fin[tv] = make_int4(pc, w.ulo[pc], w.uhi[pc], 0);
+  w.fin[n + tv] = make_int4(pc, w.vlo[pc], w.vhi[pc], 0);
+  sigma[tv] = w.sig[src];
+}
+
+// Chunks of kFinalChunk doubles (4 KB) of the column-major output are written
+// by one 16-byte store per thread.  Workgroups are dealt to the 8 XCDs in turn
+// (XCD = workgroup index mod 8), and workgroup b writes chunks congruent to b
+// mod 8 only, so each XCD streams a fixed eighth of the output's 4 KB pages;
+// measured on this part, that is the pattern that reaches the fill rate, where
+// longer per-workgroup runs fall 10-15% short.
+constexpr int kFinalR = 4;  // chunks per workgroup
+
+__device__ inline int64_t div_n(int64_t e, int64_t n, double inv_n) {
+  int64_t q = (int64_t)((double)e * inv_n);
+  if (q * n > e) --q;
+  else if ((q + 1) * n <= e) ++q;
+  return q;
+}
+
+// U: chunks c0 + 8q, c0 = (b / 8) 8 kFinalR + b mod 8
+__global__ __launch_bounds__(256) void k_final_u_chunks(int64_t n, Work w, double* U) {
+  const int64_t total = n * n;
+  const double inv_n = 1.0 / (double)n;
+  const int64_t c0 = (int64_t)(blockIdx.x >> 3) * (8 * kFinalR) + (blockIdx.x & 7);
+  const double* Uw = w.Uw;
+  int64_t e[kFinalR], row[kFinalR];
+  int4 mt[kFinalR];
+#pragma unroll
+  for (int q = 0; q < kFinalR; ++q) {
+    e[q] = (c0 + 8 * q) * kFinalChunk + 2 * threadIdx.x;
+    mt[q] = make_int4(0, 0, 0, 0);
+    row[q] = 0;
+    if (e[q] < total) {
+      const int64_t col = div_n(e[q], n, inv_n);
+      row[q] = e[q] - col * n;
+      mt[q] = w.fin[col];
+    }
+  }
+  double2 v[kFinalR];
+#pragma unroll
+  for (int q = 0; q < kFinalR; ++q) {
+    const int64_t r = row[q];
+    const int lo = mt[q].y, hi = mt[q].z;
+    v[q] = make_double2(0.0, 0.0);
+    if (e[q] < total && r + 1 >= lo && r < hi) {
+      const double* in = Uw + (int64_t)mt[q].x * n;
+      if (r >= lo && r + 1 < hi) {
+        v[q] = *reinterpret_cast<const double2*>(in + r);
+      } else {
+        v[q].x = (r >= lo && r < hi) ? in[r] : 0.0;
+        v[q].y = (r + 1 >= lo && r + 1 < hi) ? in[r + 1] : 0.0;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kFinalR; ++q)
+    if (e[q] < total) *reinterpret_cast<double2*>(U + e[q]) = v[q];
+}
+
+// V^T (n a multiple of 8 chunks): element e = tv + j n holds V[j, column(tv)]
+// inside that column's support.  A workgroup owns 512 vectors tv (two per
+// thread, their (column, lo, hi) loaded once) and walks groups of kVtJ
+// consecutive output columns j with a stride of gridDim.x / (n/512) groups;
+// every chunk it writes has its residue mod 8.  The reads of group k+1 are
+// issued before the stores of group k, so a store does not wait on memory:
+// each thread always issues the same loads -- from its source column where
+// the support reaches the group, else from a fixed address -- and masks the
+// values afterwards, which keeps the outstanding-load count uniform.
+constexpr int kVtJ = 8;
+constexpr int kVtAhead = 2;  // groups of reads in flight ahead of the stores
+
+__global__ __launch_bounds__(256) void k_final_vt_chunks(int64_t n, Work w, double* VT) {
+  const double* Vw = w.Vw;
+  const int4* fv = w.fin + n;
+  const int64_t cpc = n / kFinalChunk;  // chunks per output column
+  const int64_t b = blockIdx.x;
+  const int64_t ch = b % cpc, gstride = gridDim.x / cpc, ngroups = n / kVtJ;
+  const int64_t tv = ch * kFinalChunk + 2 * threadIdx.x;
+  const int4 m0 = fv[tv], m1 = fv[tv + 1];
+  // raw loads only; the masking happens at the store, one group later
+  auto fetch = [&](int64_t g, double2 (&v)[2][kVtJ / 2]) {
+    const int64_t j0 = g * kVtJ;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int4 mt = s ? m1 : m0;
+      const bool need = mt.y < j0 + kVtJ && mt.z > j0;
+      const double* src = need ? Vw + (int64_t)mt.x * n + j0 : Vw;
+#pragma unroll
+      for (int q = 0; q < kVtJ / 2; ++q) v[s][q] = *reinterpret_cast<const double2*>(src + 2 * q);
+    }
+  };
+  auto put = [&](int64_t g, const double2 (&v)[2][kVtJ / 2]) {
+    const int64_t j0 = g * kVtJ;
+    double* out = VT + tv + j0 * n;
+#pragma unroll
+    for (int q = 0; q < kVtJ; ++q) {
+      const int64_t j = j0 + q;
+      const double a = (j >= m0.y && j < m0.z) ? ((q & 1) ? v[0][q / 2].y : v[0][q / 2].x) : 0.0;
+      const double c = (j >= m1.y && j < m1.z) ? ((q & 1) ? v[1][q / 2].y : v[1][q / 2].x) : 0.0;
+      *reinterpret_cast<double2*>(out + q * n) = make_double2(a, c);
+    }
+  };
+  // a ring of kVtAhead + 1 buffers: the reads of group k + kVtAhead are
+  // issued before the stores of group k (the fetches past the last group
+  // read a valid group again, unused, so that every step issues the same
+  // loads)
+  double2 buf[kVtAhead + 1][2][kVtJ / 2];
+  const int64_t g0 = b / cpc;
+  if (g0 >= ngroups) return;
+  auto clampg = [&](int64_t g) { return g < ngroups ? g : ngroups - 1; };
+#pragma unroll
+  for (int a = 0; a < kVtAhead; ++a) fetch(clampg(g0 + a * gstride), buf[a]);
+  for (int64_t g = g0;; g += (kVtAhead + 1) * gstride) {
+#pragma unroll
+    for (int r = 0; r <= kVtAhead; ++r) {
+      const int64_t gr = g + r * gstride;
+      fetch(clampg(gr + kVtAhead * gstride), buf[(r + kVtAhead) % (kVtAhead + 1)]);
+      put(gr, buf[r]);
+      if (gr + gstride >= ngroups) return;
+    }
+  }
+}
+
 }  // namespace
 
 void launch_rotate(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {
@@ -620,7 +779,7 @@ void launch_rotate(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, 
 
 void launch_gather(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {
   if (nnodes <= 0) return;
-  const int gy = grid_y(nnodes, max_m, 4096);
+  const int gy = grid_y(nnodes, (int)std::min<int64_t>(65535, ((int64_t)max_m * (max_m + 1) + kGatherSlab - 1) / kGatherSlab), 8192);
   hipLaunchKernelGGL(k_gather, dim3(nnodes, gy), dim3(kBlock), 0, st, nodes, w);
 }
 
@@ -676,6 +835,19 @@ void launch_final(const int64_t* prob_n, const int64_t* prob_vec, const int64_t*
                      uitem_off, uprob, w, sigma, U);
   hipLaunchKernelGGL(k_final_vt, dim3((unsigned)total_vitems), dim3(kBlock), 0, st, prob_n, prob_vec, prob_mat,
                      vitem_off, vprob, w, VT);
+}
+
+void launch_final_single(int64_t n, const Work& w, double* sigma, double* U, double* VT, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_final_meta, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, n, w, sigma);
+  const int64_t chunks = (n * n + kFinalChunk - 1) / kFinalChunk;
+  const int64_t groups = (chunks + 8 * kFinalR - 1) / (8 * kFinalR);
+  hipLaunchKernelGGL(k_final_u_chunks, dim3((unsigned)(groups * 8)), dim3(kBlock), 0, st, n, w, U);
+  // a persistent grid: a multiple of the chunks per output column and of 8,
+  // about five workgroups per CU, at most one per group of kVtJ columns
+  const int64_t cpc = n / kFinalChunk;
+  int64_t gv = cpc * std::max<int64_t>(1, std::min<int64_t>(n / kVtJ, (1024 + cpc - 1) / cpc));
+  hipLaunchKernelGGL(k_final_vt_chunks, dim3((unsigned)gv), dim3(kBlock), 0, st, n, w, VT);
 }
 
 }  // namespace bdc

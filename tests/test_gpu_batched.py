@@ -161,3 +161,25 @@ def test_autotune_picks_a_valid_tuning(gpu):
             assert np.max(np.abs(u.T @ u - np.eye(n))) <= 1e-12
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("n", [2048, 4096, 8192])
+def test_single_problem_final_pass_matches_batched(solver, n):
+    """A single problem whose size is a multiple of 4096 writes its outputs in
+    XCD-aligned 4 KB chunks; the same problem inside a batch takes the
+    per-column work items (as a single problem of another size does).  The
+    final pass only moves data, so both must agree bit for bit."""
+    import torch
+    d, e = inputs.uniform(n, 300 + n)
+    s1, u1, v1 = [x.clone() for x in solver.svd(torch.from_numpy(d), torch.from_numpy(e))]
+    sizes = [n, 7]
+    d2 = np.concatenate([d, inputs.uniform(7, 5)[0]])
+    e2 = np.concatenate([e, [0.0], inputs.uniform(7, 5)[1], [0.0]])
+    sig, U, VT = solver.svd_batched(sizes, torch.from_numpy(d2), torch.from_numpy(e2))
+    info, _ = solver.info()
+    assert info == 0
+    res = unpack(sizes, sig.cpu().numpy(), U.cpu().numpy(), VT.cpu().numpy())
+    s, u, v = res[0]
+    assert np.array_equal(s, s1.cpu().numpy())
+    assert np.array_equal(u, u1.cpu().numpy())
+    assert np.array_equal(v, v1.cpu().numpy())
