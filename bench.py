@@ -81,6 +81,16 @@ def kernel_work(kind: str, stats: dict, n2: float, launches: int):
     return "hbm", 0.0, "GB/s", PEAK_HBM
 
 
+# the kernels a timed kind consists of (single-problem solves; the final
+# pass of a size that is not a multiple of 4096 is k_final_u + k_final_vt)
+KIND_KERNELS = {
+    "final": ["k_final_meta", "k_final_u_chunks", "k_final_vt_chunks"],
+    "deflate": ["k_zsort", "k_prep_w", "k_prep"],
+    "secular": ["k_secular"],
+    "update_gemm": ["k_update"],
+}
+
+
 def measured_traffic(workload: str, kind: str):
     """HBM bytes per launch of a kernel kind from the committed counter
     summary (profiles/traffic_<workload>_<kind>.json), or None when there is
@@ -382,6 +392,7 @@ def main():
     roofline = {
         "bound": bound,
         "kernel": dom,
+        "kernels": KIND_KERNELS.get(dom, []) if (dom != "final" or n % 4096 == 0) else ["k_final_u", "k_final_vt"],
         "achieved": achieved / scale,
         "peak": peak / scale,
         "unit": unit,

@@ -50,6 +50,13 @@ def stats(stats_csv, bench_json, out_md, title, command):
         out.append(f"\nbench.py line of the same run: {b['ms_per_step']:.3f} ms per solve; roofline kernel "
                    f"`{rf.get('kernel')}` {rf.get('avg_launch_ms', 0):.4f} ms per launch (HIP events), "
                    f"{rf.get('achieved', 0):.1f} of {rf.get('peak')} {rf.get('unit')}.\n")
+        parts = rf.get("kernels") or []
+        if parts:
+            avg = {k: float(r["AverageNs"]) / 1e3 for k, r in ours}
+            got = [p for p in parts if p in avg]
+            out.append(f"\nThe `{rf.get('kernel')}` launch is the kernels {', '.join('`' + p + '`' for p in got)}: "
+                       f"{' + '.join(f'{avg[p]:.2f}' for p in got)} = {sum(avg[p] for p in got):.2f} us per launch "
+                       f"(averages above).\n")
     open(out_md, "w").write("".join(out))
     print("".join(out))
 
