@@ -211,10 +211,19 @@ __global__ __launch_bounds__(256) void k_order(const NodeDesc* __restrict__ node
 // multiplied.
 constexpr int TK = 16;
 
+// the 64 x 64 output tile is turned around in LDS for the stores (column
+// stride kCt doubles: 16-byte aligned, spreads the writes over the banks)
+constexpr int kCt = 66;
+
 template <int TM, int TN>
 struct TileSmem {
-  double A[TK * TM];
-  double B[TK * TN];
+  union {
+    struct {
+      double A[TK * TM];
+      double B[TK * TN];
+    } ab;
+    double C[TM <= 64 ? TN * kCt : 1];
+  };
 };
 
 template <int TM, int TN, class Store>
@@ -265,12 +274,12 @@ __device__ inline void gemm_tile(TileSmem<TM, TN>& sm, const double* __restrict_
 #pragma unroll
       for (int q = 0; q < FA; ++q) {
         const int e = t + kBlock * q;
-        sm.A[(e / TM) * TM + e % TM] = ra[p][q];
+        sm.ab.A[(e / TM) * TM + e % TM] = ra[p][q];
       }
 #pragma unroll
       for (int q = 0; q < FB; ++q) {
         const int e = t + kBlock * q;
-        sm.B[(e % TK) * TN + e / TK] = rb[p][q];
+        sm.ab.B[(e % TK) * TN + e / TK] = rb[p][q];
       }
       __syncthreads();
       if (sl + P < nslab) load(ra[p], rb[p], (sl + P) * TK);
@@ -278,9 +287,9 @@ __device__ inline void gemm_tile(TileSmem<TM, TN>& sm, const double* __restrict_
       for (int kk = 0; kk < TK; kk += 4) {
         double af[BM], bf[BN];
 #pragma unroll
-        for (int a = 0; a < BM; ++a) af[a] = sm.A[(kk + lk) * TM + wm * (TM / 2) + a * 16 + li];
+        for (int a = 0; a < BM; ++a) af[a] = sm.ab.A[(kk + lk) * TM + wm * (TM / 2) + a * 16 + li];
 #pragma unroll
-        for (int b = 0; b < BN; ++b) bf[b] = sm.B[(kk + lk) * TN + wn * (TN / 2) + b * 16 + li];
+        for (int b = 0; b < BN; ++b) bf[b] = sm.ab.B[(kk + lk) * TN + wn * (TN / 2) + b * 16 + li];
 #pragma unroll
         for (int a = 0; a < BM; ++a)
 #pragma unroll
@@ -291,26 +300,56 @@ __device__ inline void gemm_tile(TileSmem<TM, TN>& sm, const double* __restrict_
   }
   // D[i][j] of a 16x16 block sits in lane j + 16 * (i % 4), register i / 4
   // (checked against a host product)
+  if constexpr (TM <= 64) {
+    // through LDS: each output column's 64 rows leave as one 512-byte run
+    // (32 lanes x 16 bytes), two columns per store instruction
+    __syncthreads();
 #pragma unroll
-  for (int a = 0; a < BM; ++a)
+    for (int a = 0; a < BM; ++a)
 #pragma unroll
-    for (int b = 0; b < BN; ++b)
+      for (int b = 0; b < BN; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = tm0 + wm * (TM / 2) + a * 16 + lk + 4 * r;
-        const int colc = tn0 + wn * (TN / 2) + b * 16 + li;
-        if (row < M && colc < N) store(row, colc, acc[a][b][r]);
+        for (int r = 0; r < 4; ++r)
+          sm.C[(wn * (TN / 2) + b * 16 + li) * kCt + wm * (TM / 2) + a * 16 + lk + 4 * r] = acc[a][b][r];
+    __syncthreads();
+    const int half = l >> 5, rr = 2 * (l & 31);
+    const int grow = tm0 + rr;
+#pragma unroll
+    for (int q = 0; q < TN / 8; ++q) {
+      const int c = wv * (TN / 4) + 2 * q + half;
+      const int colc = tn0 + c;
+      if (colc >= N) continue;
+      double* dst = store.col(colc);
+      const double2 v = *reinterpret_cast<const double2*>(&sm.C[c * kCt + rr]);
+      if (grow + 1 < M) {
+        dst[grow] = v.x;
+        dst[grow + 1] = v.y;
+      } else if (grow < M) {
+        dst[grow] = v.x;
       }
+    }
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int a = 0; a < BM; ++a)
+#pragma unroll
+      for (int b = 0; b < BN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = tm0 + wm * (TM / 2) + a * 16 + lk + 4 * r;
+          const int colc = tn0 + wn * (TN / 2) + b * 16 + li;
+          if (row < M && colc < N) *(store.col(colc) + row) = acc[a][b][r];
+        }
+  }
 }
 
+// destination of output column c (row 0): the kept value's physical column
 struct NodeStore {
   double* C;
   const int* scol;
   int64_t ld;
   int rowbase;
-  __device__ void operator()(int row, int c, double v) const {
-    C[(rowbase + row) + (int64_t)scol[c] * ld] = v;
-  }
+  __device__ double* col(int c) const { return C + rowbase + (int64_t)scol[c] * ld; }
 };
 
 // Nodes whose kept size N is at most w.small_n use 64 x 64 tiles, larger ones
@@ -451,7 +490,7 @@ __global__ __launch_bounds__(256) void k_update_flat(const NodeDesc* __restrict_
 struct PlainStore {
   double* C;
   int64_t ldc;
-  __device__ void operator()(int row, int c, double v) const { C[row + (int64_t)c * ldc] = v; }
+  __device__ double* col(int c) const { return C + (int64_t)c * ldc; }
 };
 
 template <int TM, int TN>
@@ -706,66 +745,89 @@ __global__ __launch_bounds__(256) void k_final_u_chunks(int64_t n, Work w, doubl
 }
 
 // V^T (n a multiple of 8 chunks): element e = tv + j n holds V[j, column(tv)]
-// inside that column's support.  A workgroup owns 512 vectors tv (two per
-// thread, their (column, lo, hi) loaded once) and walks groups of kVtJ
-// consecutive output columns j with a stride of gridDim.x / (n/512) groups;
-// every chunk it writes has its residue mod 8.  The reads of group k+1 are
-// issued before the stores of group k, so a store does not wait on memory:
-// each thread always issues the same loads -- from its source column where
-// the support reaches the group, else from a fixed address -- and masks the
-// values afterwards, which keeps the outstanding-load count uniform.
+// inside that column's support.  A workgroup owns 512 vectors tv and a
+// contiguous range of groups of kVtJ = 8 output columns j (chunks n/512
+// apart, all of the workgroup's residue mod 8).  Each wavefront covers 128
+// vectors: for the reads, four lanes take one vector's 64-byte run
+// V[j0 .. j0+7, column] (16 vectors per load instruction, so an instruction
+// touches at most 16 cache lines), and the runs are turned around through
+// LDS ([j][vector], 8 KB per wavefront) so that lane L stores vectors 2L and
+// 2L+1 of each output column -- one 16-byte store per chunk.  The reads of
+// the next group are issued before the current group's LDS round trip and
+// stores; every lane always issues the same loads (from a fixed address
+// where its vector's support misses the group) and the values are masked by
+// the support at the store.
 constexpr int kVtJ = 8;
-constexpr int kVtAhead = 2;  // groups of reads in flight ahead of the stores
 
 __global__ __launch_bounds__(256) void k_final_vt_chunks(int64_t n, Work w, double* VT) {
+  __shared__ double tr[4][kVtJ][128];
   const double* Vw = w.Vw;
   const int4* fv = w.fin + n;
   const int64_t cpc = n / kFinalChunk;  // chunks per output column
   const int64_t b = blockIdx.x;
-  const int64_t ch = b % cpc, gstride = gridDim.x / cpc, ngroups = n / kVtJ;
-  const int64_t tv = ch * kFinalChunk + 2 * threadIdx.x;
-  const int4 m0 = fv[tv], m1 = fv[tv + 1];
-  // raw loads only; the masking happens at the store, one group later
-  auto fetch = [&](int64_t g, double2 (&v)[2][kVtJ / 2]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t ch = b % cpc, nblk = gridDim.x / cpc, ngroups = n / kVtJ;
+  const int64_t gpb = (ngroups + nblk - 1) / nblk;
+  const int64_t g0 = (b / cpc) * gpb, gend = min(ngroups, g0 + gpb);
+  if (g0 >= gend) return;
+  const int64_t tvw = ch * kFinalChunk + wv * 128;  // the wavefront's first vector
+  // the vectors this lane stores: 2 lane, 2 lane + 1
+  const int4 s0 = fv[tvw + 2 * lane], s1 = fv[tvw + 2 * lane + 1];
+  // the vectors this lane reads: 16 i + lane / 4, i < 8; run part lane % 4
+  const int part = lane & 3;
+  int pcl[8], lol[8], hil[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int4 mt = fv[tvw + 16 * i + (lane >> 2)];
+    pcl[i] = mt.x;
+    lol[i] = mt.y;
+    hil[i] = mt.z;
+  }
+  auto fetch = [&](int64_t g, double2 (&v)[8]) {
     const int64_t j0 = g * kVtJ;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int4 mt = s ? m1 : m0;
-      const bool need = mt.y < j0 + kVtJ && mt.z > j0;
-      const double* src = need ? Vw + (int64_t)mt.x * n + j0 : Vw;
-#pragma unroll
-      for (int q = 0; q < kVtJ / 2; ++q) v[s][q] = *reinterpret_cast<const double2*>(src + 2 * q);
+    for (int i = 0; i < 8; ++i) {
+      const bool need = lol[i] < j0 + kVtJ && hil[i] > j0;
+      const double* src = need ? Vw + (int64_t)pcl[i] * n + j0 + 2 * part : Vw;
+      v[i] = *reinterpret_cast<const double2*>(src);
     }
   };
-  auto put = [&](int64_t g, const double2 (&v)[2][kVtJ / 2]) {
+  double (*T)[128] = tr[wv];
+  auto put = [&](int64_t g, const double2 (&v)[8]) {
     const int64_t j0 = g * kVtJ;
-    double* out = VT + tv + j0 * n;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int t = 16 * i + (lane >> 2);
+      T[2 * part][t] = v[i].x;
+      T[2 * part + 1][t] = v[i].y;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double* out = VT + tvw + 2 * lane + j0 * n;
 #pragma unroll
     for (int q = 0; q < kVtJ; ++q) {
       const int64_t j = j0 + q;
-      const double a = (j >= m0.y && j < m0.z) ? ((q & 1) ? v[0][q / 2].y : v[0][q / 2].x) : 0.0;
-      const double c = (j >= m1.y && j < m1.z) ? ((q & 1) ? v[1][q / 2].y : v[1][q / 2].x) : 0.0;
+      const double2 x = *reinterpret_cast<const double2*>(&T[q][2 * lane]);
+      const double a = (j >= s0.y && j < s0.z) ? x.x : 0.0;
+      const double c = (j >= s1.y && j < s1.z) ? x.y : 0.0;
       *reinterpret_cast<double2*>(out + q * n) = make_double2(a, c);
     }
   };
-  // a ring of kVtAhead + 1 buffers: the reads of group k + kVtAhead are
-  // issued before the stores of group k (the fetches past the last group
-  // read a valid group again, unused, so that every step issues the same
-  // loads)
-  double2 buf[kVtAhead + 1][2][kVtJ / 2];
-  const int64_t g0 = b / cpc;
-  if (g0 >= ngroups) return;
-  auto clampg = [&](int64_t g) { return g < ngroups ? g : ngroups - 1; };
-#pragma unroll
-  for (int a = 0; a < kVtAhead; ++a) fetch(clampg(g0 + a * gstride), buf[a]);
-  for (int64_t g = g0;; g += (kVtAhead + 1) * gstride) {
-#pragma unroll
-    for (int r = 0; r <= kVtAhead; ++r) {
-      const int64_t gr = g + r * gstride;
-      fetch(clampg(gr + kVtAhead * gstride), buf[(r + kVtAhead) % (kVtAhead + 1)]);
-      put(gr, buf[r]);
-      if (gr + gstride >= ngroups) return;
-    }
+  // one group of reads in flight ahead of the stores (the fetch after the
+  // last group reads a valid group again, unused)
+  double2 A[8], B[8];
+  fetch(g0, A);
+  for (int64_t g = g0;; g += 2) {
+    fetch(g + 1 < gend ? g + 1 : gend - 1, B);
+    put(g, A);
+    if (g + 1 >= gend) return;
+    fetch(g + 2 < gend ? g + 2 : gend - 1, A);
+    put(g + 1, B);
+    if (g + 2 >= gend) return;
   }
 }
 
@@ -843,10 +905,11 @@ void launch_final_single(int64_t n, const Work& w, double* sigma, double* U, dou
   const int64_t chunks = (n * n + kFinalChunk - 1) / kFinalChunk;
   const int64_t groups = (chunks + 8 * kFinalR - 1) / (8 * kFinalR);
   hipLaunchKernelGGL(k_final_u_chunks, dim3((unsigned)(groups * 8)), dim3(kBlock), 0, st, n, w, U);
-  // a persistent grid: a multiple of the chunks per output column and of 8,
-  // about five workgroups per CU, at most one per group of kVtJ columns
+  // a persistent grid: a multiple of the chunks per output column (and so of
+  // 8), three workgroups per CU (the registers allow three), at most one per
+  // group of kVtJ columns
   const int64_t cpc = n / kFinalChunk;
-  int64_t gv = cpc * std::max<int64_t>(1, std::min<int64_t>(n / kVtJ, (1024 + cpc - 1) / cpc));
+  int64_t gv = cpc * std::max<int64_t>(1, std::min<int64_t>(n / kVtJ, (768 + cpc - 1) / cpc));
   hipLaunchKernelGGL(k_final_vt_chunks, dim3((unsigned)gv), dim3(kBlock), 0, st, n, w, VT);
 }
 
