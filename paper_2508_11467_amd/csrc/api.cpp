@@ -254,7 +254,7 @@ int ensure_workspace(bdc_handle_t h, int64_t tn, int64_t tn2, int nnodes) {
   size_t bytes = 4 * align_up(N2 * 8) + 8 * align_up(N1 * 8) + align_up(2 * N1 * 8) +
                  19 * align_up(N1 * 4) + 2 * align_up(2 * N1 * 4) + align_up(N1 * 4) +
                  2 * align_up((nd_ + 1) * 4) + align_up(nd_ * sizeof(NodeState)) + align_up(sizeof(Ctl)) +
-                 align_up(2 * N1 * sizeof(int4));
+                 align_up(2 * N1 * sizeof(int4)) + align_up(N1 * 8) + align_up(nd_ * sizeof(SecCount));
   if (h->opt.workspace_cap_bytes && bytes > h->opt.workspace_cap_bytes) return BDC_ERR_NOMEM;
   if (h->arena) {
     if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
@@ -317,6 +317,8 @@ int ensure_workspace(bdc_handle_t h, int64_t tn, int64_t tn2, int nnodes) {
   w.st = (NodeState*)take(nd_ * sizeof(NodeState));
   w.ctl = (Ctl*)take(sizeof(Ctl));
   w.fin = (int4*)take(2 * N1 * sizeof(int4));
+  w.leaf_fl = (unsigned long long*)take(N1 * 8);
+  w.sec = (SecCount*)take(nd_ * sizeof(SecCount));
   h->cap_n = tn;
   h->cap_n2 = tn2;
   h->cap_nodes = nnodes;
@@ -417,7 +419,7 @@ int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, do
   w.sec_small_n = h->tune.sec_small_n;
   {
     Timer t(h, st, kReset);
-    launch_reset(w.ctl, w.st, p.nnodes, st);
+    launch_reset(w.ctl, w.st, w.sec, p.nnodes, st);
   }
   if (learned) {
     Timer t(h, st, kStart);
@@ -476,7 +478,7 @@ int solve(bdc_handle_t h, int64_t batch, const int64_t* sizes, const double* d, 
   if (h->plan.total_n == 0) {
     h->last_stream = st;
     h->have_call = true;
-    launch_reset(h->w.ctl, h->w.st, 0, st);
+    launch_reset(h->w.ctl, h->w.st, h->w.sec, 0, st);
     return hipGetLastError() == hipSuccess ? BDC_OK : BDC_ERR_HIP;
   }
   if (h->opt.timing || !h->opt.use_graph || h->harvest) return run_plan(h, d, e, sigma, U, VT, st);
@@ -625,16 +627,27 @@ int bdc_get_info(bdc_handle_t h, int64_t* info, bdc_stats_t* stats) {
   if (hipStreamSynchronize(h->last_stream) != hipSuccess) return BDC_ERR_HIP;
   Ctl ctl;
   if (hipMemcpy(&ctl, h->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) return BDC_ERR_HIP;
-  if (info) *info = ctl.nonfinite ? (int64_t)BDC_ERR_NONFINITE : (int64_t)ctl.leaf_capped + ctl.secular_capped;
+  std::vector<NodeState> sts;
+  int64_t sec_capped = 0;
+  unsigned long long sec_evals = 0, sec_terms = 0;
+  if (h->plan_valid && h->plan.nnodes > 0) {
+    sts.resize(h->plan.nnodes);
+    std::vector<SecCount> sc(h->plan.nnodes);
+    if (hipMemcpy(sts.data(), h->w.st, sizeof(NodeState) * h->plan.nnodes, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(sc.data(), h->w.sec, sizeof(SecCount) * h->plan.nnodes, hipMemcpyDeviceToHost) != hipSuccess)
+      return BDC_ERR_HIP;
+    for (const SecCount& c : sc) {
+      sec_capped += (int64_t)c.capped;
+      sec_evals += c.evals;
+      sec_terms += c.terms;
+    }
+  }
+  if (info) *info = ctl.nonfinite ? (int64_t)BDC_ERR_NONFINITE : (int64_t)ctl.leaf_capped + sec_capped;
   if (stats && h->plan_valid) {
     const Plan& p = h->plan;
-    std::vector<NodeState> sts(p.nnodes);
-    if (p.nnodes > 0 &&
-        hipMemcpy(sts.data(), h->w.st, sizeof(NodeState) * p.nnodes, hipMemcpyDeviceToHost) != hipSuccess)
-      return BDC_ERR_HIP;
     stats->merges = p.nnodes;
     stats->levels = (int64_t)p.levels.size();
-    stats->secular_evals = (int64_t)ctl.secular_evals;
+    stats->secular_evals = (int64_t)sec_evals;
     double fl = 0.0;
     for (int i = 0; i < p.nnodes; ++i) {
       const NodeState& s = sts[i];
@@ -650,8 +663,17 @@ int bdc_get_info(bdc_handle_t h, int64_t* info, bdc_stats_t* stats) {
     }
     stats->update_flops = fl;
     if (p.root_id0 >= 0) stats->root_N = sts[p.root_id0].N;
-    stats->secular_terms = (int64_t)ctl.secular_terms;
-    stats->leaf_flops = (double)ctl.leaf_rot_flops;
+    stats->secular_terms = (int64_t)sec_terms;
+    {
+      std::vector<unsigned long long> lf(std::max(p.nleaves, 1));
+      if (p.nleaves > 0 &&
+          hipMemcpy(lf.data(), h->w.leaf_fl, sizeof(unsigned long long) * p.nleaves, hipMemcpyDeviceToHost) !=
+              hipSuccess)
+        return BDC_ERR_HIP;
+      double lfl = 0.0;
+      for (int i = 0; i < p.nleaves; ++i) lfl += (double)lf[i];
+      stats->leaf_flops = lfl;
+    }
     double gb = 0.0;
     for (int i = 0; i < p.nnodes; ++i) {
       const NodeDesc& nd = p.host_nodes[i];

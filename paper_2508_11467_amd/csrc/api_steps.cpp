@@ -79,6 +79,8 @@ Work make_work(Tmp& t, int64_t n) {
   w.rot_col = t.alloc<int32_t>(2 * N1);
   w.st = t.alloc<NodeState>(1);
   w.ctl = t.alloc<Ctl>(1);
+  w.leaf_fl = t.alloc<unsigned long long>(1);
+  w.sec = t.alloc<SecCount>(1);
   w.oz.min_n = INT32_MAX;
   w.small_n = 96;
   w.sec_small_n = 0;
@@ -131,7 +133,7 @@ int bdc_step_leaf(bdc_handle_t h, int m, int s, const double* d, const double* e
   w.max_leaf_sweeps = mls;
   LeafDesc L{0, 0, ld, 0, m, s};
   if (hipMemcpy(ld_dev, &L, sizeof(L), hipMemcpyHostToDevice) != hipSuccess) return BDC_ERR_HIP;
-  launch_reset(w.ctl, w.st, 1, st);
+  launch_reset(w.ctl, w.st, w.sec, 1, st);
   launch_leaf(ld_dev, 1, w, st);
   if (hipMemcpy2DAsync(W, sizeof(double) * m, w.Uw, sizeof(double) * ld, sizeof(double) * m, m,
                        hipMemcpyDeviceToDevice, st) != hipSuccess)
@@ -197,7 +199,7 @@ int bdc_step_deflate(bdc_handle_t h, int m, int s, const double* sig, const doub
       hipMemcpy(ee, eh.data(), sizeof(double) * ld, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(nd_dev, &nd, sizeof(nd), hipMemcpyHostToDevice) != hipSuccess)
     return BDC_ERR_HIP;
-  launch_reset(w.ctl, w.st, 1, st);
+  launch_reset(w.ctl, w.st, w.sec, 1, st);
   launch_prep(nd_dev, 1, m, w, st);
   int rc = finish(st);
   if (rc != BDC_OK) return rc;
@@ -257,7 +259,7 @@ int bdc_step_secular_start(bdc_handle_t h, int N, const double* d, const double*
       hipMemcpy(w.st, &ns, sizeof(ns), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(nd_dev, &nd, sizeof(nd), hipMemcpyHostToDevice) != hipSuccess)
     return BDC_ERR_HIP;
-  launch_reset(w.ctl, w.st, 1, st);
+  launch_reset(w.ctl, w.st, w.sec, 1, st);
   launch_secular(nd_dev, 1, N, w, st);
   return finish(st);
 }

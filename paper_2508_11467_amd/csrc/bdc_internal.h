@@ -69,15 +69,18 @@ struct NodeState {
   unsigned long long zmax_bits;  // max(d, |z|) of the merge, as bits (atomic max)
 };
 
-// Per-call device counters.
+// Secular statistics of one merge (atomics on the node's own counters, so the
+// many merges of a level do not contend for one address).
+struct SecCount {
+  unsigned long long evals, terms;
+  unsigned long long capped;
+};
+
+// Per-call device counters (rare events only; the statistics are per node
+// and per leaf).
 struct Ctl {
   int32_t nonfinite;
   int32_t leaf_capped;
-  int32_t secular_capped;
-  int32_t pad;
-  unsigned long long secular_evals;
-  unsigned long long secular_terms;
-  unsigned long long leaf_rot_flops;
 };
 
 // Split-precision update products: bfloat16 slice planes per side (0 U,
@@ -138,6 +141,8 @@ struct Work {
   int32_t* rot_col;  //   physical columns (2 per rotation)
   double* rot_cs;    //   (c, s)
   float* xs;         // caller-given start of each root in its interval, or nullptr
+  unsigned long long* leaf_fl;  // per leaf: rotation flops (a plain store each, summed on the host)
+  SecCount* sec;     // per node: secular statistics
   int4* fin;         // final pass of a single problem: per output index, (column, lo, hi) of U then of V
   const unsigned short* mlp_pk;  // packed network for the in-kernel learned start,
                                  // or nullptr
@@ -171,7 +176,7 @@ struct Tuning {
 };
 
 // ---- launchers (defined next to their kernels) ----
-void launch_reset(Ctl* ctl, NodeState* st, int nnodes, hipStream_t st_);
+void launch_reset(Ctl* ctl, NodeState* st, SecCount* sec, int nnodes, hipStream_t st_);
 void launch_leaf(const LeafDesc* leaves, int nleaves, const Work& w, hipStream_t st);
 void launch_prep(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
 void launch_rotate(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);

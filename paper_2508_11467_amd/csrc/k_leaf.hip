@@ -289,29 +289,29 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafDesc* __restrict__ leaves
     w.vhi[pv + r0 + m] = r0 + ms;
   }
   // 6 flops per row per rotation
-  if (lane == 0) atomicAdd(&w.ctl->leaf_rot_flops, 6ull * (nrot_w * (unsigned long long)m + nrot_q * (unsigned long long)ms));
+  if (lane == 0) w.leaf_fl[blockIdx.x] = 6ull * (nrot_w * (unsigned long long)m + nrot_q * (unsigned long long)ms);
 }
 
-__global__ __launch_bounds__(256) void k_reset(Ctl* ctl, NodeState* st, int nnodes) {
+__global__ __launch_bounds__(256) void k_reset(Ctl* ctl, NodeState* st, SecCount* sec, int nnodes) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->nonfinite = 0;
     ctl->leaf_capped = 0;
-    ctl->secular_capped = 0;
-    ctl->pad = 0;
-    ctl->secular_evals = 0ull;
-    ctl->secular_terms = 0ull;
-    ctl->leaf_rot_flops = 0ull;
   }
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < nnodes; i += gridDim.x * 256) st[i].zmax_bits = 0ull;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < nnodes; i += gridDim.x * 256) {
+    st[i].zmax_bits = 0ull;
+    sec[i].evals = 0ull;
+    sec[i].terms = 0ull;
+    sec[i].capped = 0ull;
+  }
 }
 
 }  // namespace
 
-void launch_reset(Ctl* ctl, NodeState* nst, int nnodes, hipStream_t st) {
+void launch_reset(Ctl* ctl, NodeState* nst, SecCount* sec, int nnodes, hipStream_t st) {
   int blocks = (nnodes + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 64) blocks = 64;
-  hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, st, ctl, nst, nnodes);
+  hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, st, ctl, nst, sec, nnodes);
 }
 
 void launch_leaf(const LeafDesc* leaves, int nleaves, const Work& w, hipStream_t st) {

@@ -256,17 +256,19 @@ __device__ void learned_proposals(const Work& w, MlpShared& m, const double* __r
   forward_fast(m.W, m.A, xs);
 }
 
-// Evaluation counters of a wavefront's roots.
-__device__ inline void count_roots(const Work& w, int N, int iters, int capped) {
+// Evaluation counters of a wavefront's roots, added to its node's own
+// counters (one address per node: a level's many merges do not serialise on
+// a single atomic, which measured tens of microseconds per level).
+__device__ inline void count_roots(const Work& w, int node, int N, int iters, int capped) {
   int it_sum = iters, cap_sum = capped;
   for (int off = 32; off > 0; off >>= 1) {
     it_sum += __shfl_xor(it_sum, off, 64);
     cap_sum += __shfl_xor(cap_sum, off, 64);
   }
-  if ((threadIdx.x & 63) == 0) {
-    atomicAdd(&w.ctl->secular_evals, (unsigned long long)it_sum);
-    atomicAdd(&w.ctl->secular_terms, (unsigned long long)it_sum * (unsigned long long)N);
-    if (cap_sum) atomicAdd(&w.ctl->secular_capped, cap_sum);
+  if ((threadIdx.x & 63) == 0 && it_sum) {
+    atomicAdd(&w.sec[node].evals, (unsigned long long)it_sum);
+    atomicAdd(&w.sec[node].terms, (unsigned long long)it_sum * (unsigned long long)N);
+    if (cap_sum) atomicAdd(&w.sec[node].capped, (unsigned long long)cap_sum);
   }
 }
 
@@ -414,7 +416,7 @@ __device__ void secular_wide(const NodeDesc& nd, int N, const Work& w, WideLds<k
         w.tau[vo + i] = R.tau;
         w.iters[vo + i] = R.iters;
       }
-      count_roots(w, N, R.iters, R.capped);
+      count_roots(w, nd.id, N, R.iters, R.capped);
     }
     __syncthreads();
   }
@@ -522,7 +524,7 @@ __device__ void secular_lanes(const NodeDesc& nd, int N, const Work& w, LanesLds
     w.tau[vo + i] = R.tau;
     w.iters[vo + i] = R.iters;
   }
-  count_roots(w, N, writer ? R.iters : 0, writer ? R.capped : 0);
+  count_roots(w, nd.id, N, writer ? R.iters : 0, writer ? R.capped : 0);
 }
 
 // One launch per level: a node with at most sec_small_n (<= kLanesMaxN) kept
