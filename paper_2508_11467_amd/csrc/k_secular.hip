@@ -20,9 +20,9 @@
 //              per pole, each lane a strided partial product of the ratios,
 //              then a cross-lane product reduction (the paper's block-i /
 //              thread-j product with shuffles).
-//   k_vectors  singular vectors of M~ (eq. M-svd-vec), one workgroup per root
+//   k_vectors  singular vectors of M~ (eq. M-svd-vec), one wavefront per root
 //              column, written in the row order of the vector update and
-//              normalised in place.
+//              normalised.
 #include <type_traits>
 
 #include "bdc_internal.h"
@@ -571,8 +571,11 @@ __global__ __launch_bounds__(256) void k_lowner(const NodeDesc* __restrict__ nod
   }
 }
 
+// One wavefront per root column, four per workgroup: lane l takes rows
+// g = l, l + 64, ...; the first 256 rows stay in registers between the sums
+// of squares (wavefront reductions, no barrier) and the scaled stores,
+// longer columns are written once and rescaled in place.
 __global__ __launch_bounds__(256) void k_vectors(const NodeDesc* __restrict__ nodes, Work w) {
-  __shared__ double sh[8];
   const NodeDesc nd = nodes[blockIdx.x];
   const int N = w.st[nd.id].N;
   const int64_t vo = nd.vec_off + nd.r0;
@@ -580,38 +583,57 @@ __global__ __launch_bounds__(256) void k_vectors(const NodeDesc* __restrict__ no
   const double* __restrict__ d = w.sd + vo;
   const double* __restrict__ zt = w.zt + vo;
   const int* __restrict__ gsurv = w.gsurv + vo;
-  const int t = threadIdx.x;
-  for (int i = blockIdx.y; i < N; i += gridDim.y) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = blockIdx.y * 4 + wv; i < N; i += gridDim.y * 4) {
     double* ucol = w.UM + nd.mat_off + nd.r0 + (int64_t)(nd.r0 + i) * ld;
     double* vcol = w.VM + nd.mat_off + nd.r0 + (int64_t)(nd.r0 + i) * ld;
     if (N == 1) {
       // M~ = [zt_1], omega = |zt_1|: u = [-1], v = zt/(0 - omega^2) normalised = [-1]
-      if (t == 0) {
+      if (lane == 0) {
         ucol[0] = -1.0;
         vcol[0] = -1.0;
       }
       continue;
     }
     const double ov = d[w.o[vo + i]], ti = w.tau[vo + i];
-    double su = 0.0, sv = 0.0;
-    for (int g = t; g < N; g += kBlock) {
+    auto entry = [&](int g, double& v, double& u) {
       const int j = gsurv[g];
       const double dj = d[j];
       const double del = ((dj - ov) - ti) * ((dj + ov) + ti);  // d_j^2 - w_i^2
-      const double v = zt[j] / del;
-      const double u = (j == 0) ? -1.0 : dj * v;
+      v = zt[j] / del;
+      u = (j == 0) ? -1.0 : dj * v;
+    };
+    double su = 0.0, sv = 0.0;
+    double vr[4], ur[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int g = lane + 64 * q;
+      vr[q] = ur[q] = 0.0;
+      if (g < N) entry(g, vr[q], ur[q]);
+      sv += vr[q] * vr[q];
+      su += ur[q] * ur[q];
+    }
+    for (int g = lane + 256; g < N; g += 64) {
+      double v, u;
+      entry(g, v, u);
       vcol[g] = v;
       ucol[g] = u;
       sv += v * v;
       su += u * u;
     }
-    const double nv = sqrt(block_sum(sv, sh));
-    const double nu = sqrt(block_sum(su, sh + 4));
-    for (int g = t; g < N; g += kBlock) {
-      vcol[g] = vcol[g] / nv;
-      ucol[g] = ucol[g] / nu;
+    const double rv = 1.0 / sqrt(wave_sum(sv)), ru = 1.0 / sqrt(wave_sum(su));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int g = lane + 64 * q;
+      if (g < N) {
+        vcol[g] = vr[q] * rv;
+        ucol[g] = ur[q] * ru;
+      }
     }
-    __syncthreads();
+    for (int g = lane + 256; g < N; g += 64) {
+      vcol[g] *= rv;
+      ucol[g] *= ru;
+    }
   }
 }
 
@@ -656,7 +678,7 @@ void launch_lowner(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, 
 
 void launch_vectors(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {
   if (nnodes <= 0) return;
-  const int gy = grid_y(nnodes, max_m, 4096);
+  const int gy = grid_y(nnodes, (max_m + 3) / 4, 4096);
   hipLaunchKernelGGL(k_vectors, dim3(nnodes, gy), dim3(kBlock), 0, st, nodes, w);
 }
 
