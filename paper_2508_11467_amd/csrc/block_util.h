@@ -132,4 +132,17 @@ __device__ inline double block_sum_n(double v, double* sh /* >= BS/64 */) {
   return s;
 }
 
+// Block maximum for BS threads.
+template <int BS>
+__device__ inline double block_max_n(double v, double* sh /* >= BS/64 */) {
+  v = wave_maxd(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = sh[0];
+  for (int q = 1; q < BS / 64; ++q) s = fmax(s, sh[q]);
+  return s;
+}
+
 }  // namespace bdc

@@ -248,6 +248,82 @@ __device__ inline void finish_node(const NodeDesc& nd, const Work& w, const Merg
   }
 }
 
+// z and d of every node column and its place in the sorted order (as
+// k_zsort), done by one workgroup for its own merge of at most 64 * Q * BS/64
+// values: each thread takes Q columns, the children's values are staged in
+// LDS (ssig) for the binary searches, and the loads of the Q columns are
+// issued together (the V entry is fetched beside its support bounds and
+// dropped when the row lies outside them; row < m and column < m keep it
+// inside the node's block).  Returns the largest of d and |z|; the positions
+// are written before the closing barrier.
+template <int BS, int Q>
+__device__ double zsort_node(const NodeDesc& nd, const Work& w, const MergeHead& h, double* ssig, double* shd) {
+  const int m = nd.m, k = nd.k, r0 = nd.r0, m2 = nd.m - nd.k;
+  const int64_t ld = nd.ld, pv = nd.vec_off, vo = nd.vec_off + nd.r0;
+  const double* V = w.Vw + nd.mat_off;
+  const int t = threadIdx.x;
+  if (t == 0 && !(fabs(w.d[pv + r0 + k - 1]) <= DBL_MAX && fabs(w.e[pv + r0 + k - 1]) <= DBL_MAX))
+    atomicOr(&w.ctl->nonfinite, 1);
+  const double* sig = w.sig + vo;
+  int pc[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int c = t + q * BS;
+    double sv = 0.0;
+    pc[q] = r0 + k - 1;
+    if (c < m) {
+      sv = sig[c];
+      if (c != k - 1) pc[q] = w.col[vo + c];
+    }
+    ssig[c] = sv;
+  }
+  double qv[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int c = t + q * BS;
+    const int row = c < k ? r0 + k - 1 : r0 + k;  // boundary row of the child's right basis
+    const int lo = w.vlo[pv + pc[q]], hi = w.vhi[pv + pc[q]];
+    const double v = c < m ? V[row + (int64_t)pc[q] * ld] : 0.0;
+    qv[q] = (row >= lo && row < hi) ? v : 0.0;
+  }
+  __syncthreads();
+  double lmax = 0.0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int c = t + q * BS;
+    if (c >= m) continue;
+    double dv, zv;
+    int pos, sup;
+    if (c < k - 1) {
+      const double sv = ssig[c];
+      dv = sv / h.p;
+      zv = h.a_s * qv[q];
+      pos = 1 + c + count_less(ssig + k, m2, sv);
+      sup = 1;
+    } else if (c == k - 1) {
+      dv = 0.0;
+      zv = h.rr;
+      pos = 0;
+      sup = 0;
+    } else {
+      const double sv = ssig[c];
+      dv = sv / h.p;
+      zv = h.b_s * qv[q];
+      pos = 1 + (c - k) + count_leq(ssig, k - 1, sv);
+      sup = 3;
+    }
+    w.ps_d[vo + pos] = dv;
+    w.ps_z[vo + pos] = zv;
+    w.ps_c[vo + pos] = c;
+    w.ps_col[vo + pos] = pc[q];
+    w.ps_sup[vo + pos] = sup;
+    w.ps_rot[vo + pos] = 0;
+    w.status[vo + pos] = 0;
+    lmax = fmax(lmax, fmax(dv, fabs(zv)));
+  }
+  return block_max_n<BS>(lmax, shd);
+}
+
 // Deflation of one node (one workgroup).  The scan of the paper's rules over
 // positions 2..m is sequential as written, but its decisions are not: after
 // a candidate (a position whose z is not small and whose value is not within
@@ -491,21 +567,30 @@ __device__ inline void wave_exscan(const int (&c)[K], int (&before)[K], int (&to
 // of its step with a candidate, else the last candidate of the earlier steps
 // and wavefronts.  Decisions, lists and rotations are those of k_prep bit for
 // bit.  Needs m <= 64 Q BS/64.
-template <int BS, int Q>
+template <int BS, int Q, bool kFused>
 __global__ __launch_bounds__(BS) void k_prep_w(const NodeDesc* __restrict__ nodes, Work w) {
   constexpr int NW = BS / 64;
+  constexpr int kCap = 64 * Q * NW;  // positions the workgroup covers
   static_assert(Q <= 32, "class bits are kept in 32-bit masks");
   __shared__ double sh_last[NW];
   __shared__ int sh_has[NW];
   __shared__ int shi[6 * NW];
   __shared__ double shd[NW];
+  __shared__ double ssig[kFused ? kCap : 1];
 
   const NodeDesc nd = nodes[blockIdx.x];
   const int m = nd.m, k = nd.k, r0 = nd.r0;
   const int64_t vo = nd.vec_off + nd.r0;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const MergeHead h = merge_head(nd, w);
-  const double zmax = __longlong_as_double((long long)w.st[nd.id].zmax_bits);
+  double zmax;
+  if constexpr (kFused) {
+    // k_zsort's work for a merge this workgroup holds whole: the children's
+    // values staged in LDS for the merge-position searches
+    zmax = zsort_node<BS, Q>(nd, w, h, ssig, shd);
+  } else {
+    zmax = __longlong_as_double((long long)w.st[nd.id].zmax_bits);
+  }
   // tol stands for eps * ||M||: 8 * 2^-52 * max(max d, max |z|)
   const double tol = 8.0 * kEps * zmax;
   const int64_t rb = 2 * vo;
@@ -744,18 +829,21 @@ void launch_prep(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hi
   int gy = (max_m + kBlock - 1) / kBlock;
   const int cap = 4096 / nnodes;
   if (gy > cap) gy = cap > 0 ? cap : 1;
-  hipLaunchKernelGGL(k_zsort, dim3(nnodes, gy), dim3(kBlock), 0, st, nodes, w);
   // one wavefront per node up to 256 values, then 4 and 16 (4 to 16 steps
-  // per lane); beyond 16384 values the segment-per-thread kernel
+  // per lane); beyond 16384 values the segment-per-thread kernel.  Merges of
+  // at most 1024 values: the one workgroup per node does k_zsort's work too.
   const dim3 g(nnodes);
-  if (max_m <= 64) hipLaunchKernelGGL((k_prep_w<64, 1>), g, dim3(64), 0, st, nodes, w);
-  else if (max_m <= 128) hipLaunchKernelGGL((k_prep_w<64, 2>), g, dim3(64), 0, st, nodes, w);
-  else if (max_m <= 256) hipLaunchKernelGGL((k_prep_w<64, 4>), g, dim3(64), 0, st, nodes, w);
-  else if (max_m <= 1024) hipLaunchKernelGGL((k_prep_w<256, 4>), g, dim3(256), 0, st, nodes, w);
-  else if (max_m <= 4096) hipLaunchKernelGGL((k_prep_w<1024, 4>), g, dim3(1024), 0, st, nodes, w);
-  else if (max_m <= 8192) hipLaunchKernelGGL((k_prep_w<1024, 8>), g, dim3(1024), 0, st, nodes, w);
-  else if (max_m <= 16384) hipLaunchKernelGGL((k_prep_w<1024, 16>), g, dim3(1024), 0, st, nodes, w);
-  else hipLaunchKernelGGL(k_prep<1024>, g, dim3(1024), 0, st, nodes, w);
+  if (max_m <= 64) hipLaunchKernelGGL((k_prep_w<64, 1, true>), g, dim3(64), 0, st, nodes, w);
+  else if (max_m <= 128) hipLaunchKernelGGL((k_prep_w<64, 2, true>), g, dim3(64), 0, st, nodes, w);
+  else if (max_m <= 256) hipLaunchKernelGGL((k_prep_w<64, 4, true>), g, dim3(64), 0, st, nodes, w);
+  else if (max_m <= 1024) hipLaunchKernelGGL((k_prep_w<256, 4, true>), g, dim3(256), 0, st, nodes, w);
+  else {
+    hipLaunchKernelGGL(k_zsort, dim3(nnodes, gy), dim3(kBlock), 0, st, nodes, w);
+    if (max_m <= 4096) hipLaunchKernelGGL((k_prep_w<1024, 4, false>), g, dim3(1024), 0, st, nodes, w);
+    else if (max_m <= 8192) hipLaunchKernelGGL((k_prep_w<1024, 8, false>), g, dim3(1024), 0, st, nodes, w);
+    else if (max_m <= 16384) hipLaunchKernelGGL((k_prep_w<1024, 16, false>), g, dim3(1024), 0, st, nodes, w);
+    else hipLaunchKernelGGL(k_prep<1024>, g, dim3(1024), 0, st, nodes, w);
+  }
 }
 
 }  // namespace bdc
