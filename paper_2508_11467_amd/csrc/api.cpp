@@ -170,8 +170,7 @@ int make_plan(bdc_handle_t h, const int64_t* sizes, int64_t batch) {
     vo += n;
     mo += n * n;
     if (n > 0) co += (n + final_u_cols(n) - 1) / final_u_cols(n);  // U work items
-    const int64_t nt = (n + 63) / 64;
-    to += nt * ((nt + kVtTilesPerGroup - 1) / kVtTilesPerGroup);  // V^T work items
+    to += vt_bands(n) * vt_groups(n);  // V^T work items
   }
   p.total_n = vo;
   p.total_n2 = mo;

@@ -26,8 +26,15 @@
 namespace bdc {
 
 constexpr int kMaxLeaf = 32;
-// 64-column tiles of one 64-row band of V^T handled by one final-pass workgroup
+// Batched final pass of V^T: bands of kVtBand output rows (singular
+// vectors) by tiles of kVtTile output columns, kVtTilesPerGroup tiles per
+// work item (one workgroup); work items of a problem of size n
 constexpr int kVtTilesPerGroup = 16;
+constexpr int kVtBand = 256, kVtTile = 16;
+__host__ __device__ inline int64_t vt_bands(int64_t n) { return (n + kVtBand - 1) / kVtBand; }
+__host__ __device__ inline int64_t vt_groups(int64_t n) {
+  return ((n + kVtTile - 1) / kVtTile + kVtTilesPerGroup - 1) / kVtTilesPerGroup;
+}
 // largest secular problem the lanes-per-root kernel takes
 constexpr int kSecLanesMaxN = 256;
 // doubles per 4 KB output chunk of the single-problem final pass
@@ -188,7 +195,7 @@ void launch_order(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, h
 void launch_update(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, const Tuning& tu,
                    hipStream_t st);
 // Final pass: work items of U (groups of final_u_cols columns) and of V^T
-// (64-row bands x kVtTilesPerGroup column tiles), numbered per problem from
+// (bands x groups of column tiles, as above), numbered per problem from
 // uitem_off / vitem_off, with item -> problem tables uprob / vprob.
 void launch_final_single(int64_t n, const Work& w, double* sigma, double* U, double* VT, hipStream_t st);
 void launch_final(const int64_t* prob_n, const int64_t* prob_vec, const int64_t* prob_mat,

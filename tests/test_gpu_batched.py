@@ -183,3 +183,25 @@ def test_single_problem_final_pass_matches_batched(solver, n):
     assert np.array_equal(s, s1.cpu().numpy())
     assert np.array_equal(u, u1.cpu().numpy())
     assert np.array_equal(v, v1.cpu().numpy())
+
+
+def test_batched_outputs_at_8_byte_alignment(solver):
+    """Output buffers that are only 8-byte aligned (a caller's views one
+    double into an allocation) get the same bits as aligned ones; the sizes
+    make 4 KB chunks span several problems and end on odd element counts."""
+    import torch
+    sizes = [3, 1, 0, 7, 40, 2, 129, 1, 5]
+    d, e = inputs.batch_uniform(sizes, 123)
+    dt, et = torch.from_numpy(d).cuda(), torch.from_numpy(e).cuda()
+    ref = [x.clone() for x in solver.svd_batched(sizes, dt, et)]
+    tot, tot2 = sum(sizes), sum(n * n for n in sizes)
+    bufs = [torch.full((t + 1,), float("nan"), dtype=torch.float64, device="cuda") for t in (tot, tot2, tot2)]
+    out = [b[1:] for b in bufs]
+    assert out[1].data_ptr() % 16 == 8
+    got = solver.svd_batched(sizes, dt, et, out=out)
+    info, _ = solver.info()
+    assert info == 0
+    for x, y in zip(ref, got):
+        assert torch.equal(x, y)
+    # the element before each view is untouched
+    assert all(torch.isnan(b[0]) for b in bufs)
