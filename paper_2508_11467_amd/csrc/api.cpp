@@ -426,7 +426,7 @@ int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, do
   }
   {
     Timer t(h, st, kLeaf);
-    launch_leaf(p.dev_leaves, p.nleaves, w, st);
+    launch_leaf(p.dev_leaves, p.nleaves, p.leaf, w, st);
   }
   for (const Level& L : p.levels) {
     { Timer t(h, st, kPrep); launch_prep(L.dev, L.nnodes, L.max_m, w, st); }

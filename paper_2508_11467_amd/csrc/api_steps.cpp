@@ -134,7 +134,7 @@ int bdc_step_leaf(bdc_handle_t h, int m, int s, const double* d, const double* e
   LeafDesc L{0, 0, ld, 0, m, s};
   if (hipMemcpy(ld_dev, &L, sizeof(L), hipMemcpyHostToDevice) != hipSuccess) return BDC_ERR_HIP;
   launch_reset(w.ctl, w.st, w.sec, 1, st);
-  launch_leaf(ld_dev, 1, w, st);
+  launch_leaf(ld_dev, 1, m, w, st);
   if (hipMemcpy2DAsync(W, sizeof(double) * m, w.Uw, sizeof(double) * ld, sizeof(double) * m, m,
                        hipMemcpyDeviceToDevice, st) != hipSuccess)
     return BDC_ERR_HIP;

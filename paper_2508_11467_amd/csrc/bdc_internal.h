@@ -184,7 +184,8 @@ struct Tuning {
 
 // ---- launchers (defined next to their kernels) ----
 void launch_reset(Ctl* ctl, NodeState* st, SecCount* sec, int nnodes, hipStream_t st_);
-void launch_leaf(const LeafDesc* leaves, int nleaves, const Work& w, hipStream_t st);
+// leaves of at most max_m rows
+void launch_leaf(const LeafDesc* leaves, int nleaves, int max_m, const Work& w, hipStream_t st);
 void launch_prep(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
 void launch_rotate(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
 void launch_gather(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);

@@ -16,7 +16,6 @@ namespace bdc {
 namespace {
 
 constexpr double kEps = 0x1p-52;
-constexpr int kLd = kMaxLeaf + 1;  // LDS column stride (doubles)
 
 // lane k's value of a per-lane double, as a wave-uniform value
 __device__ inline double lane_val(double v, int k) {
@@ -51,13 +50,14 @@ __device__ inline void givens(double f, double g, double& c, double& s, double& 
   }
 }
 
-// columns (i, j) of an LDS matrix <- (c a_i + s a_j, -s a_i + c a_j), row = lane
-__device__ inline void rot_cols(double* A, int rows, int i, int j, double c, double s, int lane) {
+// columns (i, j) of an LDS matrix (column stride ld) <- (c a_i + s a_j,
+// -s a_i + c a_j), row = lane
+__device__ inline void rot_cols(double* A, int ld, int rows, int i, int j, double c, double s, int lane) {
   if (lane < rows) {
-    const double ai = A[lane + i * kLd];
-    const double aj = A[lane + j * kLd];
-    A[lane + i * kLd] = c * ai + s * aj;
-    A[lane + j * kLd] = -s * ai + c * aj;
+    const double ai = A[lane + i * ld];
+    const double aj = A[lane + j * ld];
+    A[lane + i * ld] = c * ai + s * aj;
+    A[lane + j * ld] = -s * ai + c * aj;
   }
 }
 
@@ -72,9 +72,14 @@ __device__ inline double wave_max(double v) {
 // applied by lane r to row r of the column-major LDS copies.  Along a sweep
 // the column being rotated forward stays in a register, so each step reads
 // one new column (independent of the chain) and writes one.
+// The LDS copies are sized for leaves of at most ML rows, so launches of
+// small leaves fit more wavefronts per CU (the chain is latency-bound, and a
+// batch has many leaves per SIMD).
+template <int ML>
 __global__ __launch_bounds__(64) void k_leaf(const LeafDesc* __restrict__ leaves, Work w) {
-  __shared__ double W[kMaxLeaf * kLd];
-  __shared__ double Q[(kMaxLeaf + 1) * kLd];
+  constexpr int kLd = ML + 1;  // LDS column stride (doubles)
+  __shared__ double W[ML * kLd];
+  __shared__ double Q[(ML + 1) * kLd];
 
   const LeafDesc L = leaves[blockIdx.x];
   const int m = L.m, s = L.s, ms = m + s, r0 = L.r0;
@@ -83,8 +88,8 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafDesc* __restrict__ leaves
   const int64_t pv = L.vec_off;
   unsigned long long nrot_w = 0, nrot_q = 0;  // rotations applied to W and to Q
 
-  for (int i = lane; i < kMaxLeaf * kLd; i += 64) W[i] = 0.0;
-  for (int i = lane; i < (kMaxLeaf + 1) * kLd; i += 64) Q[i] = 0.0;
+  for (int i = lane; i < ML * kLd; i += 64) W[i] = 0.0;
+  for (int i = lane; i < (ML + 1) * kLd; i += 64) Q[i] = 0.0;
   __syncthreads();
   if (lane < m) W[lane + lane * kLd] = 1.0;
   if (lane < ms) Q[lane + lane * kLd] = 1.0;
@@ -123,7 +128,7 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafDesc* __restrict__ leaves
         if (lane == j - 1) ereg = c * t;
         f = -sn * t;
       }
-      rot_cols(Q, ms, j, m, c, sn, lane);
+      rot_cols(Q, kLd, ms, j, m, c, sn, lane);
       ++nrot_q;
     }
   }
@@ -164,7 +169,7 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafDesc* __restrict__ leaves
             f = -sn * t;
             if (lane == j) ereg = c * t;
           }
-          rot_cols(W, m, j, i, c, sn, lane);
+          rot_cols(W, kLd, m, j, i, c, sn, lane);
           ++nrot_w;
         }
       } else {
@@ -180,7 +185,7 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafDesc* __restrict__ leaves
             f = -sn * t;
             if (lane == j - 1) ereg = c * t;
           }
-          rot_cols(Q, ms, j, hi, c, sn, lane);
+          rot_cols(Q, kLd, ms, j, hi, c, sn, lane);
           ++nrot_q;
         }
       }
@@ -314,9 +319,12 @@ void launch_reset(Ctl* ctl, NodeState* nst, SecCount* sec, int nnodes, hipStream
   hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, st, ctl, nst, sec, nnodes);
 }
 
-void launch_leaf(const LeafDesc* leaves, int nleaves, const Work& w, hipStream_t st) {
+void launch_leaf(const LeafDesc* leaves, int nleaves, int max_m, const Work& w, hipStream_t st) {
   if (nleaves <= 0) return;
-  hipLaunchKernelGGL(k_leaf, dim3(nleaves), dim3(64), 0, st, leaves, w);
+  if (max_m <= 8) hipLaunchKernelGGL(k_leaf<8>, dim3(nleaves), dim3(64), 0, st, leaves, w);
+  else if (max_m <= 16) hipLaunchKernelGGL(k_leaf<16>, dim3(nleaves), dim3(64), 0, st, leaves, w);
+  else if (max_m <= 24) hipLaunchKernelGGL(k_leaf<24>, dim3(nleaves), dim3(64), 0, st, leaves, w);
+  else hipLaunchKernelGGL(k_leaf<kMaxLeaf>, dim3(nleaves), dim3(64), 0, st, leaves, w);
 }
 
 }  // namespace bdc
