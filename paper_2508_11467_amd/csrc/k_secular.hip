@@ -242,18 +242,21 @@ struct SecLds<2> {
   };
 };
 
-// The network's proposals for roots base .. base+63 into xs (all threads of
-// the workgroup; LDS of m is free afterwards).
+// The network's proposals for roots base .. base+nrows-1 (nrows a multiple
+// of 16, at most 64) into xs (all threads of the workgroup; LDS of m is free
+// afterwards).
 __device__ void learned_proposals(const Work& w, MlpShared& m, const double* __restrict__ d,
-                                  const double* __restrict__ z, int N, double rho, int base, float* xs) {
+                                  const double* __restrict__ z, int N, double rho, int base, float* xs,
+                                  int nrows = kRows) {
   FeatLds& F = *reinterpret_cast<FeatLds*>(m.A.a1);
   const int B = far_block(N);
   stage_packed(w.mlp_pk, m.W);
-  for (int q = threadIdx.x; q < kRows * kFP; q += blockDim.x) m.A.a0[q] = 0;
+  for (int q = threadIdx.x; q < nrows * kFP; q += blockDim.x) m.A.a0[q] = 0;
   far_moments(d, z, N, B, F);
   __syncthreads();
-  block_features(d, z, N, rho, base, B, F, [&](int r, int q, float v) { m.A.a0[r * kFP + q] = bf16_bits(v); });
-  forward_fast(m.W, m.A, xs);
+  block_features(
+      d, z, N, rho, base, B, F, [&](int r, int q, float v) { m.A.a0[r * kFP + q] = bf16_bits(v); }, nrows);
+  forward_fast(m.W, m.A, xs, nrows);
 }
 
 // Evaluation counters of a wavefront's roots, added to its node's own
@@ -475,9 +478,10 @@ __device__ void secular_lanes(const NodeDesc& nd, int N, const Work& w, LanesLds
   const double* __restrict__ z = w.sz + vo;
   constexpr bool learned = kMode != 0;
   const int t = threadIdx.x;
-  // network proposals for the 64 roots from base rounded down to 64
+  // network proposals for the workgroup's own roots
   if constexpr (kMode == 2) {
-    if (N > 1) learned_proposals(w, M.m, d, z, N, rho, base & ~(kSecRoots - 1), s_x);
+    static_assert(kRoots % 16 == 0 && kRoots <= kSecRoots, "whole 16-row strips");
+    if (N > 1) learned_proposals(w, M.m, d, z, N, rho, base, s_x, kRoots);
   }
   // poles, padded to whole steps with far poles of weight 0 (their terms are
   // exact zeros: d^2 - omega^2 is about 2^1000, its reciprocal a normal number)
@@ -491,7 +495,7 @@ __device__ void secular_lanes(const NodeDesc& nd, int N, const Work& w, LanesLds
   const int i = base + t / L;
   const bool active = i < N;
   Root R;
-  const float xp = kMode == 2 ? s_x[i & (kSecRoots - 1)] : (kMode == 1 && active ? w.xs[vo + i] : 0.0f);
+  const float xp = kMode == 2 ? s_x[i - base] : (kMode == 1 && active ? w.xs[vo + i] : 0.0f);
   R.init(cd, N, rho, N == 1 ? z[0] : 0.0, i, active, learned, xp);
   while (R.need) {
     // left model poles j <= lp, right ones above (for the last root the

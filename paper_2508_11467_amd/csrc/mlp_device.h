@@ -115,21 +115,22 @@ __device__ inline void interval_of(const double* __restrict__ d, int N, double r
   }
 }
 
-// Features of roots base .. base+63 by a workgroup of 64 or 256 threads
-// (moments already in F).  Row r's features go to out(r, q, value) for
-// roots < N.
+// Features of roots base .. base+nrows-1 (nrows <= 64) by the whole
+// workgroup (moments already in F).  Row r's features go to out(r, q, value)
+// for roots < N.  The far-field sums are work items (row, quarter), each
+// summed in block order; the features are work items (row, pole or far
+// field), so a workgroup of 256 threads spreads the transcendental functions
+// over its lanes.  The values do not depend on how items fall on threads.
 template <class Out>
 __device__ void block_features(const double* __restrict__ d, const double* __restrict__ z, int N, double rho,
-                               int base, int B, FeatLds& F, Out out) {
-  const int r = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int i = base + r;
+                               int base, int B, FeatLds& F, Out out, int nrows = kRows) {
   const int nb = (N + B - 1) / B;
-  double lo = 0.0, h = 1.0, w2 = 1.0;
-  if (i < N) interval_of(d, N, rho, i, lo, h, w2);
-  // far field: quarter `part` of the blocks (every fourth block)
-  for (int part = wv; part < 4; part += nw) {
+  for (int item = threadIdx.x; item < 4 * nrows; item += blockDim.x) {
+    const int r = item % nrows, part = item / nrows, i = base + r;
     double v = 0.0, sl = 0.0;
     if (i < N) {
+      double lo, h, w2;
+      interval_of(d, N, rho, i, lo, h, w2);
       const double lam = lo * lo + 0.5 * w2;
       for (int k = part; k < nb; k += 4) {
         const int j0 = k * B, j1 = min(N, (k + 1) * B);
@@ -153,9 +154,15 @@ __device__ void block_features(const double* __restrict__ d, const double* __res
     F.ps[part][r] = sl;
   }
   __syncthreads();
-  if (wv == 0 && i < N) {
-    for (int q = 0; q < 4; ++q) {
-      int j = i - q;
+  // items: 0..3 the poles j = i - q, 4..7 the poles j = i + 1 + (q - 4),
+  // 8 feature 16, 9 features 17 and 18
+  for (int item = threadIdx.x; item < 10 * nrows; item += blockDim.x) {
+    const int r = item % nrows, task = item / nrows, i = base + r;
+    if (i >= N) continue;
+    double lo, h, w2;
+    interval_of(d, N, rho, i, lo, h, w2);
+    if (task < 4) {
+      const int q = task, j = i - q;
       if (j >= 0) {
         out(r, 2 * q, (float)fmax((d[j] - lo) / h, -4.0));
         out(r, 2 * q + 1, strength(z[j], w2));
@@ -163,7 +170,8 @@ __device__ void block_features(const double* __restrict__ d, const double* __res
         out(r, 2 * q, -4.0f);
         out(r, 2 * q + 1, -2.0f);
       }
-      j = i + 1 + q;
+    } else if (task < 8) {
+      const int q = task - 4, j = i + 1 + q;
       if (j < N) {
         out(r, 8 + 2 * q, (float)fmin((d[j] - lo) / h, 5.0));
         out(r, 9 + 2 * q, strength(z[j], w2));
@@ -171,12 +179,14 @@ __device__ void block_features(const double* __restrict__ d, const double* __res
         out(r, 8 + 2 * q, 5.0f);
         out(r, 9 + 2 * q, -2.0f);
       }
+    } else if (task == 8) {
+      out(r, 16, clampd(log2(rho / w2) / 32.0, -2.0, 2.0));
+    } else {
+      const double vv = 1.0 + (((F.pv[0][r] + F.pv[1][r]) + F.pv[2][r]) + F.pv[3][r]);
+      const double ss = ((F.ps[0][r] + F.ps[1][r]) + F.ps[2][r]) + F.ps[3][r];
+      out(r, 17, asinh8(vv));
+      out(r, 18, asinh8(ss * w2));
     }
-    out(r, 16, clampd(log2(rho / w2) / 32.0, -2.0, 2.0));
-    const double vv = 1.0 + (((F.pv[0][r] + F.pv[1][r]) + F.pv[2][r]) + F.pv[3][r]);
-    const double ss = ((F.ps[0][r] + F.ps[1][r]) + F.ps[2][r]) + F.ps[3][r];
-    out(r, 17, asinh8(vv));
-    out(r, 18, asinh8(ss * w2));
   }
   __syncthreads();
 }
@@ -227,31 +237,33 @@ __device__ inline void mm_fast(const unsigned short* A, int lda, const unsigned 
   }
 }
 
-// Inference of 64 rows (inputs in A.a0): the proposed positions in xout[64].
-// a1 and a2 alternate as the hidden activations (layer 3 writes a1 again).
-__device__ void forward_fast(const FastW& W, FastAct& A, float* xout) {
+// Inference of nrows rows (a multiple of 16, at most 64; inputs in A.a0):
+// the proposed positions in xout[0 .. nrows).  a1 and a2 alternate as the
+// hidden activations (layer 3 writes a1 again).  A layer's work items are
+// (16-row strip, 16-column tile) pairs dealt to the wavefronts; each output
+// element's sum runs over K in the same k-steps whatever the split.
+__device__ void forward_fast(const FastW& W, FastAct& A, float* xout, int nrows = kRows) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const int strips = nrows / 16;
   for (int l = 0; l < 3; ++l) {
     const unsigned short* in = l == 0 ? A.a0 : (l == 1 ? A.a1 : A.a2);
     unsigned short* outl = l == 1 ? A.a2 : A.a1;
     const unsigned short* wt = W.w + (l == 0 ? kPkW1 : (l == 1 ? kPkW2 : kPkW3));
     const float* bl = W.b + l * kH;
     const int K = l == 0 ? kFP : kH;
-    for (int strip = wv; strip < 4; strip += nw) {
-      const int r0 = strip * 16;
-      f32x4 acc[4];
-      for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-      mm_fast(in, K, wt, K, r0, K, 4, acc);
-      for (int nt = 0; nt < 4; ++nt)
-        for (int r = 0; r < 4; ++r) {
-          const int row = r0 + 4 * (lane >> 4) + r, col = nt * 16 + (lane & 15);
-          outl[row * kH + col] = bf16_bits(gelu_f(acc[nt][r] + bl[col]));
-        }
+    for (int item = wv; item < 4 * strips; item += nw) {
+      const int r0 = (item >> 2) * 16, nt = item & 3;
+      f32x4 acc[1] = {f32x4{0.f, 0.f, 0.f, 0.f}};
+      mm_fast(in, K, wt + nt * 16 * K, K, r0, K, 1, acc);
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + 4 * (lane >> 4) + r, col = nt * 16 + (lane & 15);
+        outl[row * kH + col] = bf16_bits(gelu_f(acc[0][r] + bl[col]));
+      }
     }
     __syncthreads();
   }
   // 64 -> 1 as column 0 of a 16-wide product
-  for (int strip = wv; strip < 4; strip += nw) {
+  for (int strip = wv; strip < strips; strip += nw) {
     const int r0 = strip * 16;
     f32x4 acc[1] = {f32x4{0.f, 0.f, 0.f, 0.f}};
     mm_fast(A.a1, kH, W.w + kPkW4, kH, r0, kH, 1, acc);
