@@ -225,11 +225,16 @@ struct PoleLds {
   double cd[kSecWaves][kSecChunk];
   double cz[kSecWaves][kSecChunk];
 };
-struct MlpShared {
+// Weights, activations of R rows, and the feature scratch for MB far-field
+// blocks in A.a1 .. A.a2.
+template <int R, int MB>
+struct MlpSharedT {
+  using Feat = FeatLdsT<MB, R>;
   FastW W;
-  FastAct A;  // A.a1 .. A.a2 also hold the feature scratch (FeatLds)
+  FastActT<R> A;
+  static_assert(sizeof(Feat) <= sizeof(A.a1) + sizeof(A.a2), "feature scratch");
 };
-static_assert(sizeof(FeatLds) <= sizeof(FastAct::a1) + sizeof(FastAct::a2), "feature scratch");
+using MlpShared = MlpSharedT<kRows, kMaxBlocks>;
 template <int kMode>
 struct SecLds {
   PoleLds p;
@@ -245,10 +250,12 @@ struct SecLds<2> {
 // The network's proposals for roots base .. base+nrows-1 (nrows a multiple
 // of 16, at most 64) into xs (all threads of the workgroup; LDS of m is free
 // afterwards).
-__device__ void learned_proposals(const Work& w, MlpShared& m, const double* __restrict__ d,
+template <class MS>
+__device__ void learned_proposals(const Work& w, MS& m, const double* __restrict__ d,
                                   const double* __restrict__ z, int N, double rho, int base, float* xs,
-                                  int nrows = kRows) {
-  FeatLds& F = *reinterpret_cast<FeatLds*>(m.A.a1);
+                                  int nrows) {
+  using Feat = typename MS::Feat;
+  Feat& F = *reinterpret_cast<Feat*>(m.A.a1);
   const int B = far_block(N);
   stage_packed(w.mlp_pk, m.W);
   for (int q = threadIdx.x; q < nrows * kFP; q += blockDim.x) m.A.a0[q] = 0;
@@ -328,7 +335,7 @@ __device__ void secular_wide(const NodeDesc& nd, int N, const Work& w, WideLds<k
     if constexpr (kMode == 2) {
       // the network's proposals for roots base .. base+63, then the poles
       __syncthreads();
-      learned_proposals(w, L.m, d, z, N, rho, base, s_x);
+      learned_proposals(w, L.m, d, z, N, rho, base, s_x, kRows);
       if (resident)
         for (int j = q0 + lane; j < q1; j += 64) {
           cd[wv][j - q0] = d[j];
@@ -435,8 +442,10 @@ __device__ void secular_wide(const NodeDesc& nd, int N, const Work& w, WideLds<k
 // same iteration state.  A wavefront holds 64/L roots, so it iterates only as
 // long as the slowest of those few.
 constexpr int kLanesMaxN = kSecLanesMaxN;
+// The lanes-per-root kernel's network: at most 32 rows (its roots per
+// workgroup) and, for N <= kLanesMaxN = 256, at most 16 far-field blocks.
 struct SmallMlp {
-  MlpShared m;
+  MlpSharedT<32, 16> m;
 };
 
 // v summed over the aligned group of L lanes (L in {8, 16}; within a DPP row)
@@ -480,7 +489,8 @@ __device__ void secular_lanes(const NodeDesc& nd, int N, const Work& w, LanesLds
   const int t = threadIdx.x;
   // network proposals for the workgroup's own roots
   if constexpr (kMode == 2) {
-    static_assert(kRoots % 16 == 0 && kRoots <= kSecRoots, "whole 16-row strips");
+    static_assert(kRoots % 16 == 0 && kRoots <= 32, "whole 16-row strips, at most SmallMlp's rows");
+    static_assert(kLanesMaxN <= 16 * 16, "far_block(N) gives at most 16 blocks for N <= 256");
     if (N > 1) learned_proposals(w, M.m, d, z, N, rho, base, s_x, kRoots);
   }
   // poles, padded to whole steps with far poles of weight 0 (their terms are
@@ -544,6 +554,16 @@ __global__ __launch_bounds__(256) void k_secular(const NodeDesc* __restrict__ no
   const int N = w.st[nd.id].N;
   if (N <= w.sec_small_n && N <= kLanesMaxN) secular_lanes<kMode, L>(nd, N, w, S.lanes);
   else secular_wide<kMode>(nd, N, w, S.wide);
+}
+
+// Levels whose merges all take the lanes-per-root body (every merge at most
+// sec_small_n <= kLanesMaxN values): the LDS of that body alone, so more
+// workgroups fit on a CU.
+template <int kMode, int L>
+__global__ __launch_bounds__(256) void k_secular_lanes(const NodeDesc* __restrict__ nodes, Work w) {
+  __shared__ LanesLds<kMode, L> S;
+  const NodeDesc nd = nodes[blockIdx.x];
+  secular_lanes<kMode, L>(nd, w.st[nd.id].N, w, S);
 }
 
 __global__ __launch_bounds__(256) void k_lowner(const NodeDesc* __restrict__ nodes, Work w) {
@@ -663,9 +683,12 @@ void launch_secular(const NodeDesc* nodes, int nnodes, int max_m, const Work& w,
   const int gy = grid_y(nnodes, std::max(ys, yw), 4096 + nnodes * ys);
   const dim3 grid(nnodes, gy), block(256);
   const int mode = w.mlp_pk ? 2 : (w.xs ? 1 : 0);
+  const bool lanes_only = max_m <= small_max;  // every merge has N <= max_m <= small_max
 #define BDC_LAUNCH_SEC(M)                                                                        \
   do {                                                                                           \
-    if (l8) hipLaunchKernelGGL((k_secular<M, 8>), grid, block, 0, st, nodes, w);                 \
+    if (lanes_only && l8) hipLaunchKernelGGL((k_secular_lanes<M, 8>), grid, block, 0, st, nodes, w); \
+    else if (lanes_only) hipLaunchKernelGGL((k_secular_lanes<M, 16>), grid, block, 0, st, nodes, w); \
+    else if (l8) hipLaunchKernelGGL((k_secular<M, 8>), grid, block, 0, st, nodes, w);            \
     else hipLaunchKernelGGL((k_secular<M, 16>), grid, block, 0, st, nodes, w);                   \
   } while (0)
   if (mode == 2) BDC_LAUNCH_SEC(2);

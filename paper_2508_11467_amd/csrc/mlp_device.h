@@ -78,15 +78,20 @@ __device__ inline int far_block(int N) {
   return B;
 }
 
-struct FeatLds {
-  double Z[kMaxBlocks];
-  double D[kMaxBlocks];
-  double pv[4][kRows];
-  double ps[4][kRows];
+// Feature scratch for at most MB far-field blocks and R rows.
+template <int MB, int R>
+struct FeatLdsT {
+  static constexpr int kBlocks = MB;
+  double Z[MB];
+  double D[MB];
+  double pv[4][R];
+  double ps[4][R];
 };
+using FeatLds = FeatLdsT<kMaxBlocks, kRows>;
 
 // Block moments Z_k, D_k by the whole workgroup (call, then synchronise).
-__device__ void far_moments(const double* __restrict__ d, const double* __restrict__ z, int N, int B, FeatLds& F) {
+template <class FL>
+__device__ void far_moments(const double* __restrict__ d, const double* __restrict__ z, int N, int B, FL& F) {
   const int nb = (N + B - 1) / B;
   for (int k = threadIdx.x; k < nb; k += blockDim.x) {
     double zs = 0.0, ms = 0.0;
@@ -121,9 +126,9 @@ __device__ inline void interval_of(const double* __restrict__ d, int N, double r
 // summed in block order; the features are work items (row, pole or far
 // field), so a workgroup of 256 threads spreads the transcendental functions
 // over its lanes.  The values do not depend on how items fall on threads.
-template <class Out>
+template <class FL, class Out>
 __device__ void block_features(const double* __restrict__ d, const double* __restrict__ z, int N, double rho,
-                               int base, int B, FeatLds& F, Out out, int nrows = kRows) {
+                               int base, int B, FL& F, Out out, int nrows = kRows) {
   const int nb = (N + B - 1) / B;
   for (int item = threadIdx.x; item < 4 * nrows; item += blockDim.x) {
     const int r = item % nrows, part = item / nrows, i = base + r;
@@ -208,11 +213,15 @@ struct FastW {
   float b[kPkBias + 3];
 };
 
-struct FastAct {
-  unsigned short a0[kRows * kFP];
-  unsigned short a1[kRows * kH];
-  unsigned short a2[kRows * kH];
+// Activations of R rows (bfloat16 bits)
+template <int R>
+struct FastActT {
+  static constexpr int kR = R;
+  unsigned short a0[R * kFP];
+  unsigned short a1[R * kH];
+  unsigned short a2[R * kH];
 };
+using FastAct = FastActT<kRows>;
 
 __device__ void stage_packed(const unsigned short* __restrict__ pk, FastW& W) {
   const uint4* src = (const uint4*)pk;
@@ -242,7 +251,8 @@ __device__ inline void mm_fast(const unsigned short* A, int lda, const unsigned 
 // hidden activations (layer 3 writes a1 again).  A layer's work items are
 // (16-row strip, 16-column tile) pairs dealt to the wavefronts; each output
 // element's sum runs over K in the same k-steps whatever the split.
-__device__ void forward_fast(const FastW& W, FastAct& A, float* xout, int nrows = kRows) {
+template <class Act>
+__device__ void forward_fast(const FastW& W, Act& A, float* xout, int nrows = Act::kR) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   const int strips = nrows / 16;
   for (int l = 0; l < 3; ++l) {
