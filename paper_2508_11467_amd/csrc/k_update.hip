@@ -360,8 +360,14 @@ struct NodeStore {
 // slice z = 4 whose workgroups do k_order's work (it touches none of the
 // products' data), saving a launch per level.  Tiles are visited with the row
 // index fastest, so the workgroups on one XCD (every 8th) share B panels.
+// The 64-tile class is held to four wavefronts per SIMD (126 registers, no
+// spills; unbounded it takes 168 and three): the small merges of a level are
+// thousands of short workgroups, and residency decides their time.
+constexpr int update_waves_per_eu(int tm) { return tm <= 64 ? 4 : 1; }
+
 template <int TM, int TN>
-__global__ __launch_bounds__(256) void k_update(const NodeDesc* __restrict__ nodes, Work w) {
+__global__ __launch_bounds__(256, update_waves_per_eu(TM)) void k_update(const NodeDesc* __restrict__ nodes,
+                                                                          Work w) {
   __shared__ TileSmem<TM, TN> sm;
   const NodeDesc nd = nodes[blockIdx.x];
   if (blockIdx.z == 4) {  // the 64-tile launch also carries the node's k_order work
@@ -446,7 +452,7 @@ __global__ __launch_bounds__(256) void k_tile_sched(const NodeDesc* __restrict__
 // Persistent form of k_update: a fixed grid walks the level's flattened tile
 // list of its class.
 template <int TM, int TN>
-__global__ __launch_bounds__(256) void k_update_flat(const NodeDesc* __restrict__ nodes, int nnodes, Work w) {
+__global__ __launch_bounds__(256, update_waves_per_eu(TM)) void k_update_flat(const NodeDesc* __restrict__ nodes, int nnodes, Work w) {
   __shared__ TileSmem<TM, TN> sm;
   const int* __restrict__ off = TM <= 64 ? w.tile_off64 : w.tile_off128;
   const int total = off[nnodes];
