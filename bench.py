@@ -43,7 +43,10 @@ WORKLOADS = {
     "n16384_ones": ("n = 16384, d = e = 1 (no deflation, update-GEMM bound)", 16384),
     "n4096_uniform": ("n = 4096, d, e iid U(-1,1)", 4096),
     "batch2000": ("2000 bidiagonals, sizes round(exp(U(ln 32, ln 2048))), d, e iid U(-1,1)", 0),
+    "sigma_laws": ("n = 1024 bidiagonals with the paper's singular-value laws (logrand, arith, geo at "
+                   "theta = 1e6 and 1e12), built by Golub-Kahan-Lanczos on diag(sigma)", 1024),
 }
+SIGMA_LAWS = [("logrand", 1e6), ("arith", 1e6), ("geo", 1e6), ("geo", 1e12), ("logrand", 1e12)]
 
 
 def parse():
@@ -271,6 +274,52 @@ def bench_batched(args, desc):
     print(json.dumps(line), flush=True)
 
 
+def bench_sigma_laws(args, desc, n):
+    """Each law: time per solve (autotuned), the largest |sigma_k - law_k|
+    relative to sigma_1 beside the generator's own bound delta, residual and
+    orthogonality."""
+    import numpy as np
+    import torch
+
+    from paper_2508_11467_amd import inputs
+    from paper_2508_11467_amd.api import Solver
+    dev = torch.device("cuda:0")
+    out = (torch.empty(n, dtype=torch.float64, device=dev), torch.empty((n, n), dtype=torch.float64, device=dev),
+           torch.empty((n, n), dtype=torch.float64, device=dev))
+    per = {}
+    total_ms = 0.0
+    for k, (law, theta) in enumerate(SIGMA_LAWS):
+        s = inputs.sigma_law(n, law, theta, seed=inputs.seed_for(6, k))
+        d, e, delta = inputs.gkl_bidiagonal(s, inputs.seed_for(6, 10 + k))
+        dt, et = torch.from_numpy(d).to(dev), torch.from_numpy(e).to(dev)
+        solver = Solver(0)
+        solver.autotune([n], dt, et, out=out, repeats=2)
+        ms = time_solver(solver, dt, et, out, args.steps, args.warmup)
+        info, _ = solver.info()
+        solver.close()
+        sig, ub, vb = out
+        U, VT = ub.T, vb.T
+        B = torch.diag(dt) + torch.diag(et, 1)
+        I = torch.eye(n, dtype=torch.float64, device=dev)
+        per[f"{law}({theta:g})"] = {
+            "ms_per_step": ms,
+            "sigma_err_rel": float(np.max(np.abs(sig.cpu().numpy() - s)) / s[0]),
+            "generator_delta_rel": delta / s[0],
+            "residual": float(torch.linalg.norm(B - (U * sig[None, :]) @ VT) / torch.linalg.norm(B)),
+            "orth": max(float(torch.max(torch.abs(U.T @ U - I))), float(torch.max(torch.abs(VT @ VT.T - I)))),
+            "info": info,
+        }
+        total_ms += ms
+    nominal = len(SIGMA_LAWS) * (8.0 / 3.0) * n ** 3
+    line = {
+        "metric": METRIC, "value": nominal / (total_ms * 1e-3) / 1e9, "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": total_ms / len(SIGMA_LAWS),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "n": n}, "laws": per,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(n: int):
     import numpy as np  # noqa: F401
 
@@ -314,6 +363,8 @@ def main():
     desc, n = WORKLOADS[args.workload]
     if args.workload == "batch2000":
         return bench_batched(args, desc)
+    if args.workload == "sigma_laws":
+        return bench_sigma_laws(args, desc, n)
     d, e = inputs.workload(args.workload)
     dev = torch.device("cuda:0")
     dt = torch.from_numpy(d).to(dev)

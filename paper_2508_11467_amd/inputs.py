@@ -107,6 +107,69 @@ def batch_uniform(sizes, seed: int) -> tuple[np.ndarray, np.ndarray]:
     return d, e
 
 
+def sigma_law(n: int, law: str, theta: float, seed: int | None = None) -> np.ndarray:
+    """Singular values of the paper's test-matrix types (Section 3), in
+    descending order, with condition number theta:
+
+    * ``logrand``: log sigma_i iid uniform over (log(1/theta), log 1), seeded;
+    * ``arith``: sigma_i = 1 - (i-1)/(n-1) (1 - 1/theta);
+    * ``geo``: sigma_i = theta^(-(i-1)/(n-1)).
+    """
+    if n == 1:
+        return np.ones(1)
+    i = np.arange(n, dtype=np.float64)
+    if law == "arith":
+        s = 1.0 - i / (n - 1) * (1.0 - 1.0 / theta)
+    elif law == "geo":
+        s = theta ** (-i / (n - 1))
+    elif law == "logrand":
+        s = np.exp(_rng(seed).uniform(np.log(1.0 / theta), 0.0, n))
+    else:
+        raise KeyError(law)
+    return np.sort(s)[::-1].copy()
+
+
+def gkl_bidiagonal(sigma: np.ndarray, seed: int) -> tuple[np.ndarray, np.ndarray, float]:
+    """Upper bidiagonal B with singular values sigma: Golub-Kahan-Lanczos
+    bidiagonalisation of A = diag(sigma) from a seeded random unit start
+    vector, with full reorthogonalisation (twice) of both Lanczos bases, so
+    that A V = U B with U and V orthogonal to working precision.
+
+    Returns (d, e, delta), where delta bounds |sigma_k(B) - sigma_k| for every
+    k (Weyl): delta = ||A V - U B||_2 + ||A||_2 max(||U^T U - I||_2,
+    ||V^T V - I||_2) computed in FP64, with a factor 2 of headroom for the
+    rounding of that evaluation itself.
+    """
+    n = len(sigma)
+    g = _rng(seed)
+    U = np.zeros((n, n))
+    V = np.zeros((n, n))
+    d = np.zeros(n)
+    e = np.zeros(max(n - 1, 0))
+    v = g.standard_normal(n)
+    V[:, 0] = v / np.linalg.norm(v)
+    for k in range(n):
+        u = sigma * V[:, k]
+        if k > 0:
+            u -= e[k - 1] * U[:, k - 1]
+        for _ in range(2):
+            u -= U[:, :k] @ (U[:, :k].T @ u)
+        d[k] = np.linalg.norm(u)
+        U[:, k] = u / d[k]
+        if k + 1 < n:
+            v = sigma * U[:, k] - d[k] * V[:, k]
+            for _ in range(2):
+                v -= V[:, :k + 1] @ (V[:, :k + 1].T @ v)
+            e[k] = np.linalg.norm(v)
+            V[:, k + 1] = v / e[k]
+    B = np.diag(d) + np.diag(e, 1)
+    I = np.eye(n)
+    res = np.linalg.norm(sigma[:, None] * V - U @ B, 2)
+    orth = max(np.linalg.norm(U.T @ U - I, 2), np.linalg.norm(V.T @ V - I, 2))
+    delta = 2.0 * (res + float(np.max(sigma)) * orth)
+    return d, e, delta
+
+
 # Named workloads (sizes and spectra of the measured configurations).
 def workload(name: str) -> tuple[np.ndarray, np.ndarray]:
     if name == "n256_uniform":
