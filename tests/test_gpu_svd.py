@@ -234,3 +234,37 @@ def test_full_size_n16384_normal(solver):
 def test_full_size_n16384_ones(solver):
     d, e = inputs.workload("n16384_ones")
     st = _full_size_checks(solver, d, e, samples=[0, 16383])
+
+
+def test_full_size_n16384_normal_autotuned(gpu):
+    """The headline workload in the launch configuration bench.py times: the
+    library's autotuner picks leaf size and launch shapes first."""
+    import torch
+    from paper_2508_11467_amd.api import Solver
+    d, e = inputs.workload("n16384_normal")
+    n = len(d)
+    s = Solver(0)
+    try:
+        dt, et = torch.from_numpy(d).cuda(), torch.from_numpy(e).cuda()
+        out = (torch.empty(n, dtype=torch.float64, device="cuda"),
+               torch.empty((n, n), dtype=torch.float64, device="cuda"),
+               torch.empty((n, n), dtype=torch.float64, device="cuda"))
+        best = s.autotune([n], dt, et, out=out, repeats=1)
+        print("tuning", best, flush=True)
+        del out
+        _full_size_checks(s, d, e, samples=[0, 5000, 16383])
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("start", ["plain", "learned"])
+def test_full_size_n32768_normal(gpu, start):
+    """n = 32768, d, e iid N(0,1) (the plain/learned comparison's workload)."""
+    from paper_2508_11467_amd.api import Solver
+    d, e = inputs.workload("n32768_normal")
+    s = Solver(0, start=start)
+    try:
+        st = _full_size_checks(s, d, e, samples=[0, 20000, 32767])
+        assert st["levels"] == 10
+    finally:
+        s.close()
