@@ -590,22 +590,23 @@ __global__ __launch_bounds__(256) void k_final_u(const int64_t* __restrict__ pn,
 }
 
 // V^T: bands of kVtBand output rows (singular vectors); a workgroup takes
-// one band and kVtTilesPerGroup tiles of kVtTile output columns.  A tile that
-// no vector of the band reaches (outside every support) is written as zeros
-// directly; the others read each vector's kVtTile-entry run of its Vwork
-// column inside the support (eight threads per 128-byte run, two entries
-// each), turn the tile around in LDS and write each output column's kVtBand
-// rows as one 2 KB run.  Measured on the 2000-problem batch, this shape beats
-// 64 x 64 tiles (512-byte runs), 512 x 8 tiles and one entry per lane.
+// one band and kVtTilesPerGroup tiles of kVtTile output columns.  Each
+// vector's kVtTile-entry run of its Vwork column is read inside its support
+// only (eight threads per 128-byte run, two entries each; entries outside
+// the support are zeros without a read), the tile is turned around in LDS
+// and each output column's kVtBand rows leave as one 2 KB run.  The next
+// tile's reads are issued before the current tile's LDS round trip and
+// stores.  Measured on the 2000-problem batch, this shape beats 64 x 64
+// tiles (512-byte runs), 512 x 8 tiles and one entry per lane.
 __global__ __launch_bounds__(256) void k_final_vt(const int64_t* __restrict__ pn,
                                                   const int64_t* __restrict__ pvec,
                                                   const int64_t* __restrict__ pmat,
                                                   const int64_t* __restrict__ vitem_off,
                                                   const int32_t* __restrict__ vprob, Work w, double* VT) {
   static_assert(kVtBand == kBlock && kVtTile == 16, "one vector per thread, eight threads per run");
+  constexpr int kPass = kVtBand / (kBlock / 8);  // vectors per thread in the reads
   __shared__ double tileS[kVtTile][kVtBand + 1];
   __shared__ int pcs[kVtBand], lov[kVtBand], hiv[kVtBand];
-  __shared__ int s_any;
   const int64_t gt = blockIdx.x;
   const int pr = vprob[gt];
   const int64_t n = pn[pr], pv = pvec[pr], mo = pmat[pr];
@@ -615,6 +616,7 @@ __global__ __launch_bounds__(256) void k_final_vt(const int64_t* __restrict__ pn
   const int64_t t0 = (item % nb) * kVtBand;  // first output row (singular vector index)
   const int64_t g0 = (item / nb) * kVtTilesPerGroup;
   const int64_t ntile = (n + kVtTile - 1) / kVtTile;
+  const int64_t gend = min(ntile, g0 + kVtTilesPerGroup);
   const int t = threadIdx.x;
   const int64_t tv = t0 + t;  // this thread's vector (meta) and output row (stores)
   if (tv < n) {
@@ -630,42 +632,47 @@ __global__ __launch_bounds__(256) void k_final_vt(const int64_t* __restrict__ pn
   __syncthreads();
   const double* Vw = w.Vw + mo;
   double* out = VT + mo;
-  for (int64_t g = g0; g < min(ntile, g0 + kVtTilesPerGroup); ++g) {
-    const int64_t j0 = g * kVtTile;
-    const int jn = (int)min((int64_t)kVtTile, n - j0);
-    // does any vector of the band reach columns j0 .. j0 + kVtTile - 1?
-    if (t == 0) s_any = 0;
-    __syncthreads();
-    if (pcs[t] >= 0 && j0 < hiv[t] && j0 + kVtTile > lov[t]) s_any = 1;
-    __syncthreads();
-    if (!s_any) {
-      if (tv < n)
-        for (int jj = 0; jj < jn; ++jj) out[tv + (j0 + jj) * n] = 0.0;
-      continue;
-    }
-    // load: eight threads per vector, two entries each; 32 vectors per pass
-    {
-      const int part = t & 7;
-      const int64_t ja = j0 + 2 * part, jb = ja + 1;
-#pragma unroll 4
-      for (int tt = t >> 3; tt < kVtBand; tt += kBlock / 8) {
-        const int pc = pcs[tt];
-        const int lo = lov[tt], hi = hiv[tt];
-        double a = 0.0, b = 0.0;
-        if (pc >= 0) {
-          const double* col = Vw + (int64_t)pc * n;
-          if (ja < n && ja >= lo && ja < hi) a = col[ja];
-          if (jb < n && jb >= lo && jb < hi) b = col[jb];
-        }
-        tileS[2 * part][tt] = a;
-        tileS[2 * part + 1][tt] = b;
+  const int part = t & 7;
+  auto fetch = [&](int64_t g, double (&x)[2 * kPass]) {
+    const int64_t ja = g * kVtTile + 2 * part, jb = ja + 1;
+#pragma unroll
+    for (int p = 0; p < kPass; ++p) {
+      const int tt = (t >> 3) + p * (kBlock / 8);
+      const int pc = pcs[tt];
+      const int lo = lov[tt], hi = hiv[tt];
+      double a = 0.0, b = 0.0;
+      if (pc >= 0) {
+        const double* col = Vw + (int64_t)pc * n;
+        if (ja < n && ja >= lo && ja < hi) a = col[ja];
+        if (jb < n && jb >= lo && jb < hi) b = col[jb];
       }
+      x[2 * p] = a;
+      x[2 * p + 1] = b;
+    }
+  };
+  auto put = [&](int64_t g, const double (&x)[2 * kPass]) {
+    const int jn = (int)min((int64_t)kVtTile, n - g * kVtTile);
+#pragma unroll
+    for (int p = 0; p < kPass; ++p) {
+      const int tt = (t >> 3) + p * (kBlock / 8);
+      tileS[2 * part][tt] = x[2 * p];
+      tileS[2 * part + 1][tt] = x[2 * p + 1];
     }
     __syncthreads();
-    // store: output column j0 + jj, rows t0 .. t0 + kVtBand - 1, a row per thread
+    // output column g kVtTile + jj, rows t0 .. t0 + kVtBand - 1, a row per thread
     if (tv < n)
-      for (int jj = 0; jj < jn; ++jj) out[tv + (j0 + jj) * n] = tileS[jj][t];
+      for (int jj = 0; jj < jn; ++jj) out[tv + (g * kVtTile + jj) * n] = tileS[jj][t];
     __syncthreads();
+  };
+  double A[2 * kPass], B[2 * kPass];
+  fetch(g0, A);
+  for (int64_t g = g0;; g += 2) {
+    if (g + 1 < gend) fetch(g + 1, B);
+    put(g, A);
+    if (g + 1 >= gend) return;
+    if (g + 2 < gend) fetch(g + 2, A);
+    put(g + 1, B);
+    if (g + 2 >= gend) return;
   }
 }
 
