@@ -541,11 +541,24 @@ __global__ __launch_bounds__(256) void k_final_u(const int64_t* __restrict__ pn,
       sigma[pv + tcol] = w.sig[pv + src];
     }
     __syncthreads();
-    double* out = U + mo + c0 * n;
+    double* __restrict__ out = U + mo + c0 * n;
+    const double* __restrict__ Uw = w.Uw + mo;
     const int nn = (int)n, tot = cols * nn;
-    for (int e = t; e < tot; e += kBlock) {
-      const int col = e / nn, row = e - col * nn;
-      out[e] = (row >= s_ul[col] && row < s_uh[col]) ? w.Uw[mo + s_pc[col] * n + row] : 0.0;
+    // four reads in flight per thread before their stores
+    for (int e0 = t; e0 < tot; e0 += 4 * kBlock) {
+      double v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + q * kBlock;
+        v[q] = 0.0;
+        if (e < tot) {
+          const int col = e / nn, row = e - col * nn;
+          if (row >= s_ul[col] && row < s_uh[col]) v[q] = Uw[s_pc[col] * n + row];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (e0 + q * kBlock < tot) out[e0 + q * kBlock] = v[q];
     }
     return;
   }
