@@ -400,6 +400,76 @@ __global__ __launch_bounds__(256, update_waves_per_eu(TM)) void k_update(const N
   }
 }
 
+// Levels whose merges are all at most 16 B values (rows and kept columns of
+// every side-half <= 16 B): one workgroup per node, wavefront q the
+// side-half q (U rows [0,k), U rows [k,m), V rows [0,k), V rows [k,m+s)) as
+// one (16 B) x (16 B) output of B x B v_mfma_f64_16x16x4f64 blocks with its
+// operands read straight from the gathered columns, then the node's k_order
+// work.  The k-steps run in the order of the 64-tile products (k = 0, 4, 8,
+// ...), so the sums are the same.  A level of many tiny merges takes one
+// short workgroup per node instead of five 64 x 64 tiles that are mostly
+// padding.
+template <int B>
+__global__ __launch_bounds__(256) void k_update_wave(const NodeDesc* __restrict__ nodes, Work w) {
+  constexpr int TW = 16 * B;
+  const NodeDesc nd = nodes[blockIdx.x];
+  const int sub = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const NodeState st = w.st[nd.id];
+  const int N = st.N, n1 = st.n1, n2 = st.n2;
+  if (N < w.oz.min_n) {  // larger kept sizes are done by the split-precision products
+    const int m = nd.m, s = nd.s, k = nd.k, r0 = nd.r0;
+    const int64_t ld = nd.ld, vo = nd.vec_off + nd.r0;
+    const bool isV = sub >= 2, bottom = sub & 1;
+    const int rows = bottom ? (isV ? m + s - k : m - k) : k;
+    const int kb = bottom ? n1 : 0;
+    const int ke = bottom ? N : n1 + 1 + n2;
+    const int K = ke - kb;
+    const int rowoff = bottom ? k : 0;
+    const double* G = (isV ? w.GV : w.GU) + nd.mat_off;
+    const double* Mv = (isV ? w.VM : w.UM) + nd.mat_off;
+    const double* __restrict__ A = G + (r0 + rowoff) + (int64_t)(r0 + kb) * ld;
+    const double* __restrict__ Bm = Mv + (r0 + kb) + (int64_t)r0 * ld;
+    NodeStore store{(isV ? w.Vw : w.Uw) + nd.mat_off, w.scol + vo, ld, r0 + rowoff};
+    const int li = l & 15, lk = l >> 4;
+    v4d acc[B][B];
+#pragma unroll
+    for (int a = 0; a < B; ++a)
+#pragma unroll
+      for (int b = 0; b < B; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int gk = k0 + lk;
+      double af[B], bf[B];
+#pragma unroll
+      for (int a = 0; a < B; ++a) {
+        const int row = a * 16 + li;
+        af[a] = (row < rows && gk < K) ? A[row + (int64_t)gk * ld] : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int col = b * 16 + li;
+        bf[b] = (gk < K && col < N) ? Bm[gk + (int64_t)col * ld] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < B; ++a)
+#pragma unroll
+        for (int b = 0; b < B; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+    // D[i][j] of a 16x16 block sits in lane j + 16 (i % 4), register i / 4
+#pragma unroll
+    for (int a = 0; a < B; ++a)
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = a * 16 + lk + 4 * r, col = b * 16 + li;
+          if (row < rows && col < N) *(store.col(col) + row) = acc[a][b][r];
+        }
+    static_assert(TW >= 16, "tile");
+  }
+  order_node(nd, w);
+}
+
 // ---- flattened schedule: all tiles of a level in one list per tile class.
 // Tiles of a node, sub-half by sub-half (0 U rows [0,k), 1 U rows [k,m),
 // 2 V rows [0,k), 3 V rows [k,m+s)), row index fastest.
@@ -867,6 +937,14 @@ void launch_order(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, h
 void launch_update(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, const Tuning& tu,
                    hipStream_t st) {
   if (nnodes <= 0) return;
+  // every side-half at most 16 B x 16 B (rows <= m + 1 - k, N <= m): one
+  // workgroup per node, carrying the k_order work too
+  if (max_m <= 64) {
+    if (max_m <= 32) hipLaunchKernelGGL((k_update_wave<2>), dim3(nnodes), dim3(kBlock), 0, st, nodes, w);
+    else if (max_m <= 48) hipLaunchKernelGGL((k_update_wave<3>), dim3(nnodes), dim3(kBlock), 0, st, nodes, w);
+    else hipLaunchKernelGGL((k_update_wave<4>), dim3(nnodes), dim3(kBlock), 0, st, nodes, w);
+    return;
+  }
   if (tu.flat) {
     launch_order(nodes, nnodes, max_m, w, st);
     hipLaunchKernelGGL(k_tile_sched, dim3(1), dim3(kBlock), 0, st, nodes, nnodes, w);
