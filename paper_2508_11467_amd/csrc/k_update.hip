@@ -938,8 +938,11 @@ void launch_update(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, 
                    hipStream_t st) {
   if (nnodes <= 0) return;
   // every side-half at most 16 B x 16 B (rows <= m + 1 - k, N <= m): one
-  // workgroup per node, carrying the k_order work too
-  if (max_m <= 64) {
+  // workgroup per node, carrying the k_order work too.  The 64-wide form
+  // (two wavefronts per SIMD) wins only on levels of thousands of merges
+  // (batches); a single problem's level of a few hundred merges of about 64
+  // values runs faster as 64 x 64 tiles (measured 19 vs 27 us).
+  if (max_m <= 48 || (max_m <= 64 && nnodes >= 2048)) {
     if (max_m <= 32) hipLaunchKernelGGL((k_update_wave<2>), dim3(nnodes), dim3(kBlock), 0, st, nodes, w);
     else if (max_m <= 48) hipLaunchKernelGGL((k_update_wave<3>), dim3(nnodes), dim3(kBlock), 0, st, nodes, w);
     else hipLaunchKernelGGL((k_update_wave<4>), dim3(nnodes), dim3(kBlock), 0, st, nodes, w);
