@@ -225,12 +225,11 @@ struct PoleLds {
   double cd[kSecWaves][kSecChunk];
   double cz[kSecWaves][kSecChunk];
 };
-// Weights, activations of R rows, and the feature scratch for MB far-field
-// blocks in A.a1 .. A.a2.
+// Activations of R rows, and the feature scratch for MB far-field blocks in
+// A.a1 .. A.a2 (the network's weights are read from global memory).
 template <int R, int MB>
 struct MlpSharedT {
   using Feat = FeatLdsT<MB, R>;
-  FastW W;
   FastActT<R> A;
   static_assert(sizeof(Feat) <= sizeof(A.a1) + sizeof(A.a2), "feature scratch");
 };
@@ -257,13 +256,12 @@ __device__ void learned_proposals(const Work& w, MS& m, const double* __restrict
   using Feat = typename MS::Feat;
   Feat& F = *reinterpret_cast<Feat*>(m.A.a1);
   const int B = far_block(N);
-  stage_packed(w.mlp_pk, m.W);
   for (int q = threadIdx.x; q < nrows * kFP; q += blockDim.x) m.A.a0[q] = 0;
   far_moments(d, z, N, B, F);
   __syncthreads();
   block_features(
       d, z, N, rho, base, B, F, [&](int r, int q, float v) { m.A.a0[r * kFP + q] = bf16_bits(v); }, nrows);
-  forward_fast(m.W, m.A, xs, nrows);
+  forward_fast(w.mlp_pk, reinterpret_cast<const float*>(w.mlp_pk + kPkHalf), m.A, xs, nrows);
 }
 
 // Evaluation counters of a wavefront's roots, added to its node's own

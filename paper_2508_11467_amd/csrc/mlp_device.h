@@ -208,11 +208,6 @@ constexpr int kPkHalf = kPkW4 + 16 * kH;  // bfloat16 entries
 constexpr int kPkBias = 3 * kH + 1;       // b1, b2, b3, b4 (FP32)
 constexpr size_t kPackBytes = (size_t)kPkHalf * 2 + (size_t)kPkBias * 4;
 
-struct FastW {
-  unsigned short w[kPkHalf];
-  float b[kPkBias + 3];
-};
-
 // Activations of R rows (bfloat16 bits)
 template <int R>
 struct FastActT {
@@ -223,13 +218,6 @@ struct FastActT {
 };
 using FastAct = FastActT<kRows>;
 
-__device__ void stage_packed(const unsigned short* __restrict__ pk, FastW& W) {
-  const uint4* src = (const uint4*)pk;
-  uint4* dst = (uint4*)W.w;
-  for (int q = threadIdx.x; q < kPkHalf / 8; q += blockDim.x) dst[q] = src[q];
-  const float* bs = (const float*)(pk + kPkHalf);
-  for (int q = threadIdx.x; q < kPkBias; q += blockDim.x) W.b[q] = bs[q];
-}
 
 // acc[nt] += A(16 rows from r0, K) * Bt(64 cols, K)^T with A row-major (lda)
 // and Bt output-major (ldb), both bfloat16: one 8-byte read per operand.
@@ -251,15 +239,19 @@ __device__ inline void mm_fast(const unsigned short* A, int lda, const unsigned 
 // hidden activations (layer 3 writes a1 again).  A layer's work items are
 // (16-row strip, 16-column tile) pairs dealt to the wavefronts; each output
 // element's sum runs over K in the same k-steps whatever the split.
+// wts / bias: the packed bfloat16 weights and FP32 biases (global memory,
+// read by the MFMA operand loads directly: every workgroup shares them in
+// the caches, so no workgroup stages them).
 template <class Act>
-__device__ void forward_fast(const FastW& W, Act& A, float* xout, int nrows = Act::kR) {
+__device__ void forward_fast(const unsigned short* __restrict__ wts, const float* __restrict__ bias, Act& A,
+                             float* xout, int nrows = Act::kR) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   const int strips = nrows / 16;
   for (int l = 0; l < 3; ++l) {
     const unsigned short* in = l == 0 ? A.a0 : (l == 1 ? A.a1 : A.a2);
     unsigned short* outl = l == 1 ? A.a2 : A.a1;
-    const unsigned short* wt = W.w + (l == 0 ? kPkW1 : (l == 1 ? kPkW2 : kPkW3));
-    const float* bl = W.b + l * kH;
+    const unsigned short* wt = wts + (l == 0 ? kPkW1 : (l == 1 ? kPkW2 : kPkW3));
+    const float* bl = bias + l * kH;
     const int K = l == 0 ? kFP : kH;
     for (int item = wv; item < 4 * strips; item += nw) {
       const int r0 = (item >> 2) * 16, nt = item & 3;
@@ -276,9 +268,9 @@ __device__ void forward_fast(const FastW& W, Act& A, float* xout, int nrows = Ac
   for (int strip = wv; strip < strips; strip += nw) {
     const int r0 = strip * 16;
     f32x4 acc[1] = {f32x4{0.f, 0.f, 0.f, 0.f}};
-    mm_fast(A.a1, kH, W.w + kPkW4, kH, r0, kH, 1, acc);
+    mm_fast(A.a1, kH, wts + kPkW4, kH, r0, kH, 1, acc);
     if ((lane & 15) == 0)
-      for (int r = 0; r < 4; ++r) xout[r0 + 4 * (lane >> 4) + r] = logistic(acc[0][r] + W.b[3 * kH]);
+      for (int r = 0; r < 4; ++r) xout[r0 + 4 * (lane >> 4) + r] = logistic(acc[0][r] + bias[3 * kH]);
   }
   __syncthreads();
 }
