@@ -255,7 +255,7 @@ int bdc_set_tuning(bdc_handle_t handle, const bdc_tuning_t* tuning);
 /* Times candidate tunings on bdc_svd_batched(batch, sizes, d, e, sigma, U,
  * VT) (arguments as there; a single problem is batch = 1): one warm-up and
  * `repeats` timed solves each, with HIP events on `stream`; first the leaf
- * size (8, 12, 16, 24, 32), then the launch shapes with the best one.  Keeps the
+ * size (8, 12, 16, 20, 24, 32), then the launch shapes with the best one.  Keeps the
  * fastest in the handle and returns it in *best.  Synchronous: waits for the
  * stream.  The outputs hold the last solve's results. */
 int bdc_autotune(bdc_handle_t handle, int64_t batch, const int64_t* sizes, const double* d,

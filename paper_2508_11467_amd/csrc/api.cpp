@@ -794,7 +794,7 @@ int bdc_autotune(bdc_handle_t h, int64_t batch, const int64_t* sizes, const doub
   float best_ms = -1.0f;
   int best_leaf = keep_leaf;
   Tuning best_t = keep;
-  for (int leaf : {8, 12, 16, 24, 32}) {
+  for (int leaf : {8, 12, 16, 20, 24, 32}) {
     float ms = 0.0f;
     rc = time_one(leaf, keep, ms);
     if (rc != BDC_OK) break;
