@@ -596,7 +596,8 @@ __global__ __launch_bounds__(256) void k_lowner(const NodeDesc* __restrict__ nod
 // One wavefront per root column, four per workgroup: lane l takes rows
 // g = l, l + 64, ...; the first 256 rows stay in registers between the sums
 // of squares (wavefront reductions, no barrier) and the scaled stores,
-// longer columns are written once and rescaled in place.
+// longer columns are written once and rescaled in place.  Merges of at most
+// 64 kept values take two columns per wavefront.
 __global__ __launch_bounds__(256) void k_vectors(const NodeDesc* __restrict__ nodes, Work w) {
   const NodeDesc nd = nodes[blockIdx.x];
   const int N = w.st[nd.id].N;
@@ -606,6 +607,48 @@ __global__ __launch_bounds__(256) void k_vectors(const NodeDesc* __restrict__ no
   const double* __restrict__ zt = w.zt + vo;
   const int* __restrict__ gsurv = w.gsurv + vo;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (N > 1 && N <= 64) {
+    // one row per lane: two columns per wavefront (i and i + S), their rows'
+    // d and z~ read once and both columns' loads in flight together; each
+    // column's arithmetic is the general path's
+    const int S = gridDim.y * 4;
+    const bool act = lane < N;
+    int j = 0;
+    double dj = 0.0, zj = 0.0;
+    if (act) {
+      j = gsurv[lane];
+      dj = d[j];
+      zj = zt[j];
+    }
+    for (int i = blockIdx.y * 4 + wv; i < N; i += 2 * S) {
+      const int i2 = i + S;
+      const bool has2 = i2 < N;
+      const double ov1 = d[w.o[vo + i]], t1 = w.tau[vo + i];
+      const double ov2 = has2 ? d[w.o[vo + i2]] : 0.0, t2 = has2 ? w.tau[vo + i2] : 0.0;
+      double v1 = 0.0, u1 = 0.0, v2 = 0.0, u2 = 0.0;
+      if (act) {
+        v1 = zj / (((dj - ov1) - t1) * ((dj + ov1) + t1));  // z~_j / (d_j^2 - w_i^2)
+        u1 = (j == 0) ? -1.0 : dj * v1;
+        if (has2) {
+          v2 = zj / (((dj - ov2) - t2) * ((dj + ov2) + t2));
+          u2 = (j == 0) ? -1.0 : dj * v2;
+        }
+      }
+      const double rv1 = 1.0 / sqrt(wave_sum(v1 * v1)), ru1 = 1.0 / sqrt(wave_sum(u1 * u1));
+      const double rv2 = 1.0 / sqrt(wave_sum(v2 * v2)), ru2 = 1.0 / sqrt(wave_sum(u2 * u2));
+      if (act) {
+        const int64_t c1 = nd.mat_off + nd.r0 + (int64_t)(nd.r0 + i) * ld;
+        w.VM[c1 + lane] = v1 * rv1;
+        w.UM[c1 + lane] = u1 * ru1;
+        if (has2) {
+          const int64_t c2 = nd.mat_off + nd.r0 + (int64_t)(nd.r0 + i2) * ld;
+          w.VM[c2 + lane] = v2 * rv2;
+          w.UM[c2 + lane] = u2 * ru2;
+        }
+      }
+    }
+    return;
+  }
   for (int i = blockIdx.y * 4 + wv; i < N; i += gridDim.y * 4) {
     double* ucol = w.UM + nd.mat_off + nd.r0 + (int64_t)(nd.r0 + i) * ld;
     double* vcol = w.VM + nd.mat_off + nd.r0 + (int64_t)(nd.r0 + i) * ld;
@@ -703,7 +746,8 @@ void launch_lowner(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, 
 
 void launch_vectors(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st) {
   if (nnodes <= 0) return;
-  const int gy = grid_y(nnodes, (max_m + 3) / 4, 4096);
+  // merges of at most 64 values: two columns per wavefront
+  const int gy = grid_y(nnodes, max_m <= 64 ? (max_m + 7) / 8 : (max_m + 3) / 4, 4096);
   hipLaunchKernelGGL(k_vectors, dim3(nnodes, gy), dim3(kBlock), 0, st, nodes, w);
 }
 
