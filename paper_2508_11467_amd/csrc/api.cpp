@@ -210,13 +210,13 @@ int make_plan(bdc_handle_t h, const int64_t* sizes, int64_t batch) {
     }
     if ((co > 0 && hipMemcpy(p.dev_uprob, up.data(), sizeof(int32_t) * co, hipMemcpyHostToDevice) != hipSuccess) ||
         (to > 0 && hipMemcpy(p.dev_vprob, vp.data(), sizeof(int32_t) * to, hipMemcpyHostToDevice) != hipSuccess))
-      return BDC_ERR_HIP;
+      return free_plan(p), BDC_ERR_HIP;
   }
   if (!leaves.empty() &&
       hipMemcpy(p.dev_leaves, leaves.data(), sizeof(LeafDesc) * leaves.size(), hipMemcpyHostToDevice) != hipSuccess)
-    return BDC_ERR_HIP;
+    return free_plan(p), BDC_ERR_HIP;
   if (id > 0 && hipMemcpy(nodes_dev, p.host_nodes.data(), sizeof(NodeDesc) * id, hipMemcpyHostToDevice) != hipSuccess)
-    return BDC_ERR_HIP;
+    return free_plan(p), BDC_ERR_HIP;
   std::vector<int64_t> prob(5 * std::max<int64_t>(1, batch), 0);
   for (int64_t i = 0; i < batch; ++i) {
     prob[i] = pn[i];
@@ -226,7 +226,7 @@ int make_plan(bdc_handle_t h, const int64_t* sizes, int64_t batch) {
     prob[4 * batch + i] = ptile[i];
   }
   if (batch > 0 && hipMemcpy(p.dev_prob, prob.data(), sizeof(int64_t) * 5 * batch, hipMemcpyHostToDevice) != hipSuccess)
-    return BDC_ERR_HIP;
+    return free_plan(p), BDC_ERR_HIP;
   int off = 0;
   for (size_t hh = 1; hh < by_h.size(); ++hh) {
     Level L;
@@ -328,9 +328,11 @@ int ensure_workspace(bdc_handle_t h, int64_t tn, int64_t tn2, int nnodes) {
 // per side (U, V) the row-split left operands and the column-split right
 // operands of the top and bottom halves, each `slices` bfloat16 planes of
 // n rows x P (P >= n + 32, a multiple of 8), and an exponent per plane row.
+int64_t ozaki_stride(int64_t n) { return ((n + 32 + 7) / 8) * 8; }
+
 int ensure_ozaki(bdc_handle_t h, int64_t n) {
   const int S = h->opt.ozaki_slices;
-  const int64_t P = ((n + 32 + 7) / 8) * 8;
+  const int64_t P = ozaki_stride(n);
   const size_t plane = (size_t)n * P;
   const size_t bytes = 6 * align_up((size_t)S * plane * 2) + 6 * align_up((size_t)n * 4);
   if (h->oz_arena && h->oz_bytes >= bytes && h->w.oz.P == P && h->w.oz.S == S) return BDC_OK;
@@ -412,7 +414,10 @@ int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, do
   const bool learned = h->opt.start == BDC_START_LEARNED;
   w.xs = nullptr;
   w.mlp_pk = learned ? h->mlp_pk : nullptr;
-  const bool ozaki = h->opt.gemm == BDC_GEMM_OZAKI && p.nprob == 1 && h->oz_arena;
+  // split products only with slice planes laid out for this problem's size
+  // (a buffer left by an earlier, larger solve has another row stride)
+  const bool ozaki = h->opt.gemm == BDC_GEMM_OZAKI && p.nprob == 1 && h->oz_arena &&
+                     h->w.oz.P == ozaki_stride(p.sizes[0]);
   w.oz.min_n = ozaki ? h->opt.ozaki_min_n : INT32_MAX;
   w.small_n = h->tune.small_n;
   w.sec_small_n = h->tune.sec_small_n;
@@ -470,7 +475,7 @@ int solve(bdc_handle_t h, int64_t batch, const int64_t* sizes, const double* d, 
   if (rc != BDC_OK) return rc;
   rc = ensure_workspace(h, h->plan.total_n, h->plan.total_n2, h->plan.nnodes);
   if (rc != BDC_OK) return rc;
-  if (h->opt.gemm == BDC_GEMM_OZAKI && batch == 1 && sizes[0] > h->opt.ozaki_min_n) {
+  if (h->opt.gemm == BDC_GEMM_OZAKI && batch == 1 && sizes[0] >= h->opt.ozaki_min_n) {
     rc = ensure_ozaki(h, sizes[0]);
     if (rc != BDC_OK) return rc;
   }

@@ -133,7 +133,7 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafDesc* __restrict__ leaves
     }
   }
 
-  const int max_steps = w.max_leaf_sweeps * (m > 0 ? m : 1) + 4 * m;
+  const int max_steps = w.max_leaf_sweeps * (m > 0 ? m : 1);
   int steps = 0;
   int hi = m - 1;
   while (hi > 0) {

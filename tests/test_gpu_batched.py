@@ -1,5 +1,7 @@
 """Batched solves of uneven sizes against single solves and the oracle."""
 
+import os
+
 import numpy as np
 import pytest
 
@@ -58,7 +60,9 @@ def test_batched_matches_single_solves(solver):
 
 def test_batched_config_2000(solver):
     """2000 problems, sizes log-uniform in [32, 2048]: every problem's
-    residual and orthogonality on the GPU, and a sample against the oracle."""
+    residual and orthogonality on the GPU, and every singular value of 100
+    problems (10 from each of 10 size strata, equal width in log n) against
+    the oracle's values written by tests/golden/make_oracle_sigma.py."""
     import torch
     sizes = inputs.batch_sizes(2000, 32, 2048, inputs.seed_for(4, 0)).tolist()
     d, e = inputs.batch_uniform(sizes, inputs.seed_for(4, 1))
@@ -67,10 +71,18 @@ def test_batched_config_2000(solver):
     sig, U, VT = solver.svd_batched(sizes, dt, et)
     info, st = solver.info()
     assert info == 0
+    gdir = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sample = np.load(os.path.join(gdir, "batch2000_sample_idx.npy"), allow_pickle=False).tolist()
+    ref_all = np.load(os.path.join(gdir, "oracle_sigma_batch2000_sample.npy"), allow_pickle=False)
+    assert len(sample) >= 100 and ref_all.shape[0] == sum(sizes[i] for i in sample)
+    ref_at = {}
+    ro = 0
+    for i in sample:
+        ref_at[i] = ref_all[ro:ro + sizes[i]]
+        ro += sizes[i]
+    sig_h = sig.cpu().numpy()
     off = mo = 0
-    worst_res = worst_orth = 0.0
-    rng = np.random.default_rng(5)
-    sample = set(rng.choice(len(sizes), 4, replace=False).tolist())
+    worst_res = worst_orth = worst_sig = 0.0
     for p, n in enumerate(sizes):
         s = sig[off:off + n]
         u = U[mo:mo + n * n].view(n, n).T
@@ -89,11 +101,15 @@ def test_batched_config_2000(solver):
                    float(torch.max(torch.abs(v @ v.T.contiguous() - I))))
         worst_res = max(worst_res, res)
         worst_orth = max(worst_orth, orth)
-        if p in sample:
-            ref, _, _ = oracle.bdsdc(d[off:off + n], e[off:off + n - 1])
-            assert np.max(np.abs(s.cpu().numpy() - ref)) <= 1e-13 * ref[0]
+        if p in ref_at:
+            ref = ref_at[p]
+            err = float(np.max(np.abs(sig_h[off:off + n] - ref)) / ref[0])
+            worst_sig = max(worst_sig, err)
+            assert err <= 1e-13, (p, n, err)
         off += n
         mo += n * n
+    print(f"batch2000: worst residual {worst_res:.2e}, orthogonality {worst_orth:.2e}, "
+          f"sigma vs oracle (100 problems) {worst_sig:.2e}", flush=True)
     assert worst_res <= 1e-12 and worst_orth <= 1e-12
 
 
