@@ -58,9 +58,14 @@ enum {
 /* Arithmetic of the vector-update products (options.gemm). */
 enum {
   BDC_GEMM_FP64 = 0, /* FP64 matrix cores (the paper's FP64 products) */
-  BDC_GEMM_OZAKI = 1 /* split precision: bfloat16 digit slices on the bfloat16 matrix
-                        cores, FP32 accumulation, FP64 combination (single-problem
-                        solves; batched solves keep FP64) */
+  BDC_GEMM_OZAKI = 1, /* split precision: bfloat16 digit slices on the bfloat16 matrix
+                         cores, FP32 accumulation, FP64 combination (single-problem
+                         solves; batched solves keep FP64) */
+  BDC_GEMM_CRT = 2    /* split precision: the integer product of the power-of-two
+                         scaled operands formed exactly from int8 residues modulo
+                         crt_moduli coprime moduli on the int8 matrix cores (int32
+                         accumulation) and rebuilt by the Chinese remainder theorem
+                         (single-problem solves; batched solves keep FP64) */
 };
 
 /* Size of the learned-start network: 19 features -> 64 -> 64 -> 64 -> 1. */
@@ -87,7 +92,11 @@ typedef struct {
                                  leaves about 2^-46, which at n = 16384 exceeds a
                                  1e-12 residual) */
   int ozaki_min_n;            /* merges with at least this many kept values use the
-                                 split products, >= 128 (default 256); smaller ones FP64 */
+                                 split products (either form), >= 128 (default 256);
+                                 smaller ones FP64 */
+  int crt_moduli;             /* moduli of BDC_GEMM_CRT, 13..16 (default 16: operands
+                                 rounded at 2^-54 of each row's / column's largest
+                                 entry for products up to 16384 deep) */
 } bdc_options_t;
 
 void bdc_default_options(bdc_options_t* opt);
@@ -145,6 +154,8 @@ typedef struct {
   double leaf_flops;           /* flops of the rotations applied by the leaf solves */
   double gather_bytes;         /* bytes moved gathering the kept columns (read + write) */
   int64_t final_read_elems;    /* nonzero-support entries read to write U and V^T */
+  int64_t split_merges;        /* merges whose update products took the split form */
+  double split_flops;          /* their share of update_flops */
 } bdc_stats_t;
 
 int bdc_get_info(bdc_handle_t handle, int64_t* info, bdc_stats_t* stats);
@@ -310,6 +321,20 @@ int bdc_set_harvest(bdc_handle_t handle, float* X, float* y, int32_t* tag, int64
  * weights) and combined in FP64. */
 int bdc_step_gemm_ozaki(bdc_handle_t handle, int slices, int M, int N, int K, const double* A, int lda,
                         const double* B, int ldb, double* C, int ldc, bdc_stream_t stream);
+
+/* C (M x N, ldc) = A (M x K, lda) * B (K x N, ldb), column-major FP64, on
+ * the int8 matrix cores through the Chinese remainder theorem (the
+ * integer-modular emulation known as Ozaki scheme II): every row of A and
+ * column of B is scaled by a power of two and rounded to an integer; the
+ * integer product is formed exactly from its residues modulo `moduli`
+ * (13..16) pairwise coprime odd moduli <= 255, each an int8 x int8 -> int32
+ * product, and rebuilt by Garner's mixed-radix algorithm.  The scale is the
+ * largest one for which the rebuilt product is exact (K <= 2^20), so the
+ * error comes only from rounding A and B at about 2^-beta of each row's /
+ * column's largest entry, beta = floor((log2 prod m - 1 - log2 K) / 2)
+ * (54 with 16 moduli and K = 16384), plus the final rounding to FP64. */
+int bdc_step_gemm_crt(bdc_handle_t handle, int moduli, int M, int N, int K, const double* A, int lda,
+                      const double* B, int ldb, double* C, int ldc, bdc_stream_t stream);
 
 const char* bdc_status_string(int status);
 

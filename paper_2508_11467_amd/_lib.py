@@ -20,6 +20,7 @@ BDC_START_PLAIN = 0
 BDC_START_LEARNED = 1
 BDC_GEMM_FP64 = 0
 BDC_GEMM_OZAKI = 1
+BDC_GEMM_CRT = 2
 MLP_FEATURES = 19
 MLP_PARAMS = 19 * 64 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 + 1
 
@@ -42,6 +43,7 @@ class Options(ctypes.Structure):
         ("gemm", c_int),
         ("ozaki_slices", c_int),
         ("ozaki_min_n", c_int),
+        ("crt_moduli", c_int),
     ]
 
 
@@ -61,6 +63,8 @@ class Stats(ctypes.Structure):
         ("leaf_flops", c_dbl),
         ("gather_bytes", c_dbl),
         ("final_read_elems", c_i64),
+        ("split_merges", c_i64),
+        ("split_flops", c_dbl),
     ]
 
     def as_dict(self) -> dict:
@@ -107,6 +111,7 @@ SIGNATURES = {
     "bdc_mlp_train": (c_int, [c_vp, c_vp, c_vp, c_vp, c_i64, c_i64, ctypes.c_float, c_vp, c_vp]),
     "bdc_set_harvest": (c_int, [c_vp, c_vp, c_vp, c_vp, c_i64, c_vp]),
     "bdc_step_gemm_ozaki": (c_int, [c_vp, c_int, c_int, c_int, c_int, c_vp, c_int, c_vp, c_int, c_vp, c_int, c_vp]),
+    "bdc_step_gemm_crt": (c_int, [c_vp, c_int, c_int, c_int, c_int, c_vp, c_int, c_vp, c_int, c_vp, c_int, c_vp]),
     "bdc_get_tuning": (c_int, [c_vp, ctypes.POINTER(Tuning)]),
     "bdc_set_tuning": (c_int, [c_vp, ctypes.POINTER(Tuning)]),
     "bdc_autotune": (c_int, [c_vp, c_i64, ctypes.POINTER(c_i64), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_int,

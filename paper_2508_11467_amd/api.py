@@ -28,12 +28,14 @@ class Solver:
     def __init__(self, device: int | torch.device = 0, leaf_size: int = 32, max_secular_iters: int = 64,
                  max_leaf_sweeps: int = 40, workspace_cap_bytes: int = 0, timing: bool = False,
                  use_graph: bool = True, start: str = "plain", mlp_params=None, gemm: str = "fp64",
-                 ozaki_slices: int = 7, ozaki_min_n: int = 256):
+                 ozaki_slices: int = 7, ozaki_min_n: int = 256, crt_moduli: int = 16):
         """start: "plain" (midpoint) or "learned" (the MLP's proposal; the
         parameters come from ``mlp_params`` (host float32 vector) or, when
         that is None, from the network file shipped with the package).
-        gemm: "fp64" or "ozaki" (split-precision update products for merges
-        with at least ``ozaki_min_n`` kept values, single-problem solves)."""
+        gemm: "fp64", "ozaki" (bfloat16-slice split products) or "crt" (int8
+        residue split products with ``crt_moduli`` moduli), the split forms
+        for merges with at least ``ozaki_min_n`` kept values in
+        single-problem solves."""
         self.lib = _lib.load()
         dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         if dev.type != "cuda":
@@ -50,11 +52,13 @@ class Solver:
         if start not in ("plain", "learned"):
             raise ValueError("start must be 'plain' or 'learned'")
         opt.start = _lib.BDC_START_LEARNED if start == "learned" else _lib.BDC_START_PLAIN
-        if gemm not in ("fp64", "ozaki"):
-            raise ValueError("gemm must be 'fp64' or 'ozaki'")
-        opt.gemm = _lib.BDC_GEMM_OZAKI if gemm == "ozaki" else _lib.BDC_GEMM_FP64
+        gemms = {"fp64": _lib.BDC_GEMM_FP64, "ozaki": _lib.BDC_GEMM_OZAKI, "crt": _lib.BDC_GEMM_CRT}
+        if gemm not in gemms:
+            raise ValueError("gemm must be 'fp64', 'ozaki' or 'crt'")
+        opt.gemm = gemms[gemm]
         opt.ozaki_slices = ozaki_slices
         opt.ozaki_min_n = ozaki_min_n
+        opt.crt_moduli = crt_moduli
         self.options = opt
         h = ctypes.c_void_p()
         check("bdc_create", self.lib.bdc_create(ctypes.byref(h), self.device.index, ctypes.byref(opt)))
@@ -336,6 +340,19 @@ class Solver:
             self._stream()))
         return C.T
 
+
+    def step_gemm_crt(self, A: torch.Tensor, B: torch.Tensor, moduli: int = 16) -> torch.Tensor:
+        """C = A @ B through the int8 residue (Chinese remainder) kernels."""
+        M, K = A.shape
+        K2, N = B.shape
+        assert K == K2
+        Ac = A.T.contiguous()
+        Bc = B.T.contiguous()
+        C = torch.empty((N, M), dtype=torch.float64, device=self.device)
+        check("bdc_step_gemm_crt", self.lib.bdc_step_gemm_crt(
+            self.handle, moduli, M, N, K, _ptr(Ac), max(1, M), _ptr(Bc), max(1, K), _ptr(C), max(1, M),
+            self._stream()))
+        return C.T
 
 _DEFAULT: dict = {}
 

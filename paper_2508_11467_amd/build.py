@@ -25,6 +25,7 @@ SOURCES = {
     "k_update.hip": [],
     "k_mlp.hip": [],
     "k_ozaki.hip": [],
+    "k_crt.hip": [],
     "api.cpp": [],
     "api_steps.cpp": [],
 }

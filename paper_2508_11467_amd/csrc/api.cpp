@@ -20,6 +20,7 @@
 
 #include "bdc.h"
 #include "bdc_internal.h"
+#include "crt.h"
 
 using namespace bdc;
 
@@ -29,10 +30,11 @@ constexpr uint32_t kMagic = 0xBDC05EEDu;
 
 enum Kind {
   kReset = 0, kLeaf, kPrep, kRotate, kGather, kStart, kSecular, kLowner, kVectors, kOrder, kUpdate, kUpdateOz,
-  kFinal, kKinds
+  kUpdateCrt, kFinal, kKinds
 };
 const char* kKindNames[kKinds] = {"reset", "leaf", "deflate", "rotate", "gather", "start", "secular",
-                                  "lowner", "vectors", "order", "update_gemm", "update_ozaki", "final"};
+                                  "lowner", "vectors", "order", "update_gemm", "update_ozaki", "update_crt",
+                                  "final"};
 
 struct Level {
   int nnodes = 0;
@@ -90,6 +92,10 @@ struct bdc_handle_s {
   // per-workgroup gradient partials of a training step, and harvest buffers
   void* oz_arena = nullptr;  // split-precision slice planes (single-problem solves)
   size_t oz_bytes = 0;
+  void* crt_arena = nullptr;  // int8 residue planes (single-problem solves)
+  size_t crt_bytes = 0;
+  int64_t crt_n = -1;         // problem size the residue planes are laid out for
+  int last_split_min_n = INT32_MAX;  // split threshold of the last solve (statistics)
   float* mlp = nullptr;  // params | m | v
   unsigned short* mlp_pk = nullptr;  // inference layout, repacked at each learned solve
   int adam_t = 0;
@@ -370,6 +376,61 @@ int ensure_ozaki(bdc_handle_t h, int64_t n) {
   return BDC_OK;
 }
 
+// Residue planes of the int8 split products for one problem of size n: per
+// side (U, V) L planes each of the left operands ((n + 129) rows), of the
+// right operands of the top and bottom halves ((n + 128) rows), all with row
+// stride P = n rounded up to 64 bytes (the extra rows absorb the over-read of
+// the last 128-row tile), of the products ((n + 1) x (n + 1), column-major),
+// and the per-row maxima and exponents.
+int ensure_crt(bdc_handle_t h, int64_t n) {
+  const int L = h->opt.crt_moduli;
+  const int64_t P = crt_kpad((int)n);
+  const int64_t planeA = (n + 129) * P, planeB = (n + 128) * P, ldr = n + 1, planeC = ldr * (n + 1);
+  const size_t bytes = 2 * (align_up((size_t)L * planeA) + 2 * align_up((size_t)L * planeB) +
+                            align_up((size_t)L * planeC) + 3 * align_up((size_t)(n + 1) * 8) +
+                            3 * align_up((size_t)(n + 1) * 4));
+  if (h->crt_arena && h->crt_n == n && h->crt_bytes == bytes && h->w.crt.L == L) return BDC_OK;
+  if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
+  drop_graph(h);
+  if (h->crt_arena) (void)hipFree(h->crt_arena);
+  h->crt_arena = nullptr;
+  h->crt_bytes = 0;
+  h->crt_n = -1;
+  if (h->opt.workspace_cap_bytes && h->arena_bytes + bytes > h->opt.workspace_cap_bytes) return BDC_ERR_NOMEM;
+  if (hipMalloc(&h->crt_arena, bytes) != hipSuccess) {
+    h->crt_arena = nullptr;
+    return BDC_ERR_NOMEM;
+  }
+  h->crt_bytes = bytes;
+  h->crt_n = n;
+  char* b = (char*)h->crt_arena;
+  auto take = [&](size_t nbytes) {
+    char* r = b;
+    b += align_up(nbytes);
+    return (void*)r;
+  };
+  CrtWork& c = h->w.crt;
+  for (int side = 0; side < 2; ++side) {
+    c.A[side] = (int8_t*)take((size_t)L * planeA);
+    c.Bt[side] = (int8_t*)take((size_t)L * planeB);
+    c.Bb[side] = (int8_t*)take((size_t)L * planeB);
+    c.C[side] = (int8_t*)take((size_t)L * planeC);
+    c.amax[side] = (unsigned long long*)take((size_t)(n + 1) * 8);
+    c.btmax[side] = (unsigned long long*)take((size_t)(n + 1) * 8);
+    c.bbmax[side] = (unsigned long long*)take((size_t)(n + 1) * 8);
+    c.Ea[side] = (int*)take((size_t)(n + 1) * 4);
+    c.Ebt[side] = (int*)take((size_t)(n + 1) * 4);
+    c.Ebb[side] = (int*)take((size_t)(n + 1) * 4);
+  }
+  c.planeA = planeA;
+  c.planeB = planeB;
+  c.planeC = planeC;
+  c.P = (int)P;
+  c.ldr = (int)ldr;
+  c.L = L;
+  return BDC_OK;
+}
+
 hipEvent_t next_event(bdc_handle_t h) {
   if (h->pool_used == h->pool.size()) {
     hipEvent_t e;
@@ -418,7 +479,9 @@ int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, do
   // (a buffer left by an earlier, larger solve has another row stride)
   const bool ozaki = h->opt.gemm == BDC_GEMM_OZAKI && p.nprob == 1 && h->oz_arena &&
                      h->w.oz.P == ozaki_stride(p.sizes[0]);
-  w.oz.min_n = ozaki ? h->opt.ozaki_min_n : INT32_MAX;
+  const bool crt = h->opt.gemm == BDC_GEMM_CRT && p.nprob == 1 && h->crt_arena && h->crt_n == p.sizes[0];
+  w.oz.min_n = (ozaki || crt) ? h->opt.ozaki_min_n : INT32_MAX;
+  h->last_split_min_n = w.oz.min_n;
   w.small_n = h->tune.small_n;
   w.sec_small_n = h->tune.sec_small_n;
   {
@@ -447,6 +510,10 @@ int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, do
     if (ozaki && L.max_m >= w.oz.min_n) {
       Timer t(h, st, kUpdateOz);
       launch_update_ozaki(L.dev, L.nnodes, L.max_m, w, st);
+    }
+    if (crt && L.max_m >= w.oz.min_n) {
+      Timer t(h, st, kUpdateCrt);
+      launch_update_crt(L.dev, L.nnodes, L.max_m, w, st);
     }
   }
   {
@@ -477,6 +544,10 @@ int solve(bdc_handle_t h, int64_t batch, const int64_t* sizes, const double* d, 
   if (rc != BDC_OK) return rc;
   if (h->opt.gemm == BDC_GEMM_OZAKI && batch == 1 && sizes[0] >= h->opt.ozaki_min_n) {
     rc = ensure_ozaki(h, sizes[0]);
+    if (rc != BDC_OK) return rc;
+  }
+  if (h->opt.gemm == BDC_GEMM_CRT && batch == 1 && sizes[0] >= h->opt.ozaki_min_n) {
+    rc = ensure_crt(h, sizes[0]);
     if (rc != BDC_OK) return rc;
   }
   if (h->plan.total_n == 0) {
@@ -544,6 +615,7 @@ void bdc_default_options(bdc_options_t* opt) {
   opt->gemm = BDC_GEMM_FP64;
   opt->ozaki_slices = 7;
   opt->ozaki_min_n = 256;
+  opt->crt_moduli = 16;
 }
 
 int bdc_create(bdc_handle_t* handle, int device, const bdc_options_t* opt) {
@@ -556,8 +628,9 @@ int bdc_create(bdc_handle_t* handle, int device, const bdc_options_t* opt) {
   if (o.max_secular_iters < 2 || o.max_secular_iters > 64) return -3;
   if (o.max_leaf_sweeps < 1 || o.max_leaf_sweeps > 1000) return -3;
   if (o.start != BDC_START_PLAIN && o.start != BDC_START_LEARNED) return -3;
-  if (o.gemm != BDC_GEMM_FP64 && o.gemm != BDC_GEMM_OZAKI) return -3;
+  if (o.gemm != BDC_GEMM_FP64 && o.gemm != BDC_GEMM_OZAKI && o.gemm != BDC_GEMM_CRT) return -3;
   if (!oz_supported(o.ozaki_slices) || o.ozaki_min_n < 128) return -3;
+  if (!crt_supported(o.crt_moduli)) return -3;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return BDC_ERR_NO_DEVICE;
   if (device < 0 || device >= count) return BDC_ERR_NO_DEVICE;
@@ -579,6 +652,7 @@ int bdc_destroy(bdc_handle_t h) {
     free_plan(h->plan);
     if (h->arena) (void)hipFree(h->arena);
     if (h->oz_arena) (void)hipFree(h->oz_arena);
+    if (h->crt_arena) (void)hipFree(h->crt_arena);
     if (h->mlp) (void)hipFree(h->mlp);
     if (h->mlp_pk) (void)hipFree(h->mlp_pk);
     if (h->part) (void)hipFree(h->part);
@@ -662,8 +736,13 @@ int bdc_get_info(bdc_handle_t h, int64_t* info, bdc_stats_t* stats) {
       stats->deflated_close += s.nclose;
       stats->rotations += s.nrot;
       const double N = s.N, top = s.n1 + 1 + s.n2, bot = 1 + s.n2 + s.n3;
-      fl += 2.0 * N * (nd.k * top + (nd.m - nd.k) * bot);          // left vectors
-      fl += 2.0 * N * (nd.k * top + (nd.m + nd.s - nd.k) * bot);   // right vectors
+      const double f = 2.0 * N * (nd.k * top + (nd.m - nd.k) * bot) +     // left vectors
+                       2.0 * N * (nd.k * top + (nd.m + nd.s - nd.k) * bot);  // right vectors
+      fl += f;
+      if (s.N >= h->last_split_min_n) {
+        stats->split_merges += 1;
+        stats->split_flops += f;
+      }
     }
     stats->update_flops = fl;
     if (p.root_id0 >= 0) stats->root_N = sts[p.root_id0].N;

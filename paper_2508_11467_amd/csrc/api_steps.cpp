@@ -13,6 +13,7 @@
 
 #include "bdc.h"
 #include "bdc_internal.h"
+#include "crt.h"
 
 using namespace bdc;
 
@@ -295,6 +296,32 @@ int bdc_step_gemm_ozaki(bdc_handle_t h, int slices, int M, int N, int K, const d
   int* eb = t.alloc<int>(N);
   if (!t.ok) return BDC_ERR_NOMEM;
   launch_gemm_ozaki_plain(slices, M, N, K, A, lda, B, ldb, C, ldc, sa, sb, ea, eb, P, st);
+  return finish(st);
+}
+
+int bdc_step_gemm_crt(bdc_handle_t h, int moduli, int M, int N, int K, const double* A, int lda, const double* B,
+                      int ldb, double* C, int ldc, bdc_stream_t stream) {
+  int dev, msi, mls;
+  if (bdc::handle_info(h, &dev, &msi, &mls) != BDC_OK) return BDC_ERR_INVALID_HANDLE;
+  if (!crt_supported(moduli)) return -2;
+  if (M < 0) return -3;
+  if (N < 0) return -4;
+  if (K < 0 || K > (1 << 20)) return -5;
+  if (M > 0 && K > 0 && !A) return -6;
+  if (lda < std::max(1, M)) return -7;
+  if (K > 0 && N > 0 && !B) return -8;
+  if (ldb < std::max(1, K)) return -9;
+  if (M > 0 && N > 0 && !C) return -10;
+  if (ldc < std::max(1, M)) return -11;
+  if (M == 0 || N == 0) return BDC_OK;
+  Guard g(dev);
+  hipStream_t st = (hipStream_t)stream;
+  Tmp t;
+  CrtBuffers b{};
+  b.base = t.alloc<char>(crt_plain_bytes(moduli, M, N, K, nullptr));
+  if (!t.ok) return BDC_ERR_NOMEM;
+  crt_plain_bytes(moduli, M, N, K, &b);
+  launch_gemm_crt_plain(moduli, M, N, K, A, lda, B, ldb, C, ldc, b, st);
   return finish(st);
 }
 

@@ -106,6 +106,30 @@ struct OzWork {
   int min_n;      // merges with at least this many kept values use it (INT32_MAX: off)
 };
 
+// Split-precision update products on the int8 matrix cores (k_crt.hip): per
+// side (0 U, 1 V) the L residue planes of the row-scaled left operands (A,
+// plane row = the node's row), of the column-scaled right operands of the top
+// and bottom halves (Bt, Bb, plane row = the node's first column + the kept
+// value's index), both k contiguous from 0 with row stride P, and of the
+// products (C, column-major with ld ldr at the node's diagonal block); the
+// largest |entry| per plane row (bits) and the scale exponents.
+struct CrtWork {
+  int8_t* A[2];
+  int8_t* Bt[2];
+  int8_t* Bb[2];
+  int8_t* C[2];
+  unsigned long long* amax[2];
+  unsigned long long* btmax[2];
+  unsigned long long* bbmax[2];
+  int* Ea[2];
+  int* Ebt[2];
+  int* Ebb[2];
+  int64_t planeA, planeB, planeC;  // bytes per modulus plane
+  int P;                           // row stride (bytes) of the A and B planes
+  int ldr;                         // leading dimension of the C planes
+  int L;                           // moduli
+};
+
 // Device pointers of one call (passed to every kernel by value).
 struct Work {
   const double* d;  // inputs, packed per problem at vec_off
@@ -153,7 +177,9 @@ struct Work {
   int4* fin;         // final pass of a single problem: per output index, (column, lo, hi) of U then of V
   const unsigned short* mlp_pk;  // packed network for the in-kernel learned start,
                                  // or nullptr
-  OzWork oz;
+  OzWork oz;         // oz.min_n: merges with at least this many kept values take the
+                     // split products (bfloat16 slices or int8 residues)
+  CrtWork crt;
   int small_n;        // update products of merges with N <= small_n use 64 x 64 tiles
   int sec_small_n;    // secular problems with N <= sec_small_n use the lanes-per-root kernel
   int* tile_off64;    // flattened tile schedule of a level (nnodes + 1 each)
@@ -225,6 +251,8 @@ void launch_update_ozaki(const NodeDesc* nodes, int nnodes, int max_m, const Wor
 void launch_gemm_ozaki_plain(int slices, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                              double* C, int ldc, unsigned short* sa, unsigned short* sb, int* ea, int* eb, int64_t P,
                              hipStream_t st);
+
+void launch_update_crt(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
 
 void launch_gemm_plain(int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                        double* C, int ldc, hipStream_t st);
