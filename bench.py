@@ -5,18 +5,29 @@ Default workload: n = 16384 upper bidiagonal with d, e iid N(0, 1) (fixed
 seed), sigma + full U and V^T.  A step is one whole solve with the inputs
 already resident in HBM.  Prints one JSON line.
 
-  value     nominal GFLOP/s = (8/3) n^3 / time  (the paper's convention,
-            Section 4.2.2; deflation removes most of that work, so the
-            executed vector-update flops are reported beside it)
+  value     executed GFLOP/s: the FP64 work the solve actually performs
+            (vector-update products + secular evaluations at 12 flops per
+            pole term + leaf rotations) / time.  The paper's convention,
+            (8/3) n^3 / time (Section 4.2.2), is reported beside it as
+            nominal_gflops_paper_convention: deflation removes most of that
+            work, so it is a rate of the nominal problem, not of executed
+            arithmetic.
+  accuracy  residual, orthogonality, and Section 5.1's E_sigma (against the
+            oracle's singular values stored by tests/golden/) and E_svd
   roofline  the kernel kind with the largest share of the timed region,
             measured with HIP events on the solve's stream, against its
             bound (MFMA FP64 peak, HBM bandwidth, or FP64 vector ALU)
-  cpu_baseline  the CPU oracle timed on a bounded sample of the same
-            workload family on this host
-  learned   the same workload with the learned secular start (the MLP's
-            proposal as each root's first point): time and secular
-            evaluations per root next to the plain start's; config5 repeats
-            the comparison at n = 32768 (d, e iid N(0,1))
+  split     the headline with split-precision update products (int8 residue
+            form); merges that took them are counted (none at this workload:
+            the root keeps 55 values)
+  learned   the headline with the learned secular start; config5 repeats the
+            plain/learned comparison at n = 32768
+  control   n = 16384, d = e = 1 (almost no deflation, update-product bound):
+            FP64 matrix-core products against the int8 residue products, time,
+            product rate against the roofline, and accuracy against the closed
+            form
+  batch2000 2000 bidiagonals of uneven sizes in one call
+  cpu_baseline  the CPU oracle timed on the headline workload on this host
 """
 
 from __future__ import annotations
@@ -35,6 +46,7 @@ if ROOT not in sys.path:
 PEAK_FP64_MFMA = 78.6e12     # dense FP64 matrix, FLOP/s
 PEAK_FP64_VALU = 78.6e12     # FP64 vector, FLOP/s
 PEAK_HBM = 8.0e12            # bytes/s
+PEAK_INT8_MFMA = 5.0e15      # dense int8 matrix, OP/s
 METRIC = "bidiag SVD+vectors time & GFLOP/s at n=16384 FP64; secular iters/root, learned vs plain"
 
 WORKLOADS = {
@@ -56,7 +68,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="n16384_normal", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=4096, help="size of the CPU oracle sample")
+    ap.add_argument("--cpu-n", type=int, default=16384, help="size of the CPU oracle run (N(0,1) bidiagonal)")
+    ap.add_argument("--no-control", action="store_true", help="skip the d = e = 1 control (FP64 vs split)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 2000-problem batch")
+    ap.add_argument("--no-autotune", action="store_true", help="time the default launch tuning only")
     ap.add_argument("--no-config5", action="store_true", help="skip the n = 32768 plain/learned comparison")
     ap.add_argument("--no-ozaki", action="store_true", help="skip the split-precision comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start comparison")
@@ -164,15 +179,16 @@ def plain_vs_learned(d, e, steps: int, warmup: int, tuning=None) -> dict:
     out = (torch.empty(n, dtype=torch.float64, device=dev), torch.empty((n, n), dtype=torch.float64, device=dev),
            torch.empty((n, n), dtype=torch.float64, device=dev))
     res = {}
-    for start in ("plain", "learned"):
-        s = Solver(0, start=start)
+    for name, kw in (("plain", {}), ("learned", {"start": "learned"}),
+                     ("learned_every_merge", {"start": "learned", "learned_min_n": 0})):
+        s = Solver(0, **kw)
         if tuning:
             s.set_tuning(**tuning)
         ms = time_solver(s, dt, et, out, steps, warmup)
         info, st = s.info()
         s.close()
-        res[start] = {"ms_per_step": ms, "secular_iters_per_root": st["secular_evals"] / max(st["roots"], 1),
-                      "roots": st["roots"], "info": info}
+        res[name] = {"ms_per_step": ms, "secular_iters_per_root": st["secular_evals"] / max(st["roots"], 1),
+                     "roots": st["roots"], "info": info}
     del out
     torch.cuda.empty_cache()
     return res
@@ -320,8 +336,10 @@ def bench_sigma_laws(args, desc, n):
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(n: int):
-    import numpy as np  # noqa: F401
+def cpu_baseline(n: int, executed_flops: float | None):
+    """The oracle on the headline's N(0,1) bidiagonal of size n, one run, all
+    host cores visible to the process (BLAS threads)."""
+    import resource
 
     import oracle
     from paper_2508_11467_amd import inputs
@@ -331,15 +349,180 @@ def cpu_baseline(n: int):
     oracle.bdsdc(d, e)
     t = time.perf_counter() - t0
     cores = len(os.sched_getaffinity(0))
-    return {
-        "value": (8.0 / 3.0) * n ** 3 / t / 1e9,
+    ram = os.sysconf("SC_PAGE_SIZE") * os.sysconf("SC_PHYS_PAGES") / 2 ** 30
+    peak = resource.getrusage(resource.RUSAGE_SELF).ru_maxrss / 2 ** 20
+    out = {
         "unit": "GFLOP/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": f"one n={n} N(0,1) bidiagonal (same generator) solved by the NumPy oracle in {t:.2f} s; "
-                  f"nominal (8/3)n^3 flops",
+        "sample": f"the headline workload itself: one n={n} N(0,1) bidiagonal (same seed) solved once by the "
+                  f"NumPy oracle in {t:.2f} s with {cores} BLAS threads; host RAM {ram:.0f} GiB, process peak "
+                  f"RSS {peak:.1f} GiB",
         "seconds": t,
+        "ms_per_step": t * 1e3,
+        "nominal_gflops_paper_convention": (8.0 / 3.0) * n ** 3 / t / 1e9,
     }
+    # the same executed work as the GPU solve (deflation is bit-exact, so the
+    # products, secular terms and leaf rotations are the same on both sides)
+    out["value"] = executed_flops / t / 1e9 if executed_flops else out["nominal_gflops_paper_convention"]
+    return out
+
+
+def executed_flops(stats: dict) -> float:
+    """FP64 work a solve performs: update products (counted per merge from the
+    kept sizes), secular evaluations (about 12 flops per pole term) and the
+    leaves' rotations (counted on the device)."""
+    return stats["update_flops"] + 12.0 * stats["secular_terms"] + stats["leaf_flops"]
+
+
+def timed_kinds(solver_kw: dict, tuning: dict | None, dt, et, out, steps: int) -> tuple[dict, float, dict]:
+    """Kernel-by-kernel run (every launch bracketed by HIP events on the
+    solve's stream): {kind: (total ms, launches)}, ms per step, stats."""
+    import torch
+
+    from paper_2508_11467_amd.api import Solver
+    s = Solver(0, timing=True, **solver_kw)
+    if tuning:
+        s.set_tuning(**tuning)
+    s.svd(dt, et, out=out)
+    torch.cuda.synchronize()
+    s.clear_timing()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        s.svd(dt, et, out=out)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    timing = s.timing()
+    info, stats = s.info()
+    s.close()
+    return {k: v for k, v in timing.items() if v[1] > 0}, ms, stats
+
+
+def golden_sigma(name: str):
+    """Singular values stored by tests/golden/make_oracle_sigma.py (written by
+    the oracle), or None."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", name)
+    return np.load(path, allow_pickle=False) if os.path.exists(path) else None
+
+
+def sigma_errors(sig, ref) -> dict:
+    """max |sigma - ref| / sigma_1 and Section 5.1's E_sigma = ||S1 - S2||_F / n."""
+    import numpy as np
+    s = sig.cpu().numpy()
+    return {"sigma_max_err_rel": float(np.max(np.abs(s - ref)) / ref[0]),
+            "E_sigma": float(np.linalg.norm(s - ref) / len(ref))}
+
+
+def control_leg(steps: int, warmup: int) -> dict:
+    """n = 16384, d = e = 1: FP64 matrix-core products against the int8
+    residue products (the split form), each timed as a caller runs it and
+    kernel by kernel, with the product rate against its roofline and all
+    singular values against the closed form."""
+    import numpy as np
+    import torch
+
+    from paper_2508_11467_amd import inputs
+    from paper_2508_11467_amd.api import Solver
+    n = 16384
+    d, e = inputs.workload("n16384_ones")
+    dev = torch.device("cuda:0")
+    dt, et = torch.from_numpy(d).to(dev), torch.from_numpy(e).to(dev)
+    out = (torch.empty(n, dtype=torch.float64, device=dev), torch.empty((n, n), dtype=torch.float64, device=dev),
+           torch.empty((n, n), dtype=torch.float64, device=dev))
+    ref = 2.0 * np.cos(np.arange(1, n + 1) * math.pi / (2 * n + 1))
+    res = {"workload": WORKLOADS["n16384_ones"][0]}
+    for form, kw in (("fp64", {}), ("split_int8_crt", {"gemm": "crt"})):
+        s = Solver(0, **kw)
+        ms = time_solver(s, dt, et, out, steps, warmup)
+        info, st = s.info()
+        s.close()
+        kinds, ms_k, st_k = timed_kinds(kw, None, dt, et, out, 1)
+        leg = {"ms_per_step": ms, "info": info, "ms_per_step_kernel_by_kernel": ms_k,
+               "kernel_ms_per_step": {k: v[0] for k, v in sorted(kinds.items())},
+               "update_flops": st["update_flops"], "split_merges": st["split_merges"]}
+        fp64_flops = st["update_flops"] - st["split_flops"]
+        if "update_gemm" in kinds and fp64_flops > 0:
+            t = kinds["update_gemm"][0] * 1e-3
+            leg["fp64_update"] = {"flops": fp64_flops, "ms": t * 1e3, "tflops": fp64_flops / t / 1e12,
+                                  "frac_of_fp64_mfma_peak": fp64_flops / t / PEAK_FP64_MFMA}
+        if "update_crt" in kinds and st["split_flops"] > 0:
+            t = kinds["update_crt"][0] * 1e-3
+            L = 16
+            leg["split_update"] = {
+                "flops_fp64_equivalent": st["split_flops"], "ms": t * 1e3,
+                "fp64_equivalent_tflops": st["split_flops"] / t / 1e12,
+                "moduli": L,
+                "int8_ops": L * st["split_flops"],
+                "frac_of_int8_mfma_peak": L * st["split_flops"] / t / PEAK_INT8_MFMA,
+                "note": "times the whole split stage (scaling, residues, int8 products, Garner rebuild)"}
+        leg.update(sigma_errors(out[0], ref))
+        leg.update(accuracy(d, e, out[0], out[1].T, out[2].T))
+        res[form] = leg
+    res["split_speedup"] = res["fp64"]["ms_per_step"] / res["split_int8_crt"]["ms_per_step"]
+    del out
+    torch.cuda.empty_cache()
+    return res
+
+
+def batch_leg(steps: int, warmup: int) -> dict:
+    """2000 bidiagonals, sizes log-uniform in [32, 2048]: time per batched
+    call with default and autotuned launches, the update products' rate and
+    every problem's residual and orthogonality."""
+    import torch
+
+    from paper_2508_11467_amd import inputs
+    from paper_2508_11467_amd.api import Solver
+    sizes = inputs.batch_sizes(2000, 32, 2048, inputs.seed_for(4, 0)).tolist()
+    d, e = inputs.batch_uniform(sizes, inputs.seed_for(4, 1))
+    dev = torch.device("cuda:0")
+    dt, et = torch.from_numpy(d).to(dev), torch.from_numpy(e).to(dev)
+    tot, tot2 = sum(sizes), sum(x * x for x in sizes)
+    out = (torch.empty(tot, dtype=torch.float64, device=dev), torch.empty(tot2, dtype=torch.float64, device=dev),
+           torch.empty(tot2, dtype=torch.float64, device=dev))
+
+    def run(solver, k, w):
+        for _ in range(w):
+            solver.svd_batched(sizes, dt, et, out=out)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(k):
+            solver.svd_batched(sizes, dt, et, out=out)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k
+
+    s = Solver(0)
+    ms_default = run(s, steps, warmup)
+    tuned = s.autotune(sizes, dt, et, out=out, repeats=2)
+    ms = run(s, steps, warmup)
+    info, st = s.info()
+    s.close()
+    ts = Solver(0, timing=True)
+    ts.set_tuning(**tuned)
+    run(ts, 1, 1)
+    ts.clear_timing()
+    ms_k = run(ts, steps, 0)
+    kinds = {k: v for k, v in ts.timing().items() if v[1] > 0}
+    ts.close()
+    upd = kinds.get("update_gemm", (0.0, 0))[0] / steps * 1e-3
+    res = {"workload": WORKLOADS["batch2000"][0], "ms_per_step": ms, "ms_per_step_default_options": ms_default,
+           "tuning": {k: v for k, v in tuned.items() if k != "ms"}, "info": info,
+           "ms_per_step_kernel_by_kernel": ms_k,
+           "kernel_ms_per_step": {k: v[0] / steps for k, v in sorted(kinds.items())},
+           "update_flops": st["update_flops"],
+           "update_tflops": st["update_flops"] / upd / 1e12 if upd > 0 else None,
+           "update_frac_of_fp64_mfma_peak": st["update_flops"] / upd / PEAK_FP64_MFMA if upd > 0 else None,
+           "nominal_gflops_paper_convention": sum((8.0 / 3.0) * x ** 3 for x in sizes) / (ms * 1e-3) / 1e9,
+           **batch_checks(sizes, d, e, *out)}
+    del out
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -348,7 +531,7 @@ def main():
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); "
               "this solver has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
+    import numpy as np  # noqa: F401
     import torch
 
     from paper_2508_11467_amd import inputs
@@ -365,6 +548,7 @@ def main():
         return bench_batched(args, desc)
     if args.workload == "sigma_laws":
         return bench_sigma_laws(args, desc, n)
+    headline = args.workload == "n16384_normal"
     d, e = inputs.workload(args.workload)
     dev = torch.device("cuda:0")
     dt = torch.from_numpy(d).to(dev)
@@ -372,74 +556,89 @@ def main():
     sig = torch.empty(n, dtype=torch.float64, device=dev)
     ub = torch.empty((n, n), dtype=torch.float64, device=dev)
     vb = torch.empty((n, n), dtype=torch.float64, device=dev)
+    out = (sig, ub, vb)
     # timed region 1: the solve as a caller runs it (graph replay), with the
     # default options and after the library's autotuner has picked the leaf
     # size and launch shapes for this workload (outside the timed region)
     solver = Solver(0)
-    ms_default = time_solver(solver, dt, et, (sig, ub, vb), args.steps, args.warmup)
-    tuned = solver.autotune([n], dt, et, out=(sig, ub, vb), repeats=2)
-    tuning = {k: v for k, v in tuned.items() if k != "ms"}
-    ms = time_solver(solver, dt, et, (sig, ub, vb), args.steps, args.warmup)
+    ms_default = time_solver(solver, dt, et, out, args.steps, args.warmup)
+    tuning = None
+    if not args.no_autotune:
+        tuned = solver.autotune([n], dt, et, out=out, repeats=2)
+        tuning = {k: v for k, v in tuned.items() if k != "ms"}
+    ms = time_solver(solver, dt, et, out, args.steps, args.warmup)
     info, stats = solver.info()
+    cur_tuning = solver.tuning()
     solver.close()
 
     def tuned_solver(**kw):
         s = Solver(0, **kw)
-        s.set_tuning(**tuning)
+        if tuning:
+            s.set_tuning(**tuning)
         return s
 
     # timed region 2: the same steps launched kernel by kernel, each launch
     # bracketed by HIP events on the solve's stream (per-kernel durations)
-    tsolver = tuned_solver(timing=True)
-    tsolver.svd(dt, et, out=(sig, ub, vb))
-    torch.cuda.synchronize()
-    tsolver.clear_timing()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(args.steps):
-        tsolver.svd(dt, et, out=(sig, ub, vb))
-    stop.record()
-    torch.cuda.synchronize()
-    ms_events = start.elapsed_time(stop) / args.steps
-    timing = tsolver.timing()
-    tsolver.close()
+    kinds, ms_events, _ = timed_kinds({}, tuning, dt, et, out, args.steps)
 
-    sig_fp64 = sig.clone()
     acc_fp64 = accuracy(d, e, sig, ub.T, vb.T)
+    ref = golden_sigma("oracle_sigma_n16384_normal.npy") if headline else None
+    if ref is not None:
+        acc_fp64.update(sigma_errors(sig, ref))
+        acc_fp64["sigma_reference"] = "oracle (tests/golden/oracle_sigma_n16384_normal.npy)"
+    acc_fp64["E_svd"] = acc_fp64["residual"]
 
-    # the same solves with split-precision update products
-    ozaki = None
+    # the same solves with split-precision update products (int8 residues)
+    split = None
     if not args.no_ozaki:
-        osv = tuned_solver(gemm="ozaki")
-        ms_oz = time_solver(osv, dt, et, (sig, ub, vb), args.steps, args.warmup)
-        info_o, _ = osv.info()
+        osv = tuned_solver(gemm="crt")
+        ms_sp = time_solver(osv, dt, et, out, args.steps, args.warmup)
+        info_s, st_s = osv.info()
         osv.close()
-        ozaki = {"ms_per_step": ms_oz, "value": (8.0 / 3.0) * n ** 3 / (ms_oz * 1e-3) / 1e9, "slices": int(osv.options.ozaki_slices),
-                 "min_kept_values": 256, "info": info_o,
-                 "sigma_max_rel_diff_vs_fp64": float(torch.max(torch.abs(sig - sig_fp64)) / sig_fp64[0]),
-                 **accuracy(d, e, sig, ub.T, vb.T)}
+        split = {"form": "int8 residues, Chinese remainder rebuild", "ms_per_step": ms_sp, "info": info_s,
+                 "split_merges": st_s["split_merges"], "min_kept_values": 256,
+                 "engaged": st_s["split_merges"] > 0}
+        if st_s["split_merges"] == 0:
+            split["note"] = (f"no merge of this workload keeps 256 values (root keeps {st_s['root_N']}), so the "
+                             "split products never run here; the d = e = 1 control below measures them")
+        if ref is not None:
+            split.update(sigma_errors(sig, ref))
+        split.update(accuracy(d, e, sig, ub.T, vb.T))
 
     # the same solves with the learned start
+    learned = None
     if not args.no_learned:
+        # every merge (the network's proposals for all roots: the iteration
+        # count the metric compares), then the library's default, which runs
+        # the network only on merges of at least learned_min_n kept values
+        lu = tuned_solver(start="learned", learned_min_n=0)
+        ms_every = time_solver(lu, dt, et, out, args.steps, args.warmup)
+        info_u, stats_u = lu.info()
+        lu.close()
+        learned = {"secular_iters_per_root": stats_u["secular_evals"] / max(stats_u["roots"], 1),
+                   "secular_iters_per_root_plain": stats["secular_evals"] / max(stats["roots"], 1),
+                   "ms_per_step_every_merge": ms_every, "roots": stats_u["roots"], "info": info_u}
+        if ref is not None:
+            learned.update(sigma_errors(sig, ref))
+        learned.update(accuracy(d, e, sig, ub.T, vb.T))
         ls = tuned_solver(start="learned")
-        ms_learned = time_solver(ls, dt, et, (sig, ub, vb), args.steps, args.warmup)
+        learned["ms_per_step"] = time_solver(ls, dt, et, out, args.steps, args.warmup)
         info_l, stats_l = ls.info()
+        learned["learned_min_n"] = int(ls.options.learned_min_n)
+        learned["secular_iters_per_root_gated"] = stats_l["secular_evals"] / max(stats_l["roots"], 1)
         ls.close()
 
+    flops = executed_flops(stats)
     nominal = (8.0 / 3.0) * n ** 3
-    value = nominal / (ms * 1e-3) / 1e9
+    value = flops / (ms * 1e-3) / 1e9
 
     # dominant kernel kind over the timed region
-    kinds = {k: v for k, v in timing.items() if v[1] > 0}
     dom = max(kinds, key=lambda k: kinds[k][0])
     tot_ms, launches = kinds[dom]
-    per_launch_launches = launches / args.steps
-    bound, work, unit, peak = kernel_work(dom, stats, float(n) * n, per_launch_launches)
+    bound, work, unit, peak = kernel_work(dom, stats, float(n) * n, launches / args.steps)
     avg_s = tot_ms * 1e-3 / launches
     achieved = work / avg_s
     scale = 1e9 if unit == "GB/s" else 1e12
-    traffic = measured_traffic(args.workload, dom)
     roofline = {
         "bound": bound,
         "kernel": dom,
@@ -448,7 +647,7 @@ def main():
         "peak": peak / scale,
         "unit": unit,
         "frac": achieved / peak,
-        "traffic": traffic,
+        "traffic": measured_traffic(args.workload, dom),
         "avg_launch_ms": avg_s * 1e3,
         "share_of_step": tot_ms / args.steps / ms_events,
     }
@@ -466,12 +665,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "n": n, "leaf_size": tuning["leaf_size"], "secular_start": "plain",
-                   "tuning": tuning},
-        "ms_per_step_default_options": ms_default,
-        "executed_update_gflops": stats["update_flops"] / (ms * 1e-3) / 1e9,
-        "update_flops": stats["update_flops"],
+        "config": {"workload": desc, "n": n, "leaf_size": cur_tuning["leaf_size"], "secular_start": "plain",
+                   "tuning": cur_tuning},
+        "value_definition": "executed FP64 flops per solve (update products + 12 per secular pole term + leaf "
+                            "rotations) / ms_per_step",
+        "executed_flops": flops,
+        "nominal_gflops_paper_convention": nominal / (ms * 1e-3) / 1e9,
         "nominal_flops": nominal,
+        "ms_per_step_default_options": ms_default,
+        "update_flops": stats["update_flops"],
+        "executed_update_gflops": stats["update_flops"] / (ms * 1e-3) / 1e9,
         "secular_iters_per_root": iters_per_root,
         "root_N": stats["root_N"],
         "roots": stats["roots"],
@@ -479,27 +682,24 @@ def main():
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in sorted(kinds.items())},
         "ms_per_step_kernel_by_kernel": ms_events,
         "roofline": roofline,
+        "accuracy": acc_fp64,
     }
-    line["accuracy"] = acc_fp64
-    if ozaki is not None:
-        line["ozaki"] = ozaki
-    if not args.no_learned:
-        line["learned"] = {
-            "ms_per_step": ms_learned,
-            "value": nominal / (ms_learned * 1e-3) / 1e9,
-            "secular_iters_per_root": stats_l["secular_evals"] / max(stats_l["roots"], 1),
-            "secular_iters_per_root_plain": iters_per_root,
-            "roots": stats_l["roots"],
-            "info": info_l,
-        }
-    if not args.no_config5 and args.workload == "n16384_normal":
-        del sig, ub, vb
-        torch.cuda.empty_cache()
+    if split is not None:
+        line["split"] = split
+    if learned is not None:
+        line["learned"] = learned
+    del sig, ub, vb, out
+    torch.cuda.empty_cache()
+    if headline and not args.no_config5:
         d5, e5 = inputs.workload("n32768_normal")
         line["config5"] = {"workload": WORKLOADS["n32768_normal"][0],
                            **plain_vs_learned(d5, e5, max(2, args.steps // 3), 1, tuning)}
+    if headline and not args.no_control:
+        line["control"] = control_leg(max(2, args.steps // 5), 1)
+    if headline and not args.no_batch:
+        line["batch2000"] = batch_leg(args.steps, args.warmup)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_n)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_n, flops if args.cpu_n == n and headline else None)
     print(json.dumps(line), flush=True)
 
 

@@ -97,7 +97,13 @@ typedef struct {
   int crt_moduli;             /* moduli of BDC_GEMM_CRT, 13..16 (default 16: operands
                                  rounded at 2^-54 of each row's / column's largest
                                  entry for products up to 16384 deep) */
+  int learned_min_n;          /* with BDC_START_LEARNED, the network proposes the
+                                 first points of merges of at least this many kept
+                                 values only; smaller merges start at the midpoint,
+                                 where one evaluation costs less than the network
+                                 (default BDC_LEARNED_MIN_N; 0 = every merge) */
 } bdc_options_t;
+#define BDC_LEARNED_MIN_N 1024
 
 void bdc_default_options(bdc_options_t* opt);
 
@@ -258,6 +264,9 @@ typedef struct {
                       the poles split over four wavefronts */
   int leaf_size;   /* the tree's leaf size (4..32; 0 in bdc_set_tuning keeps the
                       handle's); the paper found 32 best on its GPUs */
+  int tile128;     /* 128 x 128 products with a grid per merge: 0 (default) a
+                      single-buffered LDS tile at one workgroup per CU, 1 a
+                      double-buffered tile at two workgroups per CU */
   float ms;     /* out (bdc_autotune): time per solve of the chosen tuning */
 } bdc_tuning_t;
 

@@ -44,6 +44,7 @@ class Options(ctypes.Structure):
         ("ozaki_slices", c_int),
         ("ozaki_min_n", c_int),
         ("crt_moduli", c_int),
+        ("learned_min_n", c_int),
     ]
 
 
@@ -79,6 +80,7 @@ class Tuning(ctypes.Structure):
         ("grid128", c_int),
         ("sec_small_n", c_int),
         ("leaf_size", c_int),
+        ("tile128", c_int),
         ("ms", ctypes.c_float),
     ]
 

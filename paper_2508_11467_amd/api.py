@@ -28,10 +28,13 @@ class Solver:
     def __init__(self, device: int | torch.device = 0, leaf_size: int = 32, max_secular_iters: int = 64,
                  max_leaf_sweeps: int = 40, workspace_cap_bytes: int = 0, timing: bool = False,
                  use_graph: bool = True, start: str = "plain", mlp_params=None, gemm: str = "fp64",
-                 ozaki_slices: int = 7, ozaki_min_n: int = 256, crt_moduli: int = 16):
+                 ozaki_slices: int = 7, ozaki_min_n: int = 256, crt_moduli: int = 16,
+                 learned_min_n: int | None = None):
         """start: "plain" (midpoint) or "learned" (the MLP's proposal; the
         parameters come from ``mlp_params`` (host float32 vector) or, when
-        that is None, from the network file shipped with the package).
+        that is None, from the network file shipped with the package), for
+        merges of at least ``learned_min_n`` kept values (None: the library's
+        default; 0: every merge).
         gemm: "fp64", "ozaki" (bfloat16-slice split products) or "crt" (int8
         residue split products with ``crt_moduli`` moduli), the split forms
         for merges with at least ``ozaki_min_n`` kept values in
@@ -59,6 +62,8 @@ class Solver:
         opt.ozaki_slices = ozaki_slices
         opt.ozaki_min_n = ozaki_min_n
         opt.crt_moduli = crt_moduli
+        if learned_min_n is not None:
+            opt.learned_min_n = learned_min_n
         self.options = opt
         h = ctypes.c_void_p()
         check("bdc_create", self.lib.bdc_create(ctypes.byref(h), self.device.index, ctypes.byref(opt)))
@@ -156,8 +161,8 @@ class Solver:
         return d
 
     def set_tuning(self, small_n: int, flat: int, grid64: int, grid128: int, sec_small_n: int = 256,
-                   leaf_size: int = 0, **_ignored) -> None:
-        t = _lib.Tuning(small_n, flat, grid64, grid128, sec_small_n, leaf_size, 0.0)
+                   leaf_size: int = 0, tile128: int = 0, **_ignored) -> None:
+        t = _lib.Tuning(small_n, flat, grid64, grid128, sec_small_n, leaf_size, tile128, 0.0)
         check("bdc_set_tuning", self.lib.bdc_set_tuning(self.handle, ctypes.byref(t)))
 
     def autotune(self, sizes, d, e, out=None, repeats: int = 2) -> dict:

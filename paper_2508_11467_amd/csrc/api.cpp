@@ -247,19 +247,85 @@ int make_plan(bdc_handle_t h, const int64_t* sizes, int64_t batch) {
   return BDC_OK;
 }
 
-// Workspace: four n x n matrices per problem (Uwork, Vwork, UM, VM), the
-// per-position arrays and the node states.
+}  // namespace
+
+// Workspace layout: four n x n matrices per problem (Uwork, Vwork, UM, VM),
+// the per-position arrays and the node states, carved from `base` in this
+// order.  Returns the bytes; with w != NULL the pointers are set.
+size_t bdc::work_layout(Work* w, char* base, int64_t tn, int64_t tn2, int nnodes) {
+  const size_t N1 = (size_t)std::max<int64_t>(tn, 1), N2 = (size_t)std::max<int64_t>(tn2, 1);
+  const size_t nd_ = (size_t)std::max(nnodes, 1);
+  size_t off = 0;
+  auto take = [&](size_t nbytes) {
+    char* r = base + off;
+    off += align_up(nbytes);
+    return (void*)r;
+  };
+  Work t{};
+  t.Uw = (double*)take(N2 * 8);
+  t.Vw = (double*)take(N2 * 8);
+  t.UM = (double*)take(N2 * 8);
+  t.VM = (double*)take(N2 * 8);
+  t.sig = (double*)take(N1 * 8);
+  t.ps_d = (double*)take(N1 * 8);
+  t.ps_z = (double*)take(N1 * 8);
+  t.sd = (double*)take(N1 * 8);
+  t.sz = (double*)take(N1 * 8);
+  t.dval = (double*)take(N1 * 8);
+  t.tau = (double*)take(N1 * 8);
+  t.zt = (double*)take(N1 * 8);
+  t.rot_cs = (double*)take(2 * N1 * 8);
+  t.col = (int32_t*)take(N1 * 4);
+  t.ulo = (int32_t*)take(N1 * 4);
+  t.uhi = (int32_t*)take(N1 * 4);
+  t.vlo = (int32_t*)take(N1 * 4);
+  t.vhi = (int32_t*)take(N1 * 4);
+  t.ps_c = (int32_t*)take(N1 * 4);
+  t.ps_col = (int32_t*)take(N1 * 4);
+  t.ps_sup = (int32_t*)take(N1 * 4);
+  t.status = (int32_t*)take(N1 * 4);
+  t.ps_rot = (int32_t*)take(N1 * 4);
+  t.cand = (int32_t*)take(N1 * 4);
+  t.scol = (int32_t*)take(N1 * 4);
+  t.srot = (int32_t*)take(N1 * 4);
+  t.sgrp = (int32_t*)take(N1 * 4);
+  t.gsurv = (int32_t*)take(N1 * 4);
+  t.dcol = (int32_t*)take(N1 * 4);
+  t.drot = (int32_t*)take(N1 * 4);
+  t.o = (int32_t*)take(N1 * 4);
+  t.iters = (int32_t*)take(N1 * 4);
+  t.rot_pos = (int32_t*)take(2 * N1 * 4);
+  t.rot_col = (int32_t*)take(2 * N1 * 4);
+  t.xs = (float*)take(N1 * 4);
+  t.tile_off64 = (int*)take((nd_ + 1) * 4);
+  t.tile_off128 = (int*)take((nd_ + 1) * 4);
+  t.st = (NodeState*)take(nd_ * sizeof(NodeState));
+  t.ctl = (Ctl*)take(sizeof(Ctl));
+  t.fin = (int4*)take(2 * N1 * sizeof(int4));
+  t.leaf_fl = (unsigned long long*)take(N1 * 8);
+  t.sec = (SecCount*)take(nd_ * sizeof(SecCount));
+  if (w) {
+    w->Uw = t.Uw; w->Vw = t.Vw; w->UM = t.UM; w->VM = t.VM;
+    w->sig = t.sig; w->ps_d = t.ps_d; w->ps_z = t.ps_z; w->sd = t.sd; w->sz = t.sz; w->dval = t.dval;
+    w->tau = t.tau; w->zt = t.zt; w->rot_cs = t.rot_cs;
+    w->col = t.col; w->ulo = t.ulo; w->uhi = t.uhi; w->vlo = t.vlo; w->vhi = t.vhi;
+    w->ps_c = t.ps_c; w->ps_col = t.ps_col; w->ps_sup = t.ps_sup; w->status = t.status; w->ps_rot = t.ps_rot;
+    w->cand = t.cand; w->scol = t.scol; w->srot = t.srot; w->sgrp = t.sgrp; w->gsurv = t.gsurv;
+    w->dcol = t.dcol; w->drot = t.drot; w->o = t.o; w->iters = t.iters; w->rot_pos = t.rot_pos;
+    w->rot_col = t.rot_col; w->xs = t.xs; w->tile_off64 = t.tile_off64; w->tile_off128 = t.tile_off128;
+    w->st = t.st; w->ctl = t.ctl; w->fin = t.fin; w->leaf_fl = t.leaf_fl; w->sec = t.sec;
+  }
+  return off;
+}
+
+namespace {
+
 int ensure_workspace(bdc_handle_t h, int64_t tn, int64_t tn2, int nnodes) {
   if (tn <= h->cap_n && tn2 <= h->cap_n2 && nnodes <= h->cap_nodes && h->arena) return BDC_OK;
   tn = std::max<int64_t>(tn, h->cap_n);
   tn2 = std::max<int64_t>(tn2, h->cap_n2);
   nnodes = std::max(nnodes, h->cap_nodes);
-  const size_t N1 = (size_t)std::max<int64_t>(tn, 1), N2 = (size_t)std::max<int64_t>(tn2, 1);
-  const size_t nd_ = (size_t)std::max(nnodes, 1);
-  size_t bytes = 4 * align_up(N2 * 8) + 8 * align_up(N1 * 8) + align_up(2 * N1 * 8) +
-                 19 * align_up(N1 * 4) + 2 * align_up(2 * N1 * 4) + align_up(N1 * 4) +
-                 2 * align_up((nd_ + 1) * 4) + align_up(nd_ * sizeof(NodeState)) + align_up(sizeof(Ctl)) +
-                 align_up(2 * N1 * sizeof(int4)) + align_up(N1 * 8) + align_up(nd_ * sizeof(SecCount));
+  const size_t bytes = work_layout(nullptr, nullptr, tn, tn2, nnodes);
   if (h->opt.workspace_cap_bytes && bytes > h->opt.workspace_cap_bytes) return BDC_ERR_NOMEM;
   if (h->arena) {
     if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
@@ -275,55 +341,7 @@ int ensure_workspace(bdc_handle_t h, int64_t tn, int64_t tn2, int nnodes) {
     return BDC_ERR_NOMEM;
   }
   h->arena_bytes = bytes;
-  char* b = (char*)h->arena;
-  auto take = [&](size_t nbytes) {
-    char* r = b;
-    b += align_up(nbytes);
-    return (void*)r;
-  };
-  Work& w = h->w;
-  w.Uw = (double*)take(N2 * 8);
-  w.Vw = (double*)take(N2 * 8);
-  w.UM = (double*)take(N2 * 8);
-  w.VM = (double*)take(N2 * 8);
-  w.sig = (double*)take(N1 * 8);
-  w.ps_d = (double*)take(N1 * 8);
-  w.ps_z = (double*)take(N1 * 8);
-  w.sd = (double*)take(N1 * 8);
-  w.sz = (double*)take(N1 * 8);
-  w.dval = (double*)take(N1 * 8);
-  w.tau = (double*)take(N1 * 8);
-  w.zt = (double*)take(N1 * 8);
-  w.rot_cs = (double*)take(2 * N1 * 8);
-  w.col = (int32_t*)take(N1 * 4);
-  w.ulo = (int32_t*)take(N1 * 4);
-  w.uhi = (int32_t*)take(N1 * 4);
-  w.vlo = (int32_t*)take(N1 * 4);
-  w.vhi = (int32_t*)take(N1 * 4);
-  w.ps_c = (int32_t*)take(N1 * 4);
-  w.ps_col = (int32_t*)take(N1 * 4);
-  w.ps_sup = (int32_t*)take(N1 * 4);
-  w.status = (int32_t*)take(N1 * 4);
-  w.ps_rot = (int32_t*)take(N1 * 4);
-  w.cand = (int32_t*)take(N1 * 4);
-  w.scol = (int32_t*)take(N1 * 4);
-  w.srot = (int32_t*)take(N1 * 4);
-  w.sgrp = (int32_t*)take(N1 * 4);
-  w.gsurv = (int32_t*)take(N1 * 4);
-  w.dcol = (int32_t*)take(N1 * 4);
-  w.drot = (int32_t*)take(N1 * 4);
-  w.o = (int32_t*)take(N1 * 4);
-  w.iters = (int32_t*)take(N1 * 4);
-  w.rot_pos = (int32_t*)take(2 * N1 * 4);
-  w.rot_col = (int32_t*)take(2 * N1 * 4);
-  w.xs = (float*)take(N1 * 4);
-  w.tile_off64 = (int*)take((nd_ + 1) * 4);
-  w.tile_off128 = (int*)take((nd_ + 1) * 4);
-  w.st = (NodeState*)take(nd_ * sizeof(NodeState));
-  w.ctl = (Ctl*)take(sizeof(Ctl));
-  w.fin = (int4*)take(2 * N1 * sizeof(int4));
-  w.leaf_fl = (unsigned long long*)take(N1 * 8);
-  w.sec = (SecCount*)take(nd_ * sizeof(SecCount));
+  work_layout(&h->w, (char*)h->arena, tn, tn2, nnodes);
   h->cap_n = tn;
   h->cap_n2 = tn2;
   h->cap_nodes = nnodes;
@@ -472,6 +490,7 @@ int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, do
   w.GV = VT;
   w.max_secular_iters = h->opt.max_secular_iters;
   w.max_leaf_sweeps = h->opt.max_leaf_sweeps;
+  w.learned_min_n = h->opt.learned_min_n;
   const bool learned = h->opt.start == BDC_START_LEARNED;
   w.xs = nullptr;
   w.mlp_pk = learned ? h->mlp_pk : nullptr;
@@ -591,6 +610,7 @@ int solve(bdc_handle_t h, int64_t batch, const int64_t* sizes, const double* d, 
 }  // namespace
 
 int bdc::handle_sec_small(bdc_handle_t h) { return valid(h) ? h->tune.sec_small_n : 0; }
+int bdc::handle_tile128(bdc_handle_t h) { return valid(h) ? h->tune.tile128 : 0; }
 
 int bdc::handle_info(bdc_handle_t h, int* device, int* max_secular_iters, int* max_leaf_sweeps) {
   if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
@@ -616,6 +636,7 @@ void bdc_default_options(bdc_options_t* opt) {
   opt->ozaki_slices = 7;
   opt->ozaki_min_n = 256;
   opt->crt_moduli = 16;
+  opt->learned_min_n = BDC_LEARNED_MIN_N;
 }
 
 int bdc_create(bdc_handle_t* handle, int device, const bdc_options_t* opt) {
@@ -631,6 +652,7 @@ int bdc_create(bdc_handle_t* handle, int device, const bdc_options_t* opt) {
   if (o.gemm != BDC_GEMM_FP64 && o.gemm != BDC_GEMM_OZAKI && o.gemm != BDC_GEMM_CRT) return -3;
   if (!oz_supported(o.ozaki_slices) || o.ozaki_min_n < 128) return -3;
   if (!crt_supported(o.crt_moduli)) return -3;
+  if (o.learned_min_n < 0) return -3;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return BDC_ERR_NO_DEVICE;
   if (device < 0 || device >= count) return BDC_ERR_NO_DEVICE;
@@ -813,7 +835,8 @@ namespace {
 bool tuning_valid(const bdc_tuning_t* t) {
   return t->small_n >= 32 && t->small_n <= 4096 && (t->flat == 0 || t->flat == 1) && t->grid64 >= 1 &&
          t->grid64 <= 65535 && t->grid128 >= 1 && t->grid128 <= 65535 && t->sec_small_n >= 0 &&
-         t->sec_small_n <= kSecLanesMaxN && (t->leaf_size == 0 || (t->leaf_size >= 4 && t->leaf_size <= kMaxLeaf));
+         t->sec_small_n <= kSecLanesMaxN && (t->leaf_size == 0 || (t->leaf_size >= 4 && t->leaf_size <= kMaxLeaf)) &&
+         (t->tile128 == 0 || t->tile128 == 1);
 }
 }  // namespace
 
@@ -826,6 +849,7 @@ int bdc_get_tuning(bdc_handle_t h, bdc_tuning_t* t) {
   t->grid128 = h->tune.grid128;
   t->sec_small_n = h->tune.sec_small_n;
   t->leaf_size = h->opt.leaf_size;
+  t->tile128 = h->tune.tile128;
   return BDC_OK;
 }
 
@@ -835,7 +859,7 @@ int bdc_set_tuning(bdc_handle_t h, const bdc_tuning_t* t) {
   DeviceGuard g(h->device);
   if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
   drop_graph(h);  // launch shapes are part of a captured sequence
-  h->tune = Tuning{t->small_n, t->flat, t->grid64, t->grid128, t->sec_small_n};
+  h->tune = Tuning{t->small_n, t->flat, t->grid64, t->grid128, t->sec_small_n, t->tile128};
   if (t->leaf_size) h->opt.leaf_size = t->leaf_size;  // the plan is rebuilt on the next solve
   return BDC_OK;
 }
@@ -905,6 +929,17 @@ int bdc_autotune(bdc_handle_t h, int64_t batch, const int64_t* sizes, const doub
       }
     }
   }
+  // 3. the other form of the 128 x 128 tile with those shapes
+  if (rc == BDC_OK && !best_t.flat) {
+    Tuning c = best_t;
+    c.tile128 = 1 - c.tile128;
+    float ms = 0.0f;
+    rc = time_one(best_leaf, c, ms);
+    if (rc == BDC_OK && ms < best_ms) {
+      best_ms = ms;
+      best_t = c;
+    }
+  }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
@@ -917,6 +952,7 @@ int bdc_autotune(bdc_handle_t h, int64_t batch, const int64_t* sizes, const doub
   best->grid128 = h->tune.grid128;
   best->sec_small_n = h->tune.sec_small_n;
   best->leaf_size = h->opt.leaf_size;
+  best->tile128 = h->tune.tile128;
   best->ms = rc == BDC_OK ? best_ms : 0.0f;
   return rc;
 }

@@ -402,7 +402,7 @@ int bdc_step_gemm(bdc_handle_t h, int M, int N, int K, const double* A, int lda,
   if (ldc < std::max(1, M)) return -10;
   Guard g(dev);
   hipStream_t st = (hipStream_t)stream;
-  launch_gemm_plain(M, N, K, A, lda, B, ldb, C, ldc, st);
+  launch_gemm_plain(M, N, K, A, lda, B, ldb, C, ldc, handle_tile128(h), st);
   return hipGetLastError() == hipSuccess ? BDC_OK : BDC_ERR_HIP;
 }
 

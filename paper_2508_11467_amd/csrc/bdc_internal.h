@@ -188,6 +188,7 @@ struct Work {
   Ctl* ctl;
   int max_secular_iters;
   int max_leaf_sweeps;
+  int learned_min_n;  // merges with fewer kept values skip the in-kernel network
 };
 
 // Caller buffers that collect training rows of the learned start.
@@ -206,7 +207,12 @@ struct Tuning {
   int grid64;   // workgroups of the 64-tile update (flat), or twice the per-node cap
   int grid128;
   int sec_small_n;  // secular problems with N <= this (at most kSecLanesMaxN) use 8 or 16 lanes per root
+  int tile128 = 0;  // 128 x 128 products (per-merge grids): 0 single-buffered tile, 1 double-buffered
 };
+
+// Workspace layout of tn positions, tn2 matrix entries and nnodes merges
+// carved from base (bytes returned; with w != NULL the pointers are set).
+size_t work_layout(Work* w, char* base, int64_t tn, int64_t tn2, int nnodes);
 
 // ---- launchers (defined next to their kernels) ----
 void launch_reset(Ctl* ctl, NodeState* st, SecCount* sec, int nnodes, hipStream_t st_);
@@ -255,6 +261,8 @@ void launch_gemm_ozaki_plain(int slices, int M, int N, int K, const double* A, i
 void launch_update_crt(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, hipStream_t st);
 
 void launch_gemm_plain(int M, int N, int K, const double* A, int lda, const double* B, int ldb,
-                       double* C, int ldc, hipStream_t st);
+                       double* C, int ldc, int tile128, hipStream_t st);
+// the handle's 128 x 128 tile form (launch tuning)
+int handle_tile128(bdc_handle_t h);
 
 }  // namespace bdc

@@ -313,7 +313,11 @@ __device__ void secular_wide(const NodeDesc& nd, int N, const Work& w, WideLds<k
   const double* __restrict__ d = w.sd + vo;
   const double* __restrict__ z = w.sz + vo;
   const int maxit = w.max_secular_iters;
-  constexpr bool learned = kMode != 0;
+  // the network proposes the first points of merges of at least
+  // learned_min_n kept values; smaller ones start at the midpoint (uniform
+  // over the workgroup: one merge per workgroup)
+  const bool net = kMode == 2 && N >= w.learned_min_n;
+  const bool learned = kMode == 1 || net;
   const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
   double (*cd)[kSecChunk] = L.p.cd;
   double (*cz)[kSecChunk] = L.p.cz;
@@ -333,7 +337,7 @@ __device__ void secular_wide(const NodeDesc& nd, int N, const Work& w, WideLds<k
     if constexpr (kMode == 2) {
       // the network's proposals for roots base .. base+63, then the poles
       __syncthreads();
-      learned_proposals(w, L.m, d, z, N, rho, base, s_x, kRows);
+      if (net) learned_proposals(w, L.m, d, z, N, rho, base, s_x, kRows);
       if (resident)
         for (int j = q0 + lane; j < q1; j += 64) {
           cd[wv][j - q0] = d[j];
@@ -343,7 +347,7 @@ __device__ void secular_wide(const NodeDesc& nd, int N, const Work& w, WideLds<k
     const int i = base + lane;
     const bool active = i < N;
     Root R;
-    const float xp = kMode == 2 ? s_x[lane] : (kMode == 1 && active ? w.xs[vo + i] : 0.0f);
+    const float xp = net ? s_x[lane] : (kMode == 1 && active ? w.xs[vo + i] : 0.0f);
     R.init(d, N, rho, N == 1 ? z[0] : 0.0, i, active, learned, xp);
     for (;;) {
       if (wv == 0) {
@@ -483,13 +487,16 @@ __device__ void secular_lanes(const NodeDesc& nd, int N, const Work& w, LanesLds
   const int64_t vo = nd.vec_off + nd.r0;
   const double* __restrict__ d = w.sd + vo;
   const double* __restrict__ z = w.sz + vo;
-  constexpr bool learned = kMode != 0;
+  // the network proposes the first points of merges of at least
+  // learned_min_n kept values; smaller ones start at the midpoint
+  const bool net = kMode == 2 && N >= w.learned_min_n;
+  const bool learned = kMode == 1 || net;
   const int t = threadIdx.x;
   // network proposals for the workgroup's own roots
   if constexpr (kMode == 2) {
     static_assert(kRoots % 16 == 0 && kRoots <= 32, "whole 16-row strips, at most SmallMlp's rows");
     static_assert(kLanesMaxN <= 16 * 16, "far_block(N) gives at most 16 blocks for N <= 256");
-    if (N > 1) learned_proposals(w, M.m, d, z, N, rho, base, s_x, kRoots);
+    if (N > 1 && net) learned_proposals(w, M.m, d, z, N, rho, base, s_x, kRoots);
   }
   // poles, padded to whole steps with far poles of weight 0 (their terms are
   // exact zeros: d^2 - omega^2 is about 2^1000, its reciprocal a normal number)
@@ -503,7 +510,7 @@ __device__ void secular_lanes(const NodeDesc& nd, int N, const Work& w, LanesLds
   const int i = base + t / L;
   const bool active = i < N;
   Root R;
-  const float xp = kMode == 2 ? s_x[i - base] : (kMode == 1 && active ? w.xs[vo + i] : 0.0f);
+  const float xp = net ? s_x[i - base] : (kMode == 1 && active ? w.xs[vo + i] : 0.0f);
   R.init(cd, N, rho, N == 1 ? z[0] : 0.0, i, active, learned, xp);
   while (R.need) {
     // left model poles j <= lp, right ones above (for the last root the

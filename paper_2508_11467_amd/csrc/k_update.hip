@@ -343,6 +343,103 @@ __device__ inline void gemm_tile(TileSmem<TM, TN>& sm, const double* __restrict_
   }
 }
 
+// Second form of the 128 x 128 tile: both 16-deep slabs double-buffered in
+// LDS (one barrier per slab: the next slab's global loads are issued before
+// the current slab's products and land in the other buffer after them), and
+// laid out so that neither the stores nor the operand reads conflict on the
+// LDS banks: A as [k][m] with a row stride of 144 doubles (the two k rows of
+// a half-wavefront's read are 32 banks apart), B as [n][k] with a column
+// stride of 17 doubles (k contiguous as in memory; the 16 columns of a read
+// fall on distinct banks).  70 KB of LDS; one workgroup per CU (the 64
+// accumulators per lane need more registers than two would leave).
+constexpr int kSA2 = 144, kSB2 = 17;
+struct TileSmem2 {
+  double A[2][TK * kSA2];
+  double B[2][128 * kSB2];
+};
+
+template <class Store>
+__device__ inline void gemm_tile2(TileSmem2& sm, const double* __restrict__ A, int64_t lda,
+                                  const double* __restrict__ B, int64_t ldb, int M, int N, int K, int tm0, int tn0,
+                                  Store store) {
+  constexpr int TM = 128, TN = 128;
+  constexpr int FA = TM * TK / kBlock, FB = TN * TK / kBlock;
+  const int t = threadIdx.x, wv = t >> 6, l = t & 63;
+  const int wm = wv & 1, wn = wv >> 1;
+  const int li = l & 15, lk = l >> 4;
+  v4d acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  double ra[FA], rb[FB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < FA; ++q) {
+      const int e = t + kBlock * q;
+      const int r = e % TM, kk = e / TM;
+      const int gr = tm0 + r, gk = k0 + kk;
+      ra[q] = (gr < M && gk < K) ? A[gr + (int64_t)gk * lda] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < FB; ++q) {
+      const int e = t + kBlock * q;
+      const int kk = e % TK, c = e / TK;
+      const int gk = k0 + kk, gc = tn0 + c;
+      rb[q] = (gk < K && gc < N) ? B[gk + (int64_t)gc * ldb] : 0.0;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < FA; ++q) {
+      const int e = t + kBlock * q;
+      sm.A[buf][(e / TM) * kSA2 + e % TM] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < FB; ++q) {
+      const int e = t + kBlock * q;
+      sm.B[buf][(e / TK) * kSB2 + e % TK] = rb[q];
+    }
+  };
+  const int nslab = (K + TK - 1) / TK;
+  __syncthreads();  // the previous tile's readers are done with both buffers
+  load(0);
+  stash(0);
+  __syncthreads();
+  for (int sl = 0; sl < nslab; ++sl) {
+    const int buf = sl & 1;
+    if (sl + 1 < nslab) load((sl + 1) * TK);
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      double af[4], bf[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) af[a] = sm.A[buf][(kk + lk) * kSA2 + wm * 64 + a * 16 + li];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bf[b] = sm.B[buf][(wn * 64 + b * 16 + li) * kSB2 + kk + lk];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+    if (sl + 1 < nslab) {
+      stash(buf ^ 1);
+      __syncthreads();
+    }
+  }
+  // D[i][j] of a 16x16 block sits in lane j + 16 * (i % 4), register i / 4
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = tm0 + wm * 64 + a * 16 + lk + 4 * r;
+        const int colc = tn0 + wn * 64 + b * 16 + li;
+        if (row < M && colc < N) *(store.col(colc) + row) = acc[a][b][r];
+      }
+}
+
 // destination of output column c (row 0): the kept value's physical column
 struct NodeStore {
   double* C;
@@ -397,6 +494,35 @@ __global__ __launch_bounds__(256, update_waves_per_eu(TM)) void k_update(const N
   for (int tile = blockIdx.y; tile < ntiles; tile += gridDim.y) {
     const int tm = tile % tiles_m, tn = tile / tiles_m;
     gemm_tile<TM, TN>(sm, A, ld, B, ld, rows, N, K, tm * TM, tn * TN, store);
+  }
+}
+
+// The 128 x 128 class with the double-buffered tile (two workgroups per CU).
+__global__ __launch_bounds__(256, 1) void k_update2(const NodeDesc* __restrict__ nodes, Work w) {
+  __shared__ TileSmem2 sm;
+  const NodeDesc nd = nodes[blockIdx.x];
+  const NodeState st = w.st[nd.id];
+  const int N = st.N, n1 = st.n1, n2 = st.n2;
+  if (N <= w.small_n) return;
+  if (N >= w.oz.min_n) return;  // done by the split-precision products
+  const int m = nd.m, s = nd.s, k = nd.k, r0 = nd.r0;
+  const int64_t ld = nd.ld, vo = nd.vec_off + nd.r0;
+  const int sub = blockIdx.z;
+  const bool isV = sub >= 2, bottom = sub & 1;
+  const int rows = bottom ? (isV ? m + s - k : m - k) : k;
+  const int kb = bottom ? n1 : 0;
+  const int ke = bottom ? N : n1 + 1 + n2;
+  const int K = ke - kb;
+  const int rowoff = bottom ? k : 0;
+  const double* G = (isV ? w.GV : w.GU) + nd.mat_off;
+  const double* Mv = (isV ? w.VM : w.UM) + nd.mat_off;
+  const double* A = G + (r0 + rowoff) + (int64_t)(r0 + kb) * ld;
+  const double* B = Mv + (r0 + kb) + (int64_t)r0 * ld;
+  NodeStore store{(isV ? w.Vw : w.Uw) + nd.mat_off, w.scol + vo, ld, r0 + rowoff};
+  const int tiles_m = (rows + 127) / 128, tiles_n = (N + 127) / 128;
+  for (int tile = blockIdx.y; tile < tiles_m * tiles_n; tile += gridDim.y) {
+    const int tm = tile % tiles_m, tn = tile / tiles_m;
+    gemm_tile2(sm, A, ld, B, ld, rows, N, K, tm * 128, tn * 128, store);
   }
 }
 
@@ -577,6 +703,16 @@ __global__ __launch_bounds__(256) void k_gemm_plain(int M, int N, int K, const d
   for (int tile = blockIdx.x; tile < tiles_m * tiles_n; tile += gridDim.x) {
     const int tm = tile % tiles_m, tn = tile / tiles_m;
     gemm_tile<TM, TN>(sm, A, lda, B, ldb, M, N, K, tm * TM, tn * TN, PlainStore{C, ldc});
+  }
+}
+
+__global__ __launch_bounds__(256, 1) void k_gemm_plain2(int M, int N, int K, const double* A, int lda,
+                                                        const double* B, int ldb, double* C, int ldc) {
+  __shared__ TileSmem2 sm;
+  const int tiles_m = (M + 127) / 128, tiles_n = (N + 127) / 128;
+  for (int tile = blockIdx.x; tile < tiles_m * tiles_n; tile += gridDim.x) {
+    const int tm = tile % tiles_m, tn = tile / tiles_m;
+    gemm_tile2(sm, A, lda, B, ldb, M, N, K, tm * 128, tn * 128, PlainStore{C, ldc});
   }
 }
 
@@ -964,12 +1100,15 @@ void launch_update(const NodeDesc* nodes, int nnodes, int max_m, const Work& w, 
   if (max_m > w.small_n) {
     const int tiles = ((max_m + 1 + 127) / 128) * ((max_m + 127) / 128);
     const int gy = grid_y(nnodes, tiles, tu.grid128 * 2);
-    hipLaunchKernelGGL((k_update<128, 128>), dim3(nnodes, gy, 4), dim3(kBlock), 0, st, nodes, w);
+    if (tu.tile128)
+      hipLaunchKernelGGL(k_update2, dim3(nnodes, gy, 4), dim3(kBlock), 0, st, nodes, w);
+    else
+      hipLaunchKernelGGL((k_update<128, 128>), dim3(nnodes, gy, 4), dim3(kBlock), 0, st, nodes, w);
   }
 }
 
 void launch_gemm_plain(int M, int N, int K, const double* A, int lda, const double* B, int ldb,
-                       double* C, int ldc, hipStream_t st) {
+                       double* C, int ldc, int tile128, hipStream_t st) {
   if (M <= 0 || N <= 0) return;
   if (N <= 96) {
     int tiles = ((M + 63) / 64) * ((N + 63) / 64);
@@ -978,7 +1117,11 @@ void launch_gemm_plain(int M, int N, int K, const double* A, int lda, const doub
   } else {
     int tiles = ((M + 127) / 128) * ((N + 127) / 128);
     if (tiles > 4096) tiles = 4096;
-    hipLaunchKernelGGL((k_gemm_plain<128, 128>), dim3(tiles), dim3(kBlock), 0, st, M, N, K, A, lda, B, ldb, C, ldc);
+    if (tile128)
+      hipLaunchKernelGGL(k_gemm_plain2, dim3(tiles), dim3(kBlock), 0, st, M, N, K, A, lda, B, ldb, C, ldc);
+    else
+      hipLaunchKernelGGL((k_gemm_plain<128, 128>), dim3(tiles), dim3(kBlock), 0, st, M, N, K, A, lda, B, ldb, C,
+                         ldc);
   }
 }
 

@@ -65,7 +65,8 @@ def harvest(solver: Solver, split: str, target: int, capacity: int, log) -> tupl
 def evaluate_iters(params: np.ndarray, problems) -> dict:
     out = {}
     for start in ("plain", "learned"):
-        s = Solver(0, start=start, mlp_params=params if start == "learned" else None, use_graph=False)
+        s = Solver(0, start=start, mlp_params=params if start == "learned" else None, use_graph=False,
+                   learned_min_n=0)
         ev = roots = 0
         for d, e in problems:
             s.svd(d, e)

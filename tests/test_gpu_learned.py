@@ -222,7 +222,7 @@ def test_untrained_network_keeps_the_tolerances(gpu, small):
     """Any proposal is safe: the safeguarded iteration still converges."""
     from paper_2508_11467_amd.api import Solver
     from paper_2508_11467_amd.start_model import init_params
-    s = Solver(0, start="learned", mlp_params=init_params(3))
+    s = Solver(0, start="learned", mlp_params=init_params(3), learned_min_n=0)
     s.set_tuning(small_n=96, flat=0, grid64=1024, grid128=512, sec_small_n=small)
     try:
         for d, e in [inputs.uniform(1500, 41), inputs.workload("n4096_graded")]:
@@ -245,7 +245,7 @@ def test_trained_network_cuts_iterations(gpu):
     from paper_2508_11467_amd.api import Solver
     d, e = inputs.normal(4096, inputs.split_seed(3, 0, "valid", 77))
     plain = Solver(0)
-    learned = Solver(0, start="learned")
+    learned = Solver(0, start="learned", learned_min_n=0)
     try:
         s0, U0, V0, st0 = _solve_checks(plain, d, e)
         s1, U1, V1, st1 = _solve_checks(learned, d, e)
@@ -264,3 +264,26 @@ def test_trained_network_cuts_iterations(gpu):
     print(f"secular evaluations per root: plain {ip:.3f}, learned {il:.3f}")
     assert st0["roots"] == st1["roots"]
     assert il <= 0.9 * ip
+
+
+def test_gated_network_leaves_small_merges_plain(gpu):
+    """With the network gated to merges of at least learned_min_n kept values,
+    a problem whose merges are all smaller solves exactly as with the plain
+    start (same values bit for bit, same evaluation counts); gated at 0 the
+    network runs on every merge."""
+    from paper_2508_11467_amd.api import Solver
+    d, e = inputs.normal(2048, 55)
+    plain = Solver(0)
+    gated = Solver(0, start="learned", learned_min_n=100000)
+    ungated = Solver(0, start="learned", learned_min_n=0)
+    try:
+        s0, U0, V0, st0 = _solve_checks(plain, d, e)
+        s1, U1, V1, st1 = _solve_checks(gated, d, e)
+        s2, U2, V2, st2 = _solve_checks(ungated, d, e)
+    finally:
+        plain.close()
+        gated.close()
+        ungated.close()
+    assert np.array_equal(s0, s1) and np.array_equal(U0, U1) and np.array_equal(V0, V1)
+    assert st0["secular_evals"] == st1["secular_evals"]
+    assert st2["secular_evals"] != st0["secular_evals"]

@@ -282,7 +282,7 @@ def test_full_size_n32768_normal(gpu, start):
     every value against the oracle's Sturm bisection."""
     from paper_2508_11467_amd.api import Solver
     d, e = inputs.workload("n32768_normal")
-    s = Solver(0, start=start)
+    s = Solver(0, start=start, learned_min_n=0)
     try:
         st = _full_size_checks(s, d, e, golden("sturm_sigma_n32768_normal.npy"), f"sturm, {start}")
         assert st["levels"] == 10
