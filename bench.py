@@ -71,6 +71,7 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=16384, help="size of the CPU oracle run (N(0,1) bidiagonal)")
     ap.add_argument("--no-control", action="store_true", help="skip the d = e = 1 control (FP64 vs split)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 2000-problem batch")
+    ap.add_argument("--no-backtr", action="store_true", help="skip the back-transformation leg")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch tuning only")
     ap.add_argument("--no-config5", action="store_true", help="skip the n = 32768 plain/learned comparison")
     ap.add_argument("--no-ozaki", action="store_true", help="skip the split-precision comparison")
@@ -525,6 +526,44 @@ def batch_leg(steps: int, warmup: int) -> dict:
     return res
 
 
+def backtr_leg(steps: int) -> dict:
+    """Back-transformation (Section 4.3.3) at n = 16384: 16384 seeded
+    Householder reflectors (LAPACK storage, tau = 2 / y^T y) applied to a
+    16384 x 16384 matrix in blocks of 64 (modified compact WY form), time and
+    the FP64 rate of its products against the matrix-core peak."""
+    import torch
+
+    from paper_2508_11467_amd.api import Solver
+    n, b = 16384, 64
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    Y = torch.tril(torch.randn((n, n), dtype=torch.float64, device="cuda", generator=gen) * 0.01, -1)
+    Y = Y.T.contiguous().T  # reflectors in columns, column-major
+    tau = 2.0 / (1.0 + torch.sum(Y * Y, dim=0))
+    C = torch.randn((n, n), dtype=torch.float64, device="cuda", generator=gen).T
+    s = Solver(0)
+    s.apply_reflectors(Y, tau, C)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    z = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        s.apply_reflectors(Y, tau, C)
+    z.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(z) / steps
+    s.close()
+    fl = 0.0
+    for i0 in range(0, n, b):
+        mr, bw = n - i0, min(b, n - i0)
+        fl += 2.0 * mr * bw * bw + 4.0 * mr * bw * n + bw * bw * n
+    del Y, C, tau
+    torch.cuda.empty_cache()
+    return {"workload": "C <- Q C, Q = H_0 ... H_16383 (seeded reflectors), C 16384 x 16384, blocks of 64",
+            "ms_per_step": ms, "flops": fl, "tflops": fl / ms / 1e9,
+            "frac_of_fp64_mfma_peak": fl / (ms * 1e-3) / PEAK_FP64_MFMA}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -698,6 +737,8 @@ def main():
         line["control"] = control_leg(max(2, args.steps // 5), 1)
     if headline and not args.no_batch:
         line["batch2000"] = batch_leg(args.steps, args.warmup)
+    if headline and not args.no_backtr:
+        line["back_transformation"] = backtr_leg(2)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_n, flops if args.cpu_n == n and headline else None)
     print(json.dumps(line), flush=True)

@@ -246,6 +246,31 @@ int bdc_step_vectors(bdc_handle_t handle, int N, const double* d, const double* 
 int bdc_step_gemm(bdc_handle_t handle, int M, int N, int K, const double* A, int lda,
                   const double* B, int ldb, double* C, int ldc, bdc_stream_t stream);
 
+/* ---- back-transformation of singular vectors -------------------------------
+ * The step after the bidiagonal SVD on the paper's full-SVD path (Section
+ * 4.3.3): U = U_1 U_2 and V^T = V_2^T V_1^T, where U_1 = H_0 ... H_{n-1} and
+ * V_1 = G_0 ... G_{n-2} are the products of the column and row Householder
+ * reflectors of the bidiagonal reduction (Section 4.1) and U_2, V_2 the
+ * bidiagonal's singular vectors (bdc_svd).  Both are C <- Q C with Q a
+ * product of reflectors: U = Q_col [U_2; 0], and V = P_row V_2 (then V^T).
+ *
+ * C (m x p, column-major, ld ldc >= m) <- Q C (trans = 0) or Q^T C
+ * (trans = 1), Q = H_0 H_1 ... H_{k-1}, H_i = I - tau[i] y_i y_i^T.  y_i has
+ * a unit pivot at row i + offset, zeros above it, and below it the entries
+ * Y[r * y_rs + i * y_cs] (LAPACK's geqrf / gebrd storage: column-stored
+ * reflectors y_rs = 1, y_cs = ld; row-stored ones y_rs = ld, y_cs = 1, with
+ * offset 1 for gebrd's row reflectors); tau[i] = 0 makes H_i the identity.
+ * All pointers are device pointers; Y and tau are not written.  The
+ * reflectors are applied `block` at a time (1..64; 0 = 64) in the modified
+ * compact WY form of eq. inv_t / larft_update: T^{-1} = Y^T Y above its
+ * diagonal and 1/tau_i on it (gemm), Z = Y^T C (gemm), Z = T^{-1} \ Z (trsm),
+ * C = C - Y Z (gemm), on the FP64 matrix cores.  Scratch is owned by the
+ * handle (grown on demand).  Enqueues on `stream`; returns BDC_OK, -i for an
+ * invalid argument i, BDC_ERR_NOMEM or BDC_ERR_HIP. */
+int bdc_apply_reflectors(bdc_handle_t handle, int trans, int m, int p, int k, int offset, const double* Y,
+                         int64_t y_rs, int64_t y_cs, const double* tau, double* C, int ldc, int block,
+                         bdc_stream_t stream);
+
 /* ---- launch tuning ---------------------------------------------------------
  * Launch shapes of the vector-update products.  The autotuner times a small
  * set of candidates on the caller's own problem (or batch) and keeps the

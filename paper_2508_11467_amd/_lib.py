@@ -114,6 +114,8 @@ SIGNATURES = {
     "bdc_set_harvest": (c_int, [c_vp, c_vp, c_vp, c_vp, c_i64, c_vp]),
     "bdc_step_gemm_ozaki": (c_int, [c_vp, c_int, c_int, c_int, c_int, c_vp, c_int, c_vp, c_int, c_vp, c_int, c_vp]),
     "bdc_step_gemm_crt": (c_int, [c_vp, c_int, c_int, c_int, c_int, c_vp, c_int, c_vp, c_int, c_vp, c_int, c_vp]),
+    "bdc_apply_reflectors": (c_int, [c_vp, c_int, c_int, c_int, c_int, c_int, c_vp, c_i64, c_i64, c_vp, c_vp, c_int,
+                                     c_int, c_vp]),
     "bdc_get_tuning": (c_int, [c_vp, ctypes.POINTER(Tuning)]),
     "bdc_set_tuning": (c_int, [c_vp, ctypes.POINTER(Tuning)]),
     "bdc_autotune": (c_int, [c_vp, c_i64, ctypes.POINTER(c_i64), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_int,

@@ -239,6 +239,27 @@ class Solver:
         check("bdc_set_harvest", self.lib.bdc_set_harvest(self.handle, None, None, None, 0, None))
         self._harvest = None
 
+    # ---------------------------------------------------------------- back-transformation
+    def apply_reflectors(self, Y: torch.Tensor, tau: torch.Tensor, C: torch.Tensor, trans: bool = False,
+                         offset: int = 0, rows: bool = False, block: int = 0) -> torch.Tensor:
+        """C <- Q C (or Q^T C) in place for Q = H_0 ... H_{k-1}: reflector i
+        in column i of Y (rows=False; Y is (m, k)) or row i (rows=True; Y is
+        (k, m)), unit pivot at i + offset, stored entries below it.  C is a
+        (m, p) float64 tensor whose memory is column-major (pass the .T of a
+        contiguous (p, m) tensor)."""
+        m, p = C.shape
+        if C.stride(0) != 1 or C.stride(1) < max(1, m):
+            raise ValueError("C must be column-major (the transpose of a contiguous tensor)")
+        k = tau.shape[0]
+        if rows:
+            rs, cs = Y.stride(1), Y.stride(0)
+        else:
+            rs, cs = Y.stride(0), Y.stride(1)
+        check("bdc_apply_reflectors", self.lib.bdc_apply_reflectors(
+            self.handle, 1 if trans else 0, m, p, k, offset, _ptr(Y), rs, cs, _ptr(tau), _ptr(C), C.stride(1),
+            block, self._stream()))
+        return C
+
     # ---------------------------------------------------------------- steps
     def step_leaf(self, d, e, s: int):
         d = _f64(d, self.device)

@@ -26,6 +26,7 @@ SOURCES = {
     "k_mlp.hip": [],
     "k_ozaki.hip": [],
     "k_crt.hip": [],
+    "k_backtr.hip": [],
     "api.cpp": [],
     "api_steps.cpp": [],
 }

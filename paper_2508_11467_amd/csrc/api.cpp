@@ -20,6 +20,7 @@
 
 #include "bdc.h"
 #include "bdc_internal.h"
+#include "backtr.h"
 #include "crt.h"
 
 using namespace bdc;
@@ -92,6 +93,8 @@ struct bdc_handle_s {
   // per-workgroup gradient partials of a training step, and harvest buffers
   void* oz_arena = nullptr;  // split-precision slice planes (single-problem solves)
   size_t oz_bytes = 0;
+  void* bt_arena = nullptr;   // back-transformation scratch (grown on demand)
+  size_t bt_bytes = 0;
   void* crt_arena = nullptr;  // int8 residue planes (single-problem solves)
   size_t crt_bytes = 0;
   int64_t crt_n = -1;         // problem size the residue planes are laid out for
@@ -675,6 +678,7 @@ int bdc_destroy(bdc_handle_t h) {
     if (h->arena) (void)hipFree(h->arena);
     if (h->oz_arena) (void)hipFree(h->oz_arena);
     if (h->crt_arena) (void)hipFree(h->crt_arena);
+    if (h->bt_arena) (void)hipFree(h->bt_arena);
     if (h->mlp) (void)hipFree(h->mlp);
     if (h->mlp_pk) (void)hipFree(h->mlp_pk);
     if (h->part) (void)hipFree(h->part);
@@ -826,6 +830,47 @@ int bdc_clear_timing(bdc_handle_t h) {
   if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
   h->recs.clear();
   h->pool_used = 0;
+  return BDC_OK;
+}
+
+// ---- back-transformation -----------------------------------------------------
+
+int bdc_apply_reflectors(bdc_handle_t h, int trans, int m, int p, int k, int offset, const double* Y, int64_t y_rs,
+                         int64_t y_cs, const double* tau, double* C, int ldc, int block, bdc_stream_t stream) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  if (trans != 0 && trans != 1) return -2;
+  if (m < 0) return -3;
+  if (p < 0) return -4;
+  if (k < 0) return -5;
+  if (offset < 0) return -6;
+  if (m == 0 || p == 0 || k == 0) return BDC_OK;
+  if (!Y) return -7;
+  if (y_rs < 1 && y_cs < 1) return -8;
+  if (!tau) return -10;
+  if (!C) return -11;
+  if (ldc < m) return -12;
+  if (block == 0) block = kBtMaxBlock;
+  if (block < 1 || block > kBtMaxBlock) return -13;
+  DeviceGuard g(h->device);
+  if (!g.ok) return BDC_ERR_HIP;
+  const size_t bytes = backtr_bytes(m, p, block);
+  if (h->bt_bytes < bytes) {
+    if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
+    if (h->bt_arena) (void)hipFree(h->bt_arena);
+    h->bt_arena = nullptr;
+    h->bt_bytes = 0;
+    if (h->opt.workspace_cap_bytes && h->arena_bytes + bytes > h->opt.workspace_cap_bytes) return BDC_ERR_NOMEM;
+    if (hipMalloc(&h->bt_arena, bytes) != hipSuccess) {
+      h->bt_arena = nullptr;
+      return BDC_ERR_NOMEM;
+    }
+    h->bt_bytes = bytes;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  launch_backtr(trans, m, p, k, offset, Y, y_rs, y_cs, tau, C, ldc, block, h->bt_arena, st);
+  if (hipGetLastError() != hipSuccess) return BDC_ERR_HIP;
+  h->last_stream = st;
+  h->have_call = true;
   return BDC_OK;
 }
 

@@ -306,7 +306,7 @@ int bdc_step_gemm_crt(bdc_handle_t h, int moduli, int M, int N, int K, const dou
   if (!crt_supported(moduli)) return -2;
   if (M < 0) return -3;
   if (N < 0) return -4;
-  if (K < 0 || K > (1 << 20)) return -5;
+  if (K < 0 || K > (1 << 17)) return -5;  // int32 sums exact: K * 127^2 < 2^31
   if (M > 0 && K > 0 && !A) return -6;
   if (lda < std::max(1, M)) return -7;
   if (K > 0 && N > 0 && !B) return -8;
