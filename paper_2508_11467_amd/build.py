@@ -27,6 +27,7 @@ SOURCES = {
     "k_ozaki.hip": [],
     "k_crt.hip": [],
     "k_backtr.hip": [],
+    "plan.cpp": [],
     "api.cpp": [],
     "api_steps.cpp": [],
 }

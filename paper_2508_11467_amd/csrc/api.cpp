@@ -21,6 +21,7 @@
 #include "bdc.h"
 #include "bdc_internal.h"
 #include "backtr.h"
+#include "plan.h"
 #include "crt.h"
 
 using namespace bdc;
@@ -136,21 +137,6 @@ void free_plan(Plan& p) {
   p = Plan();
 }
 
-int build_node(std::vector<LeafDesc>& leaves, std::vector<std::vector<NodeDesc>>& by_h,
-               int64_t mat_off, int64_t vec_off, int32_t n, int leaf, int32_t r0, int32_t m, int32_t s) {
-  if (m <= leaf) {
-    leaves.push_back(LeafDesc{mat_off, vec_off, n, r0, m, s});
-    return 0;
-  }
-  const int32_t k = m / 2;
-  const int hl = build_node(leaves, by_h, mat_off, vec_off, n, leaf, r0, k - 1, 1);
-  const int hr = build_node(leaves, by_h, mat_off, vec_off, n, leaf, r0 + k, m - k, s);
-  const int h = 1 + std::max(hl, hr);
-  if ((int)by_h.size() <= h) by_h.resize(h + 1);
-  by_h[h].push_back(NodeDesc{mat_off, vec_off, n, r0, m, s, k, -1});
-  return h;
-}
-
 int make_plan(bdc_handle_t h, const int64_t* sizes, int64_t batch) {
   const int leaf = h->opt.leaf_size;
   if (h->plan_valid && h->plan.leaf == leaf && (int64_t)h->plan.sizes.size() == batch &&
@@ -164,45 +150,25 @@ int make_plan(bdc_handle_t h, const int64_t* sizes, int64_t batch) {
   p.sizes.assign(sizes, sizes + batch);
   p.leaf = leaf;
   p.nprob = (int)batch;
-  std::vector<LeafDesc> leaves;
-  std::vector<std::vector<NodeDesc>> by_h;
-  std::vector<int64_t> pn(batch), pvec(batch), pmat(batch), pcol(batch), ptile(batch);
-  int64_t vo = 0, mo = 0, co = 0, to = 0;
-  for (int64_t i = 0; i < batch; ++i) {
-    const int64_t n = sizes[i];
-    pn[i] = n;
-    pvec[i] = vo;
-    pmat[i] = mo;
-    pcol[i] = co;
-    ptile[i] = to;
-    if (n > 0) build_node(leaves, by_h, mo, vo, (int32_t)n, leaf, 0, (int32_t)n, 0);
-    vo += n;
-    mo += n * n;
-    if (n > 0) co += (n + final_u_cols(n) - 1) / final_u_cols(n);  // U work items
-    to += vt_bands(n) * vt_groups(n);  // V^T work items
-  }
-  p.total_n = vo;
-  p.total_n2 = mo;
-  p.total_cols = co;
-  p.total_tiles = to;
-  p.nleaves = (int)leaves.size();
-  // node ids level by level; remember the first problem's root
-  int id = 0;
-  for (size_t hh = 1; hh < by_h.size(); ++hh)
-    for (auto& nd : by_h[hh]) {
-      nd.id = id++;
-      if (nd.vec_off == 0 && nd.r0 == 0 && batch > 0 && nd.m == sizes[0]) p.root_id0 = nd.id;
-      p.host_nodes.push_back(nd);
-    }
+  HostPlan hp = build_host_plan(sizes, batch, leaf);
+  p.total_n = hp.total_n;
+  p.total_n2 = hp.total_n2;
+  p.total_cols = hp.total_cols;
+  p.total_tiles = hp.total_tiles;
+  p.nleaves = (int)hp.leaves.size();
+  p.root_id0 = hp.root_id0;
+  p.host_nodes = hp.nodes;
+  const int id = (int)hp.nodes.size();
   p.nnodes = id;
-  size_t bytes = align_up(sizeof(LeafDesc) * std::max<size_t>(1, leaves.size())) +
+  const int64_t co = hp.total_cols, to = hp.total_tiles;
+  size_t bytes = align_up(sizeof(LeafDesc) * std::max<size_t>(1, hp.leaves.size())) +
                  align_up(sizeof(NodeDesc) * std::max(1, id)) +
                  align_up(sizeof(int64_t) * 5 * std::max<int64_t>(1, batch)) +
                  align_up(sizeof(int32_t) * std::max<int64_t>(1, co)) + align_up(sizeof(int32_t) * std::max<int64_t>(1, to));
   if (hipMalloc(&p.block, bytes) != hipSuccess) return BDC_ERR_NOMEM;
   char* b = (char*)p.block;
   p.dev_leaves = (LeafDesc*)b;
-  b += align_up(sizeof(LeafDesc) * std::max<size_t>(1, leaves.size()));
+  b += align_up(sizeof(LeafDesc) * std::max<size_t>(1, hp.leaves.size()));
   NodeDesc* nodes_dev = (NodeDesc*)b;
   b += align_up(sizeof(NodeDesc) * std::max(1, id));
   p.dev_prob = (int64_t*)b;
@@ -210,38 +176,23 @@ int make_plan(bdc_handle_t h, const int64_t* sizes, int64_t batch) {
   p.dev_uprob = (int32_t*)b;
   b += align_up(sizeof(int32_t) * std::max<int64_t>(1, co));
   p.dev_vprob = (int32_t*)b;
-  {
-    std::vector<int32_t> up(std::max<int64_t>(1, co)), vp(std::max<int64_t>(1, to));
-    for (int64_t i = 0; i < batch; ++i) {
-      const int64_t ue = i + 1 < batch ? pcol[i + 1] : co, ve = i + 1 < batch ? ptile[i + 1] : to;
-      for (int64_t q = pcol[i]; q < ue; ++q) up[q] = (int32_t)i;
-      for (int64_t q = ptile[i]; q < ve; ++q) vp[q] = (int32_t)i;
-    }
-    if ((co > 0 && hipMemcpy(p.dev_uprob, up.data(), sizeof(int32_t) * co, hipMemcpyHostToDevice) != hipSuccess) ||
-        (to > 0 && hipMemcpy(p.dev_vprob, vp.data(), sizeof(int32_t) * to, hipMemcpyHostToDevice) != hipSuccess))
-      return free_plan(p), BDC_ERR_HIP;
-  }
-  if (!leaves.empty() &&
-      hipMemcpy(p.dev_leaves, leaves.data(), sizeof(LeafDesc) * leaves.size(), hipMemcpyHostToDevice) != hipSuccess)
+  if ((co > 0 && hipMemcpy(p.dev_uprob, hp.uprob.data(), sizeof(int32_t) * co, hipMemcpyHostToDevice) != hipSuccess) ||
+      (to > 0 && hipMemcpy(p.dev_vprob, hp.vprob.data(), sizeof(int32_t) * to, hipMemcpyHostToDevice) != hipSuccess))
     return free_plan(p), BDC_ERR_HIP;
-  if (id > 0 && hipMemcpy(nodes_dev, p.host_nodes.data(), sizeof(NodeDesc) * id, hipMemcpyHostToDevice) != hipSuccess)
+  if (!hp.leaves.empty() && hipMemcpy(p.dev_leaves, hp.leaves.data(), sizeof(LeafDesc) * hp.leaves.size(),
+                                      hipMemcpyHostToDevice) != hipSuccess)
     return free_plan(p), BDC_ERR_HIP;
-  std::vector<int64_t> prob(5 * std::max<int64_t>(1, batch), 0);
-  for (int64_t i = 0; i < batch; ++i) {
-    prob[i] = pn[i];
-    prob[batch + i] = pvec[i];
-    prob[2 * batch + i] = pmat[i];
-    prob[3 * batch + i] = pcol[i];
-    prob[4 * batch + i] = ptile[i];
-  }
-  if (batch > 0 && hipMemcpy(p.dev_prob, prob.data(), sizeof(int64_t) * 5 * batch, hipMemcpyHostToDevice) != hipSuccess)
+  if (id > 0 && hipMemcpy(nodes_dev, hp.nodes.data(), sizeof(NodeDesc) * id, hipMemcpyHostToDevice) != hipSuccess)
+    return free_plan(p), BDC_ERR_HIP;
+  if (batch > 0 &&
+      hipMemcpy(p.dev_prob, hp.prob.data(), sizeof(int64_t) * 5 * batch, hipMemcpyHostToDevice) != hipSuccess)
     return free_plan(p), BDC_ERR_HIP;
   int off = 0;
-  for (size_t hh = 1; hh < by_h.size(); ++hh) {
+  for (size_t hh = 0; hh < hp.level_count.size(); ++hh) {
     Level L;
-    L.nnodes = (int)by_h[hh].size();
+    L.nnodes = hp.level_count[hh];
+    L.max_m = hp.level_max_m[hh];
     L.dev = nodes_dev + off;
-    for (auto& nd : by_h[hh]) L.max_m = std::max(L.max_m, nd.m);
     off += L.nnodes;
     p.levels.push_back(L);
   }
