@@ -564,6 +564,11 @@ def backtr_leg(steps: int) -> dict:
             "frac_of_fp64_mfma_peak": fl / (ms * 1e-3) / PEAK_FP64_MFMA}
 
 
+def progress(msg: str) -> None:
+    """One line per finished leg on stderr (the JSON line stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -609,6 +614,7 @@ def main():
     info, stats = solver.info()
     cur_tuning = solver.tuning()
     solver.close()
+    progress(f"headline: {ms:.3f} ms per solve (default options {ms_default:.3f} ms)")
 
     def tuned_solver(**kw):
         s = Solver(0, **kw)
@@ -619,6 +625,7 @@ def main():
     # timed region 2: the same steps launched kernel by kernel, each launch
     # bracketed by HIP events on the solve's stream (per-kernel durations)
     kinds, ms_events, _ = timed_kinds({}, tuning, dt, et, out, args.steps)
+    progress(f"kernel-by-kernel: {ms_events:.3f} ms per solve")
 
     acc_fp64 = accuracy(d, e, sig, ub.T, vb.T)
     ref = golden_sigma("oracle_sigma_n16384_normal.npy") if headline else None
@@ -643,6 +650,7 @@ def main():
         if ref is not None:
             split.update(sigma_errors(sig, ref))
         split.update(accuracy(d, e, sig, ub.T, vb.T))
+        progress(f"split products: {ms_sp:.3f} ms per solve")
 
     # the same solves with the learned start
     learned = None
@@ -666,6 +674,7 @@ def main():
         learned["learned_min_n"] = int(ls.options.learned_min_n)
         learned["secular_iters_per_root_gated"] = stats_l["secular_evals"] / max(stats_l["roots"], 1)
         ls.close()
+        progress(f"learned start: {learned['ms_per_step']:.3f} ms per solve")
 
     flops = executed_flops(stats)
     nominal = (8.0 / 3.0) * n ** 3
@@ -733,13 +742,18 @@ def main():
         d5, e5 = inputs.workload("n32768_normal")
         line["config5"] = {"workload": WORKLOADS["n32768_normal"][0],
                            **plain_vs_learned(d5, e5, max(2, args.steps // 3), 1, tuning)}
+        progress("n = 32768 plain/learned done")
     if headline and not args.no_control:
         line["control"] = control_leg(max(2, args.steps // 5), 1)
+        progress("d = e = 1 control done")
     if headline and not args.no_batch:
         line["batch2000"] = batch_leg(args.steps, args.warmup)
+        progress("2000-problem batch done")
     if headline and not args.no_backtr:
         line["back_transformation"] = backtr_leg(2)
+        progress("back-transformation done")
     if not args.no_cpu_baseline:
+        progress(f"CPU oracle at n = {args.cpu_n} starting")
         line["cpu_baseline"] = cpu_baseline(args.cpu_n, flops if args.cpu_n == n and headline else None)
     print(json.dumps(line), flush=True)
 
