@@ -123,3 +123,35 @@ def cwy_t_inverse(Y: np.ndarray, tau: np.ndarray) -> np.ndarray:
     Ti = np.triu(G, 1)
     Ti[np.diag_indices_from(Ti)] = 1.0 / tau
     return Ti
+
+
+def qr(A: np.ndarray):
+    """Unblocked Householder QR of A (m x n, m >= n): the reflector of
+    Section 4.1 applied column by column, H_i eliminating below the diagonal
+    of column i and updating the trailing columns as soon as it is formed
+    (the panel step of LAPACK's geqrf named in Section 4.3.1, with no
+    blocking).
+
+    Returns (R, Y, tau): R (n x n upper triangular), Y (m x n) the reflectors
+    as full vectors (column i: zeros above row i, 1 at row i), tau (n).
+    A = Q [R; 0] with Q = H_0 H_1 ... H_{n-1}, H_i = I - tau_i y_i y_i^T."""
+    A = np.array(A, dtype=np.float64)
+    m, n = A.shape
+    assert m >= n
+    Y = np.zeros((m, n))
+    tau = np.zeros(n)
+    for i in range(n):
+        y, t, beta = reflector(A[i:, i])
+        Y[i:, i] = y
+        tau[i] = t
+        A[i:, i:] -= t * np.outer(y, y @ A[i:, i:])  # A <- H_i A
+        A[i, i] = beta
+        A[i + 1:, i] = 0.0
+    return np.triu(A[:n, :]), Y, tau
+
+
+def form_q(Y: np.ndarray, tau: np.ndarray, ncols: int) -> np.ndarray:
+    """The first ncols columns of Q = H_0 ... H_{k-1} (eq. orgqr-q: the
+    reflectors applied to the leading columns of the identity)."""
+    m = Y.shape[0]
+    return apply_q(Y, tau, np.eye(m)[:, :ncols])

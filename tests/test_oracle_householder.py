@@ -96,3 +96,38 @@ def test_pack_lapack_layout():
         assert np.all(Pq[:i + 1, i] == 0.0) and np.array_equal(Pq[i + 1:, i], Yq[i + 1:, i])
     for i in range(5):
         assert np.all(Pp[:i + 2, i] == 0.0) and np.array_equal(Pp[i + 2:, i], Yp[i + 2:, i])
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (7, 3), (60, 60), (300, 40), (129, 65)])
+def test_qr_against_lapack_geqrf_orgqr(m, n):
+    """The oracle's QR against LAPACK's geqrf (same reflector convention:
+    unit pivot, beta = -sign(alpha) ||x||): R, the reflectors and tau agree
+    to rounding; Q against orgqr; A = Q R and Q^T Q = I."""
+    g = np.random.default_rng(m * 13 + n)
+    A = g.standard_normal((m, n))
+    R, Y, tau = hh.qr(A)
+    qr_l, tau_l, _, info = lapack.dgeqrf(A)
+    assert info == 0
+    scale = np.max(np.abs(A)) * np.sqrt(m)
+    assert np.max(np.abs(R - np.triu(qr_l[:n, :]))) <= 1e-14 * scale
+    assert np.max(np.abs(tau - tau_l)) <= 1e-14
+    assert np.max(np.abs(np.tril(Y, -1) - np.tril(qr_l, -1)[:, :n])) <= 1e-13 * np.sqrt(m)
+    assert np.allclose(np.triu(Y[:n, :]), np.eye(n), atol=0.0)
+    Q = hh.form_q(Y, tau, n)
+    Q_l, _, info = lapack.dorgqr(qr_l, tau_l)
+    assert info == 0
+    assert np.max(np.abs(Q - Q_l[:, :n])) <= 1e-14 * np.sqrt(m)
+    assert np.max(np.abs(Q @ R - A)) <= 1e-14 * scale
+    assert np.max(np.abs(Q.T @ Q - np.eye(n))) <= 1e-14 * np.sqrt(m)
+
+
+def test_qr_zero_and_reduced_columns():
+    """A column that is already zero below its diagonal takes the identity
+    (tau = 0), as LAPACK does; a zero matrix gives R = 0 and Q = I."""
+    A = np.zeros((6, 3))
+    R, Y, tau = hh.qr(A)
+    assert np.array_equal(tau, np.zeros(3)) and np.array_equal(R, np.zeros((3, 3)))
+    assert np.array_equal(hh.form_q(Y, tau, 3), np.eye(6)[:, :3])
+    B = np.triu(np.arange(1.0, 25.0).reshape(6, 4))[:, :4]
+    R, Y, tau = hh.qr(B)
+    assert np.array_equal(tau, np.zeros(4)) and np.array_equal(R, B[:4])
