@@ -170,6 +170,19 @@ def gkl_bidiagonal(sigma: np.ndarray, seed: int) -> tuple[np.ndarray, np.ndarray
     return d, e, delta
 
 
+def dense_normal(m: int, n: int, seed: int) -> np.ndarray:
+    """A dense m x n matrix with iid N(0, 1) entries, drawn in row-major
+    order (the inputs of the dense routines that surround the bidiagonal
+    solver: QR of a tall matrix, bidiagonal reduction)."""
+    return _rng(seed).standard_normal((m, n))
+
+
+# Seeds of the dense workloads: the tall-and-skinny matrix of Section 5.1
+# (m = 20000, n = 1000) and the square matrices of the reduction.
+DENSE_TS_SEED = BASE_SEED + 700
+DENSE_SQUARE_SEED = BASE_SEED + 800
+
+
 # Named workloads (sizes and spectra of the measured configurations).
 def workload(name: str) -> tuple[np.ndarray, np.ndarray]:
     if name == "n256_uniform":
