@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 2000-problem batch")
     ap.add_argument("--no-backtr", action="store_true", help="skip the back-transformation leg")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch tuning only")
+    ap.add_argument("--gemm", default="fp64", choices=["fp64", "crt", "ozaki"],
+                    help="update-product form of the main timed solves (the library's default is fp64)")
     ap.add_argument("--no-config5", action="store_true", help="skip the n = 32768 plain/learned comparison")
     ap.add_argument("--no-ozaki", action="store_true", help="skip the split-precision comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start comparison")
@@ -604,7 +606,8 @@ def main():
     # timed region 1: the solve as a caller runs it (graph replay), with the
     # default options and after the library's autotuner has picked the leaf
     # size and launch shapes for this workload (outside the timed region)
-    solver = Solver(0)
+    main_kw = {} if args.gemm == "fp64" else {"gemm": args.gemm}
+    solver = Solver(0, **main_kw)
     ms_default = time_solver(solver, dt, et, out, args.steps, args.warmup)
     tuning = None
     if not args.no_autotune:
@@ -624,7 +627,7 @@ def main():
 
     # timed region 2: the same steps launched kernel by kernel, each launch
     # bracketed by HIP events on the solve's stream (per-kernel durations)
-    kinds, ms_events, _ = timed_kinds({}, tuning, dt, et, out, args.steps)
+    kinds, ms_events, _ = timed_kinds(main_kw, tuning, dt, et, out, args.steps)
     progress(f"kernel-by-kernel: {ms_events:.3f} ms per solve")
 
     acc_fp64 = accuracy(d, e, sig, ub.T, vb.T)
@@ -713,7 +716,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "n": n, "leaf_size": cur_tuning["leaf_size"], "secular_start": "plain",
+        "config": {"workload": desc, "n": n, "leaf_size": cur_tuning["leaf_size"], "secular_start": "plain", "gemm": args.gemm,
                    "tuning": cur_tuning},
         "value_definition": "executed FP64 flops per solve (update products + 12 per secular pole term + leaf "
                             "rotations) / ms_per_step",

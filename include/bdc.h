@@ -365,8 +365,10 @@ int bdc_step_gemm_ozaki(bdc_handle_t handle, int slices, int M, int N, int K, co
  * product, and rebuilt by Garner's mixed-radix algorithm.  The scale is the
  * largest one for which the rebuilt product is exact (K <= 2^20), so the
  * error comes only from rounding A and B at about 2^-beta of each row's /
- * column's largest entry, beta = floor((log2 prod m - 1 - log2 K) / 2)
- * (54 with 16 moduli and K = 16384), plus the final rounding to FP64. */
+ * column's largest entry, beta = min(55, floor((log2 prod m - 1 - log2 K) / 2))
+ * (54 with 16 moduli and K = 16384), plus the single final rounding to FP64
+ * (the integer is rebuilt exactly, so exact integer products come out bit
+ * for bit). */
 int bdc_step_gemm_crt(bdc_handle_t handle, int moduli, int M, int N, int K, const double* A, int lda,
                       const double* B, int ldb, double* C, int ldc, bdc_stream_t stream);
 

@@ -248,7 +248,9 @@ class Solver:
         (m, p) float64 tensor whose memory is column-major (pass the .T of a
         contiguous (p, m) tensor)."""
         m, p = C.shape
-        if C.stride(0) != 1 or C.stride(1) < max(1, m):
+        # strides of size-1 dimensions carry no layout (torch sets them freely)
+        ldc = C.stride(1) if p > 1 else max(1, m)
+        if (m > 1 and C.stride(0) != 1) or ldc < max(1, m):
             raise ValueError("C must be column-major (the transpose of a contiguous tensor)")
         k = tau.shape[0]
         if rows:
@@ -256,7 +258,7 @@ class Solver:
         else:
             rs, cs = Y.stride(0), Y.stride(1)
         check("bdc_apply_reflectors", self.lib.bdc_apply_reflectors(
-            self.handle, 1 if trans else 0, m, p, k, offset, _ptr(Y), rs, cs, _ptr(tau), _ptr(C), C.stride(1),
+            self.handle, 1 if trans else 0, m, p, k, offset, _ptr(Y), rs, cs, _ptr(tau), _ptr(C), ldc,
             block, self._stream()))
         return C
 

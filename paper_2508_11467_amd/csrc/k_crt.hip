@@ -13,11 +13,12 @@
 //      exact int32 accumulation, and each sum is reduced mod m_l again;
 //   4. the integer A'B' is rebuilt from its L residues by Garner's
 //      mixed-radix algorithm with balanced digits (every step exact in FP32)
-//      and a Horner sum of the digits in FP64, then scaled back by
-//      2^-(E_r + E_c).
+//      and an exact Horner sum of the digits in 128-bit integers, then
+//      scaled back by 2^-(E_r + E_c) with a single rounding to FP64.
 //
 // beta is chosen so that K 2^(2 beta) <= (M - 1)/2, M = prod m_l, hence
-// |A'B'| lies inside the balanced range and step 4 recovers it exactly.  The
+// |A'B'| lies inside the balanced range and step 4 recovers it exactly; it is
+// capped at 55 so that |A'| <= 2^55 fits the seven bytes step 2 splits it into.  The
 // only roundings are those of A and B to integers (at most half a unit of
 // 2^-beta times the row's / column's largest entry) and the final conversion
 // to FP64.  Residue planes are int8, k contiguous, rows padded to kCrtRowPad
@@ -309,9 +310,41 @@ __global__ __launch_bounds__(256, 1) void k_crt_gemm(const int8_t* __restrict__ 
 
 // ------------------------------------------------------------ 4. rebuild
 // Garner with balanced digits: v_0 = r_0; t_l <- (t_l - v_j) inv(m_j) mod m_l
-// for j < l; then x = v_0 + m_0 (v_1 + m_1 (v_2 + ...)) in FP64.
+// for j < l (every step exact in FP32); then the integer
+// x = v_0 + m_0 (v_1 + m_1 (v_2 + ...)) exactly, in 128-bit two's complement
+// (|x| <= (M - 1) / 2 < 2^127), and x 2^e rounded once to FP64 (to nearest,
+// ties to even): an exact product of integers comes out bit for bit.
+__device__ __forceinline__ double round_i128(long long hi, unsigned long long lo, int e) {
+  const bool neg = hi < 0;
+  unsigned long long uh = (unsigned long long)hi, ul = lo;
+  if (neg) {  // magnitude
+    ul = ~ul + 1ull;
+    uh = ~uh + (ul == 0ull ? 1ull : 0ull);
+  }
+  if (uh == 0ull && ul == 0ull) return 0.0;
+  unsigned long long t;
+  bool sticky;
+  if (uh != 0ull) {
+    const int lz = __clzll((long long)uh);
+    t = lz ? (uh << lz) | (ul >> (64 - lz)) : uh;
+    sticky = lz ? (ul << lz) != 0ull : ul != 0ull;
+    e += 64 - lz;
+  } else {
+    const int lz = __clzll((long long)ul);
+    t = ul << lz;
+    sticky = false;
+    e -= lz;
+  }
+  // |x| 2^e = (t + a fraction below its last bit) 2^e; keep the top 53 bits of t
+  unsigned long long mant = t >> 11;
+  const unsigned int rem = (unsigned int)(t & 0x7FFull);
+  if (rem > 0x400u || (rem == 0x400u && (sticky || (mant & 1ull)))) ++mant;
+  const double v = ldexp((double)mant, e + 11);
+  return neg ? -v : v;
+}
+
 template <int L>
-__device__ __forceinline__ double garner(const int8_t* __restrict__ rc, int64_t planeC) {
+__device__ __forceinline__ double garner(const int8_t* __restrict__ rc, int64_t planeC, int e) {
   float tt[L];
 #pragma unroll
   for (int l = 0; l < L; ++l) tt[l] = (float)rc[l * planeC];
@@ -319,10 +352,20 @@ __device__ __forceinline__ double garner(const int8_t* __restrict__ rc, int64_t 
   for (int j = 0; j < L - 1; ++j)
 #pragma unroll
     for (int l = j + 1; l < L; ++l) tt[l] = bal_mod((tt[l] - tt[j]) * kTab.inv[j][l], l);
-  double x = (double)tt[L - 1];
+  // Horner: x <- x m_l + v_l on (hi, lo) = hi 2^64 + lo
+  long long v = (long long)(int)tt[L - 1];
+  long long hi = v < 0 ? -1ll : 0ll;
+  unsigned long long lo = (unsigned long long)v;
 #pragma unroll
-  for (int l = L - 2; l >= 0; --l) x = fma(x, (double)kMod[l], (double)tt[l]);
-  return x;
+  for (int l = L - 2; l >= 0; --l) {
+    const unsigned long long m = (unsigned long long)kMod[l];
+    const unsigned long long plo = lo * m;
+    hi = hi * (long long)m + (long long)__umul64hi(lo, m);
+    v = (long long)(int)tt[l];
+    lo = plo + (unsigned long long)v;
+    hi += (v < 0 ? -1ll : 0ll) + (lo < plo ? 1ll : 0ll);
+  }
+  return round_i128(hi, lo, e);
 }
 
 // Thread: one output element, scaled by 2^-(E_r + E_c).
@@ -333,8 +376,7 @@ __global__ __launch_bounds__(256) void k_crt_combine(const int8_t* __restrict__ 
   const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (g >= (int64_t)M * N) return;
   const int col = (int)(g / M), row = (int)(g % M);
-  const double x = garner<L>(RC + (int64_t)col * ldr + row, planeC);
-  C[row + (int64_t)col * ldc] = ldexp(x, -(ea[row] + eb[col]));
+  C[row + (int64_t)col * ldc] = garner<L>(RC + (int64_t)col * ldr + row, planeC, -(ea[row] + eb[col]));
 }
 
 // ------------------------------------------------------------ vector update of a merge level
@@ -504,8 +546,7 @@ __global__ __launch_bounds__(256) void k_crt_lvl_combine(const NodeDesc* __restr
   const int8_t* C = w.crt.C[h.isV] + (int64_t)nd.r0 * w.crt.ldr + nd.r0 + h.rowoff;
   for (int64_t g = (int64_t)blockIdx.y * 256 + threadIdx.x; g < total; g += (int64_t)gridDim.y * 256) {
     const int c = (int)(g / h.rows), i = (int)(g - (int64_t)c * h.rows);
-    const double x = garner<L>(C + (int64_t)c * w.crt.ldr + i, w.crt.planeC);
-    dst[i + (int64_t)w.scol[vo + c] * nd.ld] = ldexp(x, -(Ea[i] + Eb[c]));
+    dst[i + (int64_t)w.scol[vo + c] * nd.ld] = garner<L>(C + (int64_t)c * w.crt.ldr + i, w.crt.planeC, -(Ea[i] + Eb[c]));
   }
 }
 
@@ -563,8 +604,9 @@ int crt_beta(int L, int P) {
   for (int l = 0; l < L; ++l) lg += std::log2((double)kMod[l]);
   int lk = 0;
   while ((1 << lk) < P) ++lk;
-  // K 2^(2 beta) <= (M - 1) / 2 with a little room for the log2 rounding
-  return (int)std::floor((lg - 1.0 - lk - 1e-9) / 2.0);
+  // K 2^(2 beta) <= (M - 1) / 2 with a little room for the log2 rounding;
+  // at most 55, so that |A'| <= 2^55 fits the seven bytes split16 takes
+  return std::min(kCrtMaxBeta, (int)std::floor((lg - 1.0 - lk - 1e-9) / 2.0));
 }
 
 bool crt_supported(int L) { return L >= kCrtMinMod && L <= kCrtMaxMod; }

@@ -87,6 +87,15 @@ def ones(n: int) -> tuple[np.ndarray, np.ndarray]:
     return np.ones(n), np.ones(max(n - 1, 0))
 
 
+def near_ones(n: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """d, e iid 1 + 0.1 U(-1,1): a perturbed d = e = 1, which keeps most
+    values at every merge (large update products)."""
+    g = _rng(seed)
+    d = 1.0 + 0.1 * g.uniform(-1.0, 1.0, n)
+    e = 1.0 + 0.1 * g.uniform(-1.0, 1.0, max(n - 1, 0))
+    return d, e
+
+
 def batch_sizes(count: int, lo: int, hi: int, seed: int) -> np.ndarray:
     """Sizes n_i = round(exp(U(ln lo, ln hi))), as int64."""
     g = _rng(seed)

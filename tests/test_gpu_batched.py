@@ -163,8 +163,9 @@ def test_autotune_picks_a_valid_tuning(gpu):
         best = s.autotune(sizes, d, e, repeats=1)
         assert best["ms"] > 0 and best["flat"] in (0, 1) and best["small_n"] in (64, 96, 192)
         assert best["leaf_size"] in (8, 12, 16, 20, 24, 32)
+        assert best["tile128"] in (0, 1)
         assert s.tuning() == {k: best[k] for k in ("small_n", "flat", "grid64", "grid128", "sec_small_n",
-                                                    "leaf_size")}
+                                                    "leaf_size", "tile128")}
         sig, U, VT = s.svd_batched(sizes, torch.from_numpy(d), torch.from_numpy(e))
         info, _ = s.info()
         assert info == 0

@@ -21,12 +21,13 @@ def solver(gpu):
 
 
 def beta(L, K):
-    """Largest beta with P 2^(2 beta) <= (M - 1) / 2, P = K rounded up to 64,
-    M the product of the first L moduli (the exactness condition of the
-    rebuilt integer product)."""
+    """Largest beta <= 55 with P 2^(2 beta) <= (M - 1) / 2, P = K rounded up
+    to 64, M the product of the first L moduli (the exactness condition of
+    the rebuilt integer product; 55 keeps the scaled operands within the
+    seven bytes the residues are taken from)."""
     P = max(64, -(-K // 64) * 64)
     lg = sum(math.log2(m) for m in MODULI[:L])
-    return math.floor((lg - 1.0 - math.ceil(math.log2(P)) - 1e-9) / 2.0)
+    return min(55, math.floor((lg - 1.0 - math.ceil(math.log2(P)) - 1e-9) / 2.0))
 
 
 def bound(A, B, L):
@@ -125,17 +126,19 @@ def _checks(d, e, sig, U, VT):
 
 
 @pytest.mark.parametrize("L", [14, 16])
-@pytest.mark.parametrize("name", ["uniform", "ones", "normal"])
+@pytest.mark.parametrize("name", ["uniform", "ones", "near_ones"])
 def test_solve_with_crt_meets_tolerances(gpu, name, L):
     """Whole solves with the int8 residue products on every merge that keeps
-    at least 128 values, against the oracle at the FP64 tolerances."""
+    at least 128 values, against the oracle at the FP64 tolerances (the
+    uniform spectrum keeps at most 98 values per merge at this size, so there
+    the split products never run and the solve is the FP64 one)."""
     import torch
 
     from paper_2508_11467_amd import inputs
     from paper_2508_11467_amd.api import Solver
     n = 2000
     d, e = {"uniform": lambda: inputs.uniform(n, 3), "ones": lambda: inputs.ones(n),
-            "normal": lambda: inputs.normal(n, 4)}[name]()
+            "near_ones": lambda: inputs.near_ones(n, 5)}[name]()
     s = Solver(0, gemm="crt", ozaki_min_n=128, crt_moduli=L)
     try:
         sig, U, VT = s.svd(torch.from_numpy(d), torch.from_numpy(e))
@@ -144,7 +147,7 @@ def test_solve_with_crt_meets_tolerances(gpu, name, L):
         es, res, ou, ov = _checks(d, e, sig.cpu().numpy(), U.cpu().numpy(), VT.cpu().numpy())
         print(f"{name} L={L}: split merges {st['split_merges']} sigma {es:.2e} residual {res:.2e} "
               f"orth {ou:.2e} {ov:.2e}", flush=True)
-        if name != "normal":
+        if name != "uniform":
             assert st["split_merges"] > 0
         assert es <= 1e-13 and res <= 1e-12 and ou <= 1e-12 and ov <= 1e-12
     finally:
