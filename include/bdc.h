@@ -46,7 +46,8 @@ enum {
   BDC_ERR_HIP = -1004,            /* a HIP runtime call failed */
   BDC_ERR_NONFINITE = -1005,      /* (info) d or e holds Inf or NaN */
   BDC_ERR_UNSUPPORTED = -1006,    /* option value not supported by this build */
-  BDC_ERR_NO_MODEL = -1007        /* learned start requested before bdc_mlp_set */
+  BDC_ERR_NO_MODEL = -1007,       /* learned start requested before bdc_mlp_set */
+  BDC_ERR_TOO_LARGE = -1008       /* beyond the fixed scratch of an allocation-free entry point */
 };
 
 /* Start of the secular iteration (options.start). */
@@ -270,6 +271,24 @@ int bdc_step_gemm(bdc_handle_t handle, int M, int N, int K, const double* A, int
 int bdc_apply_reflectors(bdc_handle_t handle, int trans, int m, int p, int k, int offset, const double* Y,
                          int64_t y_rs, int64_t y_cs, const double* tau, double* C, int ldc, int block,
                          bdc_stream_t stream);
+
+/* bdc_apply_reflectors for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results (bit for bit), but the
+ * scratch is a fixed 32 MiB array of device memory per GPU, held until the
+ * process ends, and C is transformed in panels of at most 2048 columns.  No
+ * hipMalloc, hipFree or allocating library call is made.  Limit:
+ * 8 (m b + b^2 + 9 b max(b, min(p, 2048))) + 1024 <= 32 MiB for the block
+ * size b (m <= 47040 with b = 64 and p >= 2048, any k); larger problems return
+ * BDC_ERR_TOO_LARGE before any work is enqueued.  Every call on one GPU shares
+ * that GPU's array (which keeps the last call's contents; nothing in it needs
+ * to start at zero): calls that overlap in time on one GPU, from any handle
+ * or stream, race and must be ordered by the caller.  Returns as
+ * bdc_apply_reflectors, or BDC_ERR_TOO_LARGE, or BDC_ERR_HIP when the
+ * array's address could not be found when the handle was created. */
+int bdc_apply_reflectors_noalloc(bdc_handle_t handle, int trans, int m, int p, int k, int offset,
+                                 const double* Y, int64_t y_rs, int64_t y_cs, const double* tau, double* C,
+                                 int ldc, int block, bdc_stream_t stream);
 
 /* ---- launch tuning ---------------------------------------------------------
  * Launch shapes of the vector-update products.  The autotuner times a small

@@ -16,6 +16,7 @@ BDC_ERR_HIP = -1004
 BDC_ERR_NONFINITE = -1005
 BDC_ERR_UNSUPPORTED = -1006
 BDC_ERR_NO_MODEL = -1007
+BDC_ERR_TOO_LARGE = -1008
 BDC_START_PLAIN = 0
 BDC_START_LEARNED = 1
 BDC_GEMM_FP64 = 0
@@ -116,6 +117,8 @@ SIGNATURES = {
     "bdc_step_gemm_crt": (c_int, [c_vp, c_int, c_int, c_int, c_int, c_vp, c_int, c_vp, c_int, c_vp, c_int, c_vp]),
     "bdc_apply_reflectors": (c_int, [c_vp, c_int, c_int, c_int, c_int, c_int, c_vp, c_i64, c_i64, c_vp, c_vp, c_int,
                                      c_int, c_vp]),
+    "bdc_apply_reflectors_noalloc": (c_int, [c_vp, c_int, c_int, c_int, c_int, c_int, c_vp, c_i64, c_i64, c_vp,
+                                             c_vp, c_int, c_int, c_vp]),
     "bdc_get_tuning": (c_int, [c_vp, ctypes.POINTER(Tuning)]),
     "bdc_set_tuning": (c_int, [c_vp, ctypes.POINTER(Tuning)]),
     "bdc_autotune": (c_int, [c_vp, c_i64, ctypes.POINTER(c_i64), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_int,

@@ -241,12 +241,13 @@ class Solver:
 
     # ---------------------------------------------------------------- back-transformation
     def apply_reflectors(self, Y: torch.Tensor, tau: torch.Tensor, C: torch.Tensor, trans: bool = False,
-                         offset: int = 0, rows: bool = False, block: int = 0) -> torch.Tensor:
+                         offset: int = 0, rows: bool = False, block: int = 0, noalloc: bool = False) -> torch.Tensor:
         """C <- Q C (or Q^T C) in place for Q = H_0 ... H_{k-1}: reflector i
         in column i of Y (rows=False; Y is (m, k)) or row i (rows=True; Y is
         (k, m)), unit pivot at i + offset, stored entries below it.  C is a
         (m, p) float64 tensor whose memory is column-major (pass the .T of a
-        contiguous (p, m) tensor)."""
+        contiguous (p, m) tensor).  noalloc=True calls the allocation-free
+        entry point (fixed per-GPU scratch; same results)."""
         m, p = C.shape
         # strides of size-1 dimensions carry no layout (torch sets them freely)
         ldc = C.stride(1) if p > 1 else max(1, m)
@@ -257,7 +258,8 @@ class Solver:
             rs, cs = Y.stride(1), Y.stride(0)
         else:
             rs, cs = Y.stride(0), Y.stride(1)
-        check("bdc_apply_reflectors", self.lib.bdc_apply_reflectors(
+        name = "bdc_apply_reflectors_noalloc" if noalloc else "bdc_apply_reflectors"
+        check(name, getattr(self.lib, name)(
             self.handle, 1 if trans else 0, m, p, k, offset, _ptr(Y), rs, cs, _ptr(tau), _ptr(C), ldc,
             block, self._stream()))
         return C

@@ -96,6 +96,7 @@ struct bdc_handle_s {
   size_t oz_bytes = 0;
   void* bt_arena = nullptr;   // back-transformation scratch (grown on demand)
   size_t bt_bytes = 0;
+  void* bt_fixed = nullptr;   // this device's fixed scratch (allocation-free back-transformation)
   void* crt_arena = nullptr;  // int8 residue planes (single-problem solves)
   size_t crt_bytes = 0;
   int64_t crt_n = -1;         // problem size the residue planes are laid out for
@@ -614,6 +615,11 @@ int bdc_create(bdc_handle_t* handle, int device, const bdc_options_t* opt) {
   if (!h) return BDC_ERR_NOMEM;
   h->device = device;
   h->opt = o;
+  {
+    // the fixed scratch's address on this device, looked up once per device
+    DeviceGuard g(device);
+    if (g.ok) h->bt_fixed = backtr_fixed_scratch(device);
+  }
   *handle = h;
   return BDC_OK;
 }
@@ -786,22 +792,33 @@ int bdc_clear_timing(bdc_handle_t h) {
 
 // ---- back-transformation -----------------------------------------------------
 
-int bdc_apply_reflectors(bdc_handle_t h, int trans, int m, int p, int k, int offset, const double* Y, int64_t y_rs,
-                         int64_t y_cs, const double* tau, double* C, int ldc, int block, bdc_stream_t stream) {
+namespace {
+// argument checks shared by both back-transformation entry points: BDC_OK to
+// proceed, 1 for an empty call (nothing to do), or the error status
+int reflector_args(bdc_handle_t h, int trans, int m, int p, int k, int offset, const double* Y, int64_t y_rs,
+                   int64_t y_cs, const double* tau, double* C, int ldc, int* block) {
   if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
   if (trans != 0 && trans != 1) return -2;
   if (m < 0) return -3;
   if (p < 0) return -4;
   if (k < 0) return -5;
   if (offset < 0) return -6;
-  if (m == 0 || p == 0 || k == 0) return BDC_OK;
+  if (m == 0 || p == 0 || k == 0) return 1;
   if (!Y) return -7;
   if (y_rs < 1 && y_cs < 1) return -8;
   if (!tau) return -10;
   if (!C) return -11;
   if (ldc < m) return -12;
-  if (block == 0) block = kBtMaxBlock;
-  if (block < 1 || block > kBtMaxBlock) return -13;
+  if (*block == 0) *block = kBtMaxBlock;
+  if (*block < 1 || *block > kBtMaxBlock) return -13;
+  return BDC_OK;
+}
+}  // namespace
+
+int bdc_apply_reflectors(bdc_handle_t h, int trans, int m, int p, int k, int offset, const double* Y, int64_t y_rs,
+                         int64_t y_cs, const double* tau, double* C, int ldc, int block, bdc_stream_t stream) {
+  const int a = reflector_args(h, trans, m, p, k, offset, Y, y_rs, y_cs, tau, C, ldc, &block);
+  if (a != BDC_OK) return a == 1 ? BDC_OK : a;
   DeviceGuard g(h->device);
   if (!g.ok) return BDC_ERR_HIP;
   const size_t bytes = backtr_bytes(m, p, block);
@@ -818,7 +835,25 @@ int bdc_apply_reflectors(bdc_handle_t h, int trans, int m, int p, int k, int off
     h->bt_bytes = bytes;
   }
   hipStream_t st = (hipStream_t)stream;
-  launch_backtr(trans, m, p, k, offset, Y, y_rs, y_cs, tau, C, ldc, block, h->bt_arena, st);
+  launch_backtr(trans, m, p, k, offset, Y, y_rs, y_cs, tau, C, ldc, block, h->bt_arena, p, st);
+  if (hipGetLastError() != hipSuccess) return BDC_ERR_HIP;
+  h->last_stream = st;
+  h->have_call = true;
+  return BDC_OK;
+}
+
+int bdc_apply_reflectors_noalloc(bdc_handle_t h, int trans, int m, int p, int k, int offset, const double* Y,
+                                 int64_t y_rs, int64_t y_cs, const double* tau, double* C, int ldc, int block,
+                                 bdc_stream_t stream) {
+  const int a = reflector_args(h, trans, m, p, k, offset, Y, y_rs, y_cs, tau, C, ldc, &block);
+  if (a != BDC_OK) return a == 1 ? BDC_OK : a;
+  const int panel = std::min(p, kBtFixedPanel);
+  if (backtr_bytes(m, panel, block) > kBtFixedScratchBytes) return BDC_ERR_TOO_LARGE;
+  if (!h->bt_fixed) return BDC_ERR_HIP;  // the scratch address was not found at bdc_create
+  DeviceGuard g(h->device);
+  if (!g.ok) return BDC_ERR_HIP;
+  hipStream_t st = (hipStream_t)stream;
+  launch_backtr(trans, m, p, k, offset, Y, y_rs, y_cs, tau, C, ldc, block, h->bt_fixed, panel, st);
   if (hipGetLastError() != hipSuccess) return BDC_ERR_HIP;
   h->last_stream = st;
   h->have_call = true;
@@ -1096,6 +1131,7 @@ const char* bdc_status_string(int status) {
     case BDC_ERR_NONFINITE: return "input holds Inf or NaN";
     case BDC_ERR_UNSUPPORTED: return "unsupported option";
     case BDC_ERR_NO_MODEL: return "learned start selected but no network parameters were set";
+    case BDC_ERR_TOO_LARGE: return "problem larger than the fixed scratch of the allocation-free entry point";
     default: return status < 0 ? "invalid argument" : "iteration caps reached";
   }
 }

@@ -11,13 +11,26 @@ namespace bdc {
 constexpr int kBtMaxBlock = 64;  // reflectors per block, at most
 constexpr int kBtSlices = 8;     // depth slices of the Y^T products, at most
 
-// scratch bytes of launch_backtr for an m x p matrix and block b
-size_t backtr_bytes(int m, int p, int block);
+// the allocation-free entry point: a fixed 32 MiB of device memory per GPU,
+// C taken in panels of at most 2048 columns
+constexpr size_t kBtFixedScratchBytes = size_t(32) << 20;
+constexpr int kBtFixedPanel = 2048;
+constexpr int kBtMaxDevices = 64;
+
+// scratch bytes of launch_backtr for m rows, column panels of `panel`
+// columns and blocks of `block` reflectors
+size_t backtr_bytes(int m, int panel, int block);
 
 // C (m x p, ldc) <- Q C (trans 0) or Q^T C (trans 1), Q = H_0 ... H_{k-1};
 // reflector i has its unit pivot at row i + offset, zeros above, and entry r
-// below at Y[r * rs + i * cs]; tau[i] = 0 makes H_i the identity
+// below at Y[r * rs + i * cs]; tau[i] = 0 makes H_i the identity.  The
+// columns of C are taken `panel` at a time (every column is transformed on
+// its own, so any panel width gives the same results).
 void launch_backtr(int trans, int m, int p, int k, int offset, const double* Y, int64_t rs, int64_t cs,
-                   const double* tau, double* C, int ldc, int block, void* scratch, hipStream_t st);
+                   const double* tau, double* C, int ldc, int block, void* scratch, int panel, hipStream_t st);
+
+// device address of the fixed scratch on `device` (which must be current),
+// looked up once per device; nullptr if the lookup failed
+void* backtr_fixed_scratch(int device);
 
 }  // namespace bdc

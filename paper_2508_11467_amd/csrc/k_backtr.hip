@@ -13,6 +13,7 @@
 // long m' dimension as their depth (Y^T Y, Y^T C) split it over several
 // workgroups whose partial sums are added in a fixed order (deterministic).
 #include <algorithm>
+#include <mutex>
 
 #include "bdc_internal.h"
 #include "backtr.h"
@@ -243,19 +244,20 @@ __global__ __launch_bounds__(256, 1) void k_bt_update(const double* __restrict__
 
 }  // namespace
 
-size_t backtr_bytes(int m, int p, int block) {
+size_t backtr_bytes(int m, int panel, int block) {
   const size_t slices = kBtSlices;
-  return 8 * ((size_t)m * block + (size_t)block * block + (size_t)block * std::max(p, block) +
-              slices * (size_t)block * std::max(p, block)) + 4 * 256;
+  const size_t w = (size_t)block * std::max(panel, block);
+  return 8 * ((size_t)m * block + (size_t)block * block + w + slices * w) + 4 * 256;
 }
 
 void launch_backtr(int trans, int m, int p, int k, int offset, const double* Y, int64_t rs, int64_t cs,
-                   const double* tau, double* C, int ldc, int block, void* scratch, hipStream_t st) {
+                   const double* tau, double* C, int ldc, int block, void* scratch, int panel, hipStream_t st) {
+  if (panel < 1 || panel > p) panel = p;
   double* Yp = (double*)scratch;
   double* Ti = Yp + (size_t)m * block;
   double* W = Ti + (size_t)block * block;
-  double* P = W + (size_t)block * std::max(p, block);
-  const int64_t pstride = (int64_t)block * std::max(p, block);
+  double* P = W + (size_t)block * std::max(panel, block);
+  const int64_t pstride = (int64_t)block * std::max(panel, block);
   const int nblk = (k + block - 1) / block;
   for (int q = 0; q < nblk; ++q) {
     const int j = trans ? q : nblk - 1 - q;
@@ -274,21 +276,53 @@ void launch_backtr(int trans, int m, int p, int k, int offset, const double* Y, 
                        rows, bw, bw, chunk, P, pstride);
     hipLaunchKernelGGL(k_bt_reduce, dim3((bw * bw + 255) / 256), dim3(256), 0, st, P, pstride, slices,
                        (int64_t)bw * bw, Ti, bw, 1, tau + i0);
-    // W = Y^T C
-    double* Cb = C + r0;
-    hipLaunchKernelGGL(k_bt_ytx, dim3((p + 127) / 128, 1, slices), dim3(256), 0, st, Yp, rows, Cb, (int64_t)ldc,
-                       rows, bw, p, chunk, P, pstride);
-    hipLaunchKernelGGL(k_bt_reduce, dim3((unsigned)(((int64_t)bw * p + 255) / 256)), dim3(256), 0, st, P, pstride,
-                       slices, (int64_t)bw * p, W, bw, 0, tau);
-    // Z = T^{-1} \ W  or  T^{-T} \ W
-    if (trans)
-      hipLaunchKernelGGL(k_bt_trsm<true>, dim3((p + 255) / 256), dim3(256), 0, st, Ti, bw, W, p);
-    else
-      hipLaunchKernelGGL(k_bt_trsm<false>, dim3((p + 255) / 256), dim3(256), 0, st, Ti, bw, W, p);
-    // C -= Y Z
-    hipLaunchKernelGGL(k_bt_update, dim3((rows + 127) / 128, (p + 127) / 128), dim3(256), 0, st, Yp, rows, W, bw,
-                       Cb, (int64_t)ldc, rows, p);
+    // the columns of C in panels of at most `panel` (every column is
+    // transformed on its own, so the panels give the same results)
+    for (int c0 = 0; c0 < p; c0 += panel) {
+      const int pw = std::min(panel, p - c0);
+      double* Cb = C + r0 + (int64_t)c0 * ldc;
+      // W = Y^T C
+      hipLaunchKernelGGL(k_bt_ytx, dim3((pw + 127) / 128, 1, slices), dim3(256), 0, st, Yp, rows, Cb, (int64_t)ldc,
+                         rows, bw, pw, chunk, P, pstride);
+      hipLaunchKernelGGL(k_bt_reduce, dim3((unsigned)(((int64_t)bw * pw + 255) / 256)), dim3(256), 0, st, P,
+                         pstride, slices, (int64_t)bw * pw, W, bw, 0, tau);
+      // Z = T^{-1} \ W  or  T^{-T} \ W
+      if (trans)
+        hipLaunchKernelGGL(k_bt_trsm<true>, dim3((pw + 255) / 256), dim3(256), 0, st, Ti, bw, W, pw);
+      else
+        hipLaunchKernelGGL(k_bt_trsm<false>, dim3((pw + 255) / 256), dim3(256), 0, st, Ti, bw, W, pw);
+      // C -= Y Z
+      hipLaunchKernelGGL(k_bt_update, dim3((rows + 127) / 128, (pw + 127) / 128), dim3(256), 0, st, Yp, rows, W,
+                         bw, Cb, (int64_t)ldc, rows, pw);
+    }
   }
+}
+
+// ---------------------------------------------------------------- fixed scratch
+// Device memory of the allocation-free entry point: one array per GPU, held
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel (on the host the name stands for a host-side shadow, not a device
+// address); it passes the address hipGetSymbolAddress returns for the
+// current device.
+static __device__ __align__(256) char scratch[kBtFixedScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kBtMaxDevices] = {};
+bool g_scratch_done[kBtMaxDevices] = {};
+}  // namespace
+
+void* backtr_fixed_scratch(int device) {
+  if (device < 0 || device >= kBtMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_done[device]) {
+    // once per device, with that device current (the caller's guard)
+    void* ptr = nullptr;
+    const hipError_t rc = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_ptr[device] = rc == hipSuccess ? ptr : nullptr;
+    g_scratch_done[device] = true;
+  }
+  return g_scratch_ptr[device];
 }
 
 }  // namespace bdc
