@@ -27,6 +27,11 @@ already resident in HBM.  Prints one JSON line.
             product rate against the roofline, and accuracy against the closed
             form
   batch2000 2000 bidiagonals of uneven sizes in one call
+  back_transformation, tall_skinny_qr, dense_svd  the routines around the
+            bidiagonal solve on the paper's full-SVD path: C <- Q C with
+            16384 reflectors, geqrf + orgqr of a 20000 x 1000 matrix, and the
+            dense 4096 x 4096 SVD (gebrd, the bidiagonal SVD, both
+            back-transformations)
   cpu_baseline  the CPU oracle timed on the headline workload on this host
 """
 
@@ -72,7 +77,13 @@ def parse():
     ap.add_argument("--no-control", action="store_true", help="skip the d = e = 1 control (FP64 vs split)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 2000-problem batch")
     ap.add_argument("--no-backtr", action="store_true", help="skip the back-transformation leg")
+    ap.add_argument("--no-qr", action="store_true", help="skip the tall-and-skinny QR leg")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense SVD (reduction) leg")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch tuning only")
+    ap.add_argument("--tuning", default="",
+                    help="launch tuning to time instead of running the autotuner, as k=v,... (the fields of "
+                         "bdc_tuning_t, e.g. small_n=192,flat=0,grid64=1024,grid128=512,sec_small_n=256,"
+                         "leaf_size=12,tile128=1)")
     ap.add_argument("--gemm", default="fp64", choices=["fp64", "crt", "ozaki"],
                     help="update-product form of the main timed solves (the library's default is fp64)")
     ap.add_argument("--no-config5", action="store_true", help="skip the n = 32768 plain/learned comparison")
@@ -121,7 +132,7 @@ def measured_traffic(workload: str, kind: str):
         return None
     from paper_2508_11467_amd.build import source_hash
     t = json.load(open(path))
-    if t.get("source_hash") != source_hash():
+    if not t.get("source_files") or t.get("source_hash") != source_hash(t["source_files"]):
         return None
     return t.get("traffic_bytes_per_launch")
 
@@ -257,7 +268,11 @@ def bench_batched(args, desc):
     solver = Solver(0)
     ms_default = run(solver, args.steps, args.warmup)
     t0 = time.perf_counter()
-    tuned = solver.autotune(sizes, dt, et, out=out, repeats=2)
+    if args.tuning:
+        tuned = {k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))}
+        solver.set_tuning(**tuned)
+    else:
+        tuned = solver.autotune(sizes, dt, et, out=out, repeats=2)
     tune_s = time.perf_counter() - t0
     ms = run(solver, args.steps, args.warmup)
     info, stats = solver.info()
@@ -444,6 +459,8 @@ def control_leg(steps: int, warmup: int) -> dict:
         info, st = s.info()
         s.close()
         kinds, ms_k, st_k = timed_kinds(kw, None, dt, et, out, 1)
+        if form == "fp64":
+            res["fp64_evals_per_root"] = st["secular_evals"] / max(st["roots"], 1)
         leg = {"ms_per_step": ms, "info": info, "ms_per_step_kernel_by_kernel": ms_k,
                "kernel_ms_per_step": {k: v[0] for k, v in sorted(kinds.items())},
                "update_flops": st["update_flops"], "split_merges": st["split_merges"]}
@@ -466,6 +483,18 @@ def control_leg(steps: int, warmup: int) -> dict:
         leg.update(accuracy(d, e, out[0], out[1].T, out[2].T))
         res[form] = leg
     res["split_speedup"] = res["fp64"]["ms_per_step"] / res["split_int8_crt"]["ms_per_step"]
+    # the learned start on this (low-deflation, large-merge) workload: the
+    # library's default gating and the network on every merge
+    for form, kw in (("learned", {"start": "learned"}), ("learned_every_merge", {"start": "learned",
+                                                                                  "learned_min_n": 0})):
+        s = Solver(0, **kw)
+        ms = time_solver(s, dt, et, out, steps, warmup)
+        info, st = s.info()
+        s.close()
+        res[form] = {"ms_per_step": ms, "info": info,
+                     "secular_iters_per_root": st["secular_evals"] / max(st["roots"], 1), "roots": st["roots"]}
+        res[form].update(sigma_errors(out[0], ref))
+    res["fp64"]["secular_iters_per_root"] = res.pop("fp64_evals_per_root")
     del out
     torch.cuda.empty_cache()
     return res
@@ -566,6 +595,122 @@ def backtr_leg(steps: int) -> dict:
             "frac_of_fp64_mfma_peak": fl / (ms * 1e-3) / PEAK_FP64_MFMA}
 
 
+def qr_leg(steps: int) -> dict:
+    """Tall-and-skinny QR (Section 4.3.1-4.3.2) of the m = 20000, n = 1000
+    N(0,1) matrix: bdc_geqrf (panels on the GPU, trailing updates in the
+    modified compact WY form) and bdc_orgqr (the first n columns of Q), time
+    and FP64 rate (LAPACK's flop counts), with R's diagonal against the
+    oracle's stored values and Q's orthogonality."""
+    import numpy as np
+    import torch
+
+    from paper_2508_11467_amd import inputs
+    from paper_2508_11467_amd.api import Solver
+    m, n = 20000, 1000
+    A0 = inputs.dense_normal(m, n, inputs.DENSE_TS_SEED)
+    dev = torch.device("cuda:0")
+    Ad0 = torch.from_numpy(np.ascontiguousarray(A0.T)).to(dev).T
+    Ad = torch.empty((n, m), dtype=torch.float64, device=dev).T
+    s = Solver(0)
+    Ad.copy_(Ad0)
+    tau = s.geqrf(Ad)
+    Q = s.orgqr(Ad, tau)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        Ad.copy_(Ad0)
+        a.record()
+        tau = s.geqrf(Ad)
+        b.record()
+    torch.cuda.synchronize()
+    ms_qr = sum(a.elapsed_time(b) for a, b in ev) / steps
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        Q = s.orgqr(Ad, tau)
+    b.record()
+    torch.cuda.synchronize()
+    ms_q = a.elapsed_time(b) / steps
+    s.close()
+    fl = 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
+    out = {"workload": f"m = {m}, n = {n}, iid N(0,1), seed {inputs.DENSE_TS_SEED}, panels of 32 (geqrf), blocks of "
+                       "64 (orgqr)",
+           "geqrf_ms": ms_qr, "geqrf_tflops": fl / ms_qr / 1e9, "orgqr_ms": ms_q, "orgqr_tflops": fl / ms_q / 1e9,
+           "flops_each": fl}
+    gold = golden_sigma("oracle_qr_ts20000x1000.npy")
+    if gold is not None:
+        out["diag_R_max_abs_err_vs_oracle"] = float(np.max(np.abs(torch.diagonal(Ad[:n, :]).cpu().numpy() - gold[0])))
+    Qc = Q.contiguous()
+    out["orth_Q"] = float(torch.max(torch.abs(Qc.T.contiguous() @ Qc - torch.eye(n, dtype=torch.float64,
+                                                                                   device=dev))))
+    del Ad, Ad0, Q, Qc
+    torch.cuda.empty_cache()
+    return out
+
+
+def dense_svd_leg(n: int, steps: int) -> dict:
+    """The dense square SVD on the GPU (Sections 4.1-4.3): bdc_gebrd (the
+    merged-rank-(2b) reduction), bdc_svd of the bidiagonal, and the
+    back-transformations U = Q [U_2], V = P V_2 (bdc_apply_reflectors), on an
+    n x n N(0,1) matrix; time of the reduction alone and of the whole SVD,
+    the reduction's FP64 rate ((8/3) n^3 flops), E_svd and orthogonality."""
+    import numpy as np
+    import torch
+
+    from paper_2508_11467_amd import inputs
+    from paper_2508_11467_amd.api import Solver
+    dev = torch.device("cuda:0")
+    A0 = inputs.dense_normal(n, n, inputs.DENSE_SQUARE_SEED)
+    Ad0 = torch.from_numpy(np.ascontiguousarray(A0.T)).to(dev).T
+    Ad = torch.empty((n, n), dtype=torch.float64, device=dev).T
+    U = torch.empty((n, n), dtype=torch.float64, device=dev).T
+    V = torch.empty((n, n), dtype=torch.float64, device=dev).T
+    s = Solver(0)
+
+    def pipeline():
+        d, e, tq, tp = s.gebrd(Ad)
+        sig, U2, VT2 = s.svd(d, e)
+        U.copy_(U2)
+        V.copy_(VT2.T)
+        s.apply_reflectors(Ad, tq, U, trans=False, offset=0)
+        s.apply_reflectors(Ad, tp[:n - 1], V, trans=False, offset=1, rows=True)
+        return sig
+
+    Ad.copy_(Ad0)
+    pipeline()
+    torch.cuda.synchronize()
+    ev_r = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev_r:
+        Ad.copy_(Ad0)
+        a.record()
+        s.gebrd(Ad)
+        b.record()
+    ev_s = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    sig = None
+    for a, b in ev_s:
+        Ad.copy_(Ad0)
+        a.record()
+        sig = pipeline()
+        b.record()
+    torch.cuda.synchronize()
+    s.close()
+    ms_r = sum(a.elapsed_time(b) for a, b in ev_r) / steps
+    ms_s = sum(a.elapsed_time(b) for a, b in ev_s) / steps
+    At = torch.from_numpy(A0).to(dev)
+    e_svd = float(torch.linalg.norm(At - (U * sig[None, :]) @ V.T.contiguous()) / torch.linalg.norm(At))
+    I = torch.eye(n, dtype=torch.float64, device=dev)
+    Uc, Vc = U.contiguous(), V.contiguous()
+    orth = max(float(torch.max(torch.abs(Uc.T.contiguous() @ Uc - I))),
+               float(torch.max(torch.abs(Vc.T.contiguous() @ Vc - I))))
+    fl = 8.0 / 3.0 * n ** 3
+    out = {"workload": f"n = {n} square, iid N(0,1), seed {inputs.DENSE_SQUARE_SEED}",
+           "gebrd_ms": ms_r, "gebrd_tflops": fl / ms_r / 1e9, "svd_ms": ms_s,
+           "svd_share_gebrd": ms_r / ms_s, "E_svd": e_svd, "orth": orth}
+    del Ad, Ad0, U, V, At, Uc, Vc
+    torch.cuda.empty_cache()
+    return out
+
+
 def progress(msg: str) -> None:
     """One line per finished leg on stderr (the JSON line stays alone on stdout)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -610,7 +755,10 @@ def main():
     solver = Solver(0, **main_kw)
     ms_default = time_solver(solver, dt, et, out, args.steps, args.warmup)
     tuning = None
-    if not args.no_autotune:
+    if args.tuning:
+        tuning = {k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))}
+        solver.set_tuning(**tuning)
+    elif not args.no_autotune:
         tuned = solver.autotune([n], dt, et, out=out, repeats=2)
         tuning = {k: v for k, v in tuned.items() if k != "ms"}
     ms = time_solver(solver, dt, et, out, args.steps, args.warmup)
@@ -755,6 +903,12 @@ def main():
     if headline and not args.no_backtr:
         line["back_transformation"] = backtr_leg(2)
         progress("back-transformation done")
+    if headline and not args.no_qr:
+        line["tall_skinny_qr"] = qr_leg(3)
+        progress("tall-and-skinny QR done")
+    if headline and not args.no_dense:
+        line["dense_svd"] = dense_svd_leg(4096, 2)
+        progress("dense SVD done")
     if not args.no_cpu_baseline:
         progress(f"CPU oracle at n = {args.cpu_n} starting")
         line["cpu_baseline"] = cpu_baseline(args.cpu_n, flops if args.cpu_n == n and headline else None)

@@ -276,10 +276,10 @@ int bdc_apply_reflectors(bdc_handle_t handle, int trans, int m, int p, int k, in
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same arguments, kernels and results (bit for bit), but the
  * scratch is a fixed 32 MiB array of device memory per GPU, held until the
- * process ends, and C is transformed in panels of at most 2048 columns.  No
+ * process ends, and C is transformed in panels of at most 512 columns.  No
  * hipMalloc, hipFree or allocating library call is made.  Limit:
- * 8 (m b + b^2 + 9 b max(b, min(p, 2048))) + 1024 <= 32 MiB for the block
- * size b (m <= 47040 with b = 64 and p >= 2048, any k); larger problems return
+ * 8 (m b + b^2 + 33 b max(b, min(p, 512))) + 1024 <= 32 MiB for the block
+ * size b (m <= 48574 with b = 64 and p >= 512, any k); larger problems return
  * BDC_ERR_TOO_LARGE before any work is enqueued.  Every call on one GPU shares
  * that GPU's array (which keeps the last call's contents; nothing in it needs
  * to start at zero): calls that overlap in time on one GPU, from any handle
@@ -289,6 +289,58 @@ int bdc_apply_reflectors(bdc_handle_t handle, int trans, int m, int p, int k, in
 int bdc_apply_reflectors_noalloc(bdc_handle_t handle, int trans, int m, int p, int k, int offset,
                                  const double* Y, int64_t y_rs, int64_t y_cs, const double* tau, double* C,
                                  int ldc, int block, bdc_stream_t stream);
+
+/* ---- bidiagonal reduction -----------------------------------------------------
+ * The step before the bidiagonal SVD on the paper's dense path (Section 4.1,
+ * Algorithm 1, the merged-rank-(2b) gebrd): B = Q^T A P with Q = H_0 ...
+ * H_{n-1}, P = G_0 ... G_{n-2}.
+ *
+ * bdc_gebrd: A (m x n, column-major, ld lda >= m, m >= n, device) is
+ * overwritten in LAPACK's gebrd storage: d on the diagonal, e on the
+ * superdiagonal, the column reflectors below the diagonal (H_i: unit pivot
+ * at row i) and the row reflectors right of the superdiagonal (G_i: unit
+ * pivot at column i + 1); d (n), e (n - 1), tauq (n), taup (n, taup[n-1] =
+ * 0) are device outputs.  Panels of `block` columns and rows (1..32; 0 = 32)
+ * are reduced by one cooperative grid each (eq. bidiag-y-k3, bidiag-x-k3:
+ * two passes over the panel-start trailing matrix per column, five grid
+ * barriers per column), then the trailing matrix is updated by the one
+ * product A - P Q^T (eq. bidiag-A-trail3) on the FP64 matrix cores.  With
+ * bdc_svd(d, e) = U_2 Sigma V_2^T it gives the dense SVD: U = Q [U_2; 0] by
+ * bdc_apply_reflectors on the column reflectors (y_rs = 1, y_cs = lda,
+ * offset 0, tauq) and V = P V_2 on the row reflectors (y_rs = lda, y_cs = 1,
+ * offset 1, taup).  Returns BDC_OK, -i for argument i, BDC_ERR_NOMEM or
+ * BDC_ERR_HIP. */
+int bdc_gebrd(bdc_handle_t handle, int m, int n, double* A, int lda, double* d, double* e, double* tauq,
+              double* taup, int block, bdc_stream_t stream);
+
+/* ---- tall-and-skinny QR ---------------------------------------------------
+ * The first step of the paper's SVD of a tall matrix (Section 4.3.1-4.3.2):
+ * A = Q R, then the SVD of the small R, and U = Q [U_0; 0].
+ *
+ * bdc_geqrf: A (m x n, column-major, ld lda >= m, m >= n, device) is
+ * overwritten with R on and above the diagonal and the Householder vectors
+ * below it, tau (n, device) with their scalars -- LAPACK's geqrf storage,
+ * H_i = I - tau_i y_i y_i^T with y_i = 1 at row i.  Blocked: panels of
+ * `block` columns (1..64; 0 = 32) are factored on the GPU one column at a
+ * time by a cooperative grid (one grid barrier per column), and the trailing
+ * columns are updated by the panel's reflectors in the modified compact WY
+ * form of eq. inv_t / larft_update (T^{-1} = Y^T Y, gemm, trsm, gemm).  The
+ * rows below a panel's top block must fit the resident grid (at most 160
+ * rows per workgroup: m - j0 - block <= 40960 on a 256-CU device), else
+ * BDC_ERR_TOO_LARGE.  Returns BDC_OK, -i for argument i, BDC_ERR_NOMEM,
+ * BDC_ERR_TOO_LARGE or BDC_ERR_HIP. */
+int bdc_geqrf(bdc_handle_t handle, int m, int n, double* A, int lda, double* tau, int block,
+              bdc_stream_t stream);
+
+/* bdc_orgqr: Q (m x ncols, column-major, ld ldq >= m, device) <- the first
+ * ncols columns of H_0 H_1 ... H_{k-1} (k <= ncols <= m; reflectors as
+ * bdc_geqrf leaves them in A, ld lda), eq. orgqr-q: the identity multiplied
+ * by the blocks of `block` reflectors (1..64; 0 = 64) from the last to the
+ * first, T^{-1} of each block computed afresh (its own block size, not
+ * geqrf's), block j touching only the rows and columns from its first pivot
+ * on.  Returns BDC_OK, -i for argument i, BDC_ERR_NOMEM or BDC_ERR_HIP. */
+int bdc_orgqr(bdc_handle_t handle, int m, int ncols, int k, const double* A, int lda, const double* tau,
+              double* Q, int ldq, int block, bdc_stream_t stream);
 
 /* ---- launch tuning ---------------------------------------------------------
  * Launch shapes of the vector-update products.  The autotuner times a small
@@ -308,9 +360,9 @@ typedef struct {
                       the poles split over four wavefronts */
   int leaf_size;   /* the tree's leaf size (4..32; 0 in bdc_set_tuning keeps the
                       handle's); the paper found 32 best on its GPUs */
-  int tile128;     /* 128 x 128 products with a grid per merge: 0 (default) a
-                      single-buffered LDS tile at one workgroup per CU, 1 a
-                      double-buffered tile at two workgroups per CU */
+  int tile128;     /* 128 x 128 products with a grid per merge: 0 a
+                      single-buffered LDS tile, 1 (default) a double-buffered
+                      tile at two workgroups per CU (bitwise the same sums) */
   float ms;     /* out (bdc_autotune): time per solve of the chosen tuning */
 } bdc_tuning_t;
 

@@ -119,6 +119,9 @@ SIGNATURES = {
                                      c_int, c_vp]),
     "bdc_apply_reflectors_noalloc": (c_int, [c_vp, c_int, c_int, c_int, c_int, c_int, c_vp, c_i64, c_i64, c_vp,
                                              c_vp, c_int, c_int, c_vp]),
+    "bdc_geqrf": (c_int, [c_vp, c_int, c_int, c_vp, c_int, c_vp, c_int, c_vp]),
+    "bdc_gebrd": (c_int, [c_vp, c_int, c_int, c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_int, c_vp]),
+    "bdc_orgqr": (c_int, [c_vp, c_int, c_int, c_int, c_vp, c_int, c_vp, c_vp, c_int, c_int, c_vp]),
     "bdc_get_tuning": (c_int, [c_vp, ctypes.POINTER(Tuning)]),
     "bdc_set_tuning": (c_int, [c_vp, ctypes.POINTER(Tuning)]),
     "bdc_autotune": (c_int, [c_vp, c_i64, ctypes.POINTER(c_i64), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_int,

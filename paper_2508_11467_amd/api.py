@@ -161,7 +161,7 @@ class Solver:
         return d
 
     def set_tuning(self, small_n: int, flat: int, grid64: int, grid128: int, sec_small_n: int = 256,
-                   leaf_size: int = 0, tile128: int = 0, **_ignored) -> None:
+                   leaf_size: int = 0, tile128: int = 1, **_ignored) -> None:
         t = _lib.Tuning(small_n, flat, grid64, grid128, sec_small_n, leaf_size, tile128, 0.0)
         check("bdc_set_tuning", self.lib.bdc_set_tuning(self.handle, ctypes.byref(t)))
 
@@ -263,6 +263,53 @@ class Solver:
             self.handle, 1 if trans else 0, m, p, k, offset, _ptr(Y), rs, cs, _ptr(tau), _ptr(C), ldc,
             block, self._stream()))
         return C
+
+    # ---------------------------------------------------------------- tall-and-skinny QR
+    @staticmethod
+    def _colmajor_ld(X: torch.Tensor, name: str) -> int:
+        """Leading dimension of a (rows, cols) float64 view of column-major
+        memory (the .T of a contiguous (cols, rows) tensor)."""
+        r, c = X.shape
+        ld = X.stride(1) if c > 1 else max(1, r)
+        if X.dtype != torch.float64 or (r > 1 and X.stride(0) != 1) or ld < max(1, r):
+            raise ValueError(f"{name} must be float64 and column-major (the transpose of a contiguous tensor)")
+        return ld
+
+    def gebrd(self, A: torch.Tensor, block: int = 0):
+        """A (m, n), m >= n, column-major float64 on the device, is overwritten
+        with the bidiagonal and the reflectors (LAPACK's gebrd storage);
+        returns (d, e, tauq, taup)."""
+        m, n = A.shape
+        lda = self._colmajor_ld(A, "A")
+        d = torch.empty(n, dtype=torch.float64, device=self.device)
+        e = torch.empty(max(n - 1, 1), dtype=torch.float64, device=self.device)
+        tq = torch.empty(n, dtype=torch.float64, device=self.device)
+        tp = torch.empty(n, dtype=torch.float64, device=self.device)
+        check("bdc_gebrd", self.lib.bdc_gebrd(self.handle, m, n, _ptr(A), lda, _ptr(d), _ptr(e), _ptr(tq), _ptr(tp),
+                                              block, self._stream()))
+        return d, e[:max(n - 1, 0)], tq, tp
+
+    def geqrf(self, A: torch.Tensor, block: int = 0) -> torch.Tensor:
+        """A (m, n), m >= n, column-major float64 on the device, is overwritten
+        with R and the Householder vectors (LAPACK's geqrf storage); returns
+        tau (n)."""
+        m, n = A.shape
+        lda = self._colmajor_ld(A, "A")
+        tau = torch.empty(n, dtype=torch.float64, device=self.device)
+        check("bdc_geqrf", self.lib.bdc_geqrf(self.handle, m, n, _ptr(A), lda, _ptr(tau), block, self._stream()))
+        return tau
+
+    def orgqr(self, A: torch.Tensor, tau: torch.Tensor, ncols: int | None = None, block: int = 0) -> torch.Tensor:
+        """The first ncols (default n) columns of Q = H_0 ... H_{n-1} from
+        geqrf's A and tau, as an (m, ncols) column-major tensor."""
+        m, n = A.shape
+        lda = self._colmajor_ld(A, "A")
+        nc = n if ncols is None else int(ncols)
+        k = tau.shape[0]
+        Q = torch.empty((nc, m), dtype=torch.float64, device=self.device).T
+        check("bdc_orgqr", self.lib.bdc_orgqr(self.handle, m, nc, k, _ptr(A), lda, _ptr(tau), _ptr(Q), max(1, m),
+                                              block, self._stream()))
+        return Q
 
     # ---------------------------------------------------------------- steps
     def step_leaf(self, d, e, s: int):

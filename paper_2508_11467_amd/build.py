@@ -27,23 +27,40 @@ SOURCES = {
     "k_ozaki.hip": [],
     "k_crt.hip": [],
     "k_backtr.hip": [],
+    "k_qr.hip": [],
+    "k_gebrd.hip": [],
     "plan.cpp": [],
     "api.cpp": [],
     "api_steps.cpp": [],
 }
 
 
-def source_hash() -> str:
-    """SHA-256 of the kernel and ABI sources (identifies a build's kernels)."""
+def source_hash(files=None) -> str:
+    """SHA-256 of the kernel and ABI sources (identifies a build's kernels);
+    with `files` (names under csrc/), of those files and the shared device
+    header only (identifies the kernels a measurement was taken of)."""
     import hashlib
     h = hashlib.sha256()
-    for d in (CSRC, INCLUDE):
-        for name in sorted(os.listdir(d)):
-            if name.endswith((".hip", ".h", ".cpp")):
-                h.update(name.encode())
-                with open(os.path.join(d, name), "rb") as f:
-                    h.update(f.read())
+    if files:
+        paths = [os.path.join(CSRC, f) for f in sorted(set(files) | {"bdc_internal.h"})]
+    else:
+        paths = [os.path.join(d, name) for d in (CSRC, INCLUDE) for name in sorted(os.listdir(d))
+                 if name.endswith((".hip", ".h", ".cpp"))]
+    for path in paths:
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def kernel_sources(names) -> list:
+    """The csrc/*.hip files that define the named kernels."""
+    out = set()
+    for fn in sorted(os.listdir(CSRC)):
+        if fn.endswith(".hip"):
+            text = open(os.path.join(CSRC, fn)).read()
+            out.update(fn for k in names if f"void {k}(" in text)
+    return sorted(out)
 
 
 def rocm() -> str:

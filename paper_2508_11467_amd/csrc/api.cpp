@@ -23,12 +23,16 @@
 #include "backtr.h"
 #include "plan.h"
 #include "crt.h"
+#include "qr.h"
+#include "gebrd.h"
 
 using namespace bdc;
 
 namespace {
 
 constexpr uint32_t kMagic = 0xBDC05EEDu;
+constexpr int kQrDefaultBlock = 32;  // panel width of bdc_geqrf when block = 0
+constexpr int kQrMaxGrid = 2048;     // workgroups of a QR panel, at most
 
 enum Kind {
   kReset = 0, kLeaf, kPrep, kRotate, kGather, kStart, kSecular, kLowner, kVectors, kOrder, kUpdate, kUpdateOz,
@@ -97,6 +101,10 @@ struct bdc_handle_s {
   void* bt_arena = nullptr;   // back-transformation scratch (grown on demand)
   size_t bt_bytes = 0;
   void* bt_fixed = nullptr;   // this device's fixed scratch (allocation-free back-transformation)
+  void* qr_sync = nullptr;    // QR panel: grid-barrier state and partial sums
+  size_t qr_sync_size = 0;
+  void* brd_work = nullptr;   // bidiagonal reduction: panel buffers, barrier state, partial sums
+  size_t brd_bytes = 0;
   void* crt_arena = nullptr;  // int8 residue planes (single-problem solves)
   size_t crt_bytes = 0;
   int64_t crt_n = -1;         // problem size the residue planes are laid out for
@@ -350,15 +358,17 @@ int ensure_ozaki(bdc_handle_t h, int64_t n) {
 }
 
 // Residue planes of the int8 split products for one problem of size n: per
-// side (U, V) L planes each of the left operands ((n + 129) rows), of the
-// right operands of the top and bottom halves ((n + 128) rows), all with row
+// side (U, V) L planes each of the left operands ((n + 257) rows), of the
+// right operands of the top and bottom halves ((n + 256) rows), all with row
 // stride P = n rounded up to 64 bytes (the extra rows absorb the over-read of
-// the last 128-row tile), of the products ((n + 1) x (n + 1), column-major),
-// and the per-row maxima and exponents.
+// the last 256-row tile), of the products ((n + 1) x (n + 1), column-major,
+// column stride n + 1 rounded up to 16 bytes), and the per-row maxima and
+// exponents.
 int ensure_crt(bdc_handle_t h, int64_t n) {
   const int L = h->opt.crt_moduli;
   const int64_t P = crt_kpad((int)n);
-  const int64_t planeA = (n + 129) * P, planeB = (n + 128) * P, ldr = n + 1, planeC = ldr * (n + 1);
+  const int64_t planeA = (n + 257) * P, planeB = (n + 256) * P, ldr = (n + 1 + 15) / 16 * 16,
+                planeC = ldr * (n + 1);
   const size_t bytes = 2 * (align_up((size_t)L * planeA) + 2 * align_up((size_t)L * planeB) +
                             align_up((size_t)L * planeC) + 3 * align_up((size_t)(n + 1) * 8) +
                             3 * align_up((size_t)(n + 1) * 4));
@@ -636,6 +646,8 @@ int bdc_destroy(bdc_handle_t h) {
     if (h->oz_arena) (void)hipFree(h->oz_arena);
     if (h->crt_arena) (void)hipFree(h->crt_arena);
     if (h->bt_arena) (void)hipFree(h->bt_arena);
+    if (h->qr_sync) (void)hipFree(h->qr_sync);
+    if (h->brd_work) (void)hipFree(h->brd_work);
     if (h->mlp) (void)hipFree(h->mlp);
     if (h->mlp_pk) (void)hipFree(h->mlp_pk);
     if (h->part) (void)hipFree(h->part);
@@ -815,25 +827,32 @@ int reflector_args(bdc_handle_t h, int trans, int m, int p, int k, int offset, c
 }
 }  // namespace
 
+namespace {
+// the handle's back-transformation scratch, grown to at least `bytes`
+int ensure_bt(bdc_handle_t h, size_t bytes) {
+  if (h->bt_bytes >= bytes) return BDC_OK;
+  if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
+  if (h->bt_arena) (void)hipFree(h->bt_arena);
+  h->bt_arena = nullptr;
+  h->bt_bytes = 0;
+  if (h->opt.workspace_cap_bytes && h->arena_bytes + bytes > h->opt.workspace_cap_bytes) return BDC_ERR_NOMEM;
+  if (hipMalloc(&h->bt_arena, bytes) != hipSuccess) {
+    h->bt_arena = nullptr;
+    return BDC_ERR_NOMEM;
+  }
+  h->bt_bytes = bytes;
+  return BDC_OK;
+}
+}  // namespace
+
 int bdc_apply_reflectors(bdc_handle_t h, int trans, int m, int p, int k, int offset, const double* Y, int64_t y_rs,
                          int64_t y_cs, const double* tau, double* C, int ldc, int block, bdc_stream_t stream) {
   const int a = reflector_args(h, trans, m, p, k, offset, Y, y_rs, y_cs, tau, C, ldc, &block);
   if (a != BDC_OK) return a == 1 ? BDC_OK : a;
   DeviceGuard g(h->device);
   if (!g.ok) return BDC_ERR_HIP;
-  const size_t bytes = backtr_bytes(m, p, block);
-  if (h->bt_bytes < bytes) {
-    if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
-    if (h->bt_arena) (void)hipFree(h->bt_arena);
-    h->bt_arena = nullptr;
-    h->bt_bytes = 0;
-    if (h->opt.workspace_cap_bytes && h->arena_bytes + bytes > h->opt.workspace_cap_bytes) return BDC_ERR_NOMEM;
-    if (hipMalloc(&h->bt_arena, bytes) != hipSuccess) {
-      h->bt_arena = nullptr;
-      return BDC_ERR_NOMEM;
-    }
-    h->bt_bytes = bytes;
-  }
+  const int rc = ensure_bt(h, backtr_bytes(m, p, block));
+  if (rc != BDC_OK) return rc;
   hipStream_t st = (hipStream_t)stream;
   launch_backtr(trans, m, p, k, offset, Y, y_rs, y_cs, tau, C, ldc, block, h->bt_arena, p, st);
   if (hipGetLastError() != hipSuccess) return BDC_ERR_HIP;
@@ -854,6 +873,110 @@ int bdc_apply_reflectors_noalloc(bdc_handle_t h, int trans, int m, int p, int k,
   if (!g.ok) return BDC_ERR_HIP;
   hipStream_t st = (hipStream_t)stream;
   launch_backtr(trans, m, p, k, offset, Y, y_rs, y_cs, tau, C, ldc, block, h->bt_fixed, panel, st);
+  if (hipGetLastError() != hipSuccess) return BDC_ERR_HIP;
+  h->last_stream = st;
+  h->have_call = true;
+  return BDC_OK;
+}
+
+// ---- tall-and-skinny QR ---------------------------------------------------------
+
+int bdc_geqrf(bdc_handle_t h, int m, int n, double* A, int lda, double* tau, int block, bdc_stream_t stream) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  if (m < 0) return -2;
+  if (n < 0 || n > m) return -3;
+  if (m == 0 || n == 0) return BDC_OK;
+  if (!A) return -4;
+  if (lda < m) return -5;
+  if (!tau) return -6;
+  if (block == 0) block = kQrDefaultBlock;
+  if (block < 1 || block > qr_max_block()) return -7;
+  DeviceGuard g(h->device);
+  if (!g.ok) return BDC_ERR_HIP;
+  int rc = ensure_bt(h, backtr_bytes(m, n, block));
+  if (rc != BDC_OK) return rc;
+  const size_t sb = qr_sync_bytes(kQrMaxGrid);
+  if (h->qr_sync_size < sb) {
+    if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
+    if (h->qr_sync) (void)hipFree(h->qr_sync);
+    h->qr_sync = nullptr;
+    h->qr_sync_size = 0;
+    if (hipMalloc(&h->qr_sync, sb) != hipSuccess) {
+      h->qr_sync = nullptr;
+      return BDC_ERR_NOMEM;
+    }
+    h->qr_sync_size = sb;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  rc = launch_geqrf(h->device, m, n, A, lda, tau, block, h->qr_sync, h->qr_sync_size, h->bt_arena, st);
+  if (rc != BDC_OK) return rc;
+  if (hipGetLastError() != hipSuccess) return BDC_ERR_HIP;
+  h->last_stream = st;
+  h->have_call = true;
+  return BDC_OK;
+}
+
+int bdc_orgqr(bdc_handle_t h, int m, int ncols, int k, const double* A, int lda, const double* tau, double* Q, int ldq,
+              int block, bdc_stream_t stream) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  if (m < 0) return -2;
+  if (ncols < 0 || ncols > m) return -3;
+  if (k < 0 || k > ncols) return -4;
+  if (m == 0 || ncols == 0) return BDC_OK;
+  if (k > 0 && !A) return -5;
+  if (lda < m) return -6;
+  if (k > 0 && !tau) return -7;
+  if (!Q) return -8;
+  if (ldq < m) return -9;
+  if (block == 0) block = kBtMaxBlock;
+  if (block < 1 || block > kBtMaxBlock) return -10;
+  DeviceGuard g(h->device);
+  if (!g.ok) return BDC_ERR_HIP;
+  const int rc = ensure_bt(h, backtr_bytes(m, ncols, block));
+  if (rc != BDC_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  launch_orgqr(m, ncols, k, A, lda, tau, Q, ldq, block, h->bt_arena, st);
+  if (hipGetLastError() != hipSuccess) return BDC_ERR_HIP;
+  h->last_stream = st;
+  h->have_call = true;
+  return BDC_OK;
+}
+
+// ---- bidiagonal reduction -------------------------------------------------------
+
+int bdc_gebrd(bdc_handle_t h, int m, int n, double* A, int lda, double* d, double* e, double* tauq, double* taup,
+              int block, bdc_stream_t stream) {
+  if (!valid(h)) return BDC_ERR_INVALID_HANDLE;
+  if (m < 0) return -2;
+  if (n < 0 || n > m) return -3;
+  if (m == 0 || n == 0) return BDC_OK;
+  if (!A) return -4;
+  if (lda < m) return -5;
+  if (!d) return -6;
+  if (!e && n > 1) return -7;
+  if (!tauq) return -8;
+  if (!taup) return -9;
+  if (block == 0) block = gebrd_max_block();
+  if (block < 1 || block > gebrd_max_block()) return -10;
+  DeviceGuard g(h->device);
+  if (!g.ok) return BDC_ERR_HIP;
+  const size_t bytes = gebrd_work_bytes(m, n, block, kQrMaxGrid);
+  if (h->brd_bytes < bytes) {
+    if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
+    if (h->brd_work) (void)hipFree(h->brd_work);
+    h->brd_work = nullptr;
+    h->brd_bytes = 0;
+    if (h->opt.workspace_cap_bytes && h->arena_bytes + bytes > h->opt.workspace_cap_bytes) return BDC_ERR_NOMEM;
+    if (hipMalloc(&h->brd_work, bytes) != hipSuccess) {
+      h->brd_work = nullptr;
+      return BDC_ERR_NOMEM;
+    }
+    h->brd_bytes = bytes;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int rc = launch_gebrd(h->device, m, n, A, lda, tauq, taup, d, e, block, h->brd_work, h->brd_bytes,
+                              kQrMaxGrid, st);
+  if (rc != BDC_OK) return rc;
   if (hipGetLastError() != hipSuccess) return BDC_ERR_HIP;
   h->last_stream = st;
   h->have_call = true;

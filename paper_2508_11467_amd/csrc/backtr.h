@@ -9,12 +9,12 @@
 namespace bdc {
 
 constexpr int kBtMaxBlock = 64;  // reflectors per block, at most
-constexpr int kBtSlices = 8;     // depth slices of the Y^T products, at most
+constexpr int kBtSlices = 32;    // depth slices of the Y^T products, at most
 
 // the allocation-free entry point: a fixed 32 MiB of device memory per GPU,
-// C taken in panels of at most 2048 columns
+// C taken in panels of at most 512 columns
 constexpr size_t kBtFixedScratchBytes = size_t(32) << 20;
-constexpr int kBtFixedPanel = 2048;
+constexpr int kBtFixedPanel = 512;
 constexpr int kBtMaxDevices = 64;
 
 // scratch bytes of launch_backtr for m rows, column panels of `panel`
@@ -25,9 +25,16 @@ size_t backtr_bytes(int m, int panel, int block);
 // reflector i has its unit pivot at row i + offset, zeros above, and entry r
 // below at Y[r * rs + i * cs]; tau[i] = 0 makes H_i the identity.  The
 // columns of C are taken `panel` at a time (every column is transformed on
-// its own, so any panel width gives the same results).
+// its own, so any panel width gives the same results).  The Y^T products
+// split their depth into at most kBtSlices slices (enough for about a
+// thousand workgroups over p columns), added in a fixed order.
 void launch_backtr(int trans, int m, int p, int k, int offset, const double* Y, int64_t rs, int64_t cs,
                    const double* tau, double* C, int ldc, int block, void* scratch, int panel, hipStream_t st);
+
+// C (rows x N, ldc) -= Y (rows x K, ldy) Z (K x N, ldz), column-major, on the
+// FP64 matrix cores
+void launch_sub_product(int rows, int N, int K, const double* Y, int ldy, const double* Z, int ldz, double* C,
+                        int ldc, hipStream_t st);
 
 // device address of the fixed scratch on `device` (which must be current),
 // looked up once per device; nullptr if the lookup failed

@@ -207,7 +207,7 @@ struct Tuning {
   int grid64;   // workgroups of the 64-tile update (flat), or twice the per-node cap
   int grid128;
   int sec_small_n;  // secular problems with N <= this (at most kSecLanesMaxN) use 8 or 16 lanes per root
-  int tile128 = 0;  // 128 x 128 products (per-merge grids): 0 single-buffered tile, 1 double-buffered
+  int tile128 = 1;  // 128 x 128 products (per-merge grids): 0 single-buffered tile, 1 double-buffered (default)
 };
 
 // Workspace layout of tn positions, tn2 matrix entries and nnodes merges

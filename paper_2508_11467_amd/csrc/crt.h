@@ -11,10 +11,10 @@ namespace bdc {
 constexpr int kCrtMinMod = 13, kCrtMaxMod = 16;  // supported numbers of moduli
 constexpr int kCrtMaxBeta = 55;                   // scaled operands are integers of at most 56 bits
 
-// residue planes: k padded to a multiple of 64 (one MFMA k step), rows and
-// columns to a multiple of 128 (one output tile)
+// residue planes: k padded to a multiple of 64 (one k stage of the products),
+// rows and columns to a multiple of 256 (one output tile)
 __host__ __device__ inline int crt_kpad(int K) { return ((K > 0 ? K : 1) + 63) / 64 * 64; }
-__host__ __device__ inline int crt_rowpad(int R) { return ((R > 0 ? R : 1) + 127) / 128 * 128; }
+__host__ __device__ inline int crt_rowpad(int R) { return ((R > 0 ? R : 1) + 255) / 256 * 256; }
 
 // largest beta <= kCrtMaxBeta with P 2^(2 beta) <= (M - 1) / 2 for the first L moduli
 int crt_beta(int L, int P);

@@ -234,12 +234,13 @@ __global__ __launch_bounds__(256) void k_bt_trsm(const double* __restrict__ Ti, 
     if (i < bw) W[i + (int64_t)c * bw] = z[i];
 }
 
-// C (rows x N) -= Yp (rows x bw) Z (bw x N): grid (row tiles, column tiles).
+// C (rows x N) -= Yp (rows x K) Z (K x N, ld ldz): grid (row tiles, column
+// tiles).
 __global__ __launch_bounds__(256, 1) void k_bt_update(const double* __restrict__ Yp, int ldp,
-                                                      const double* __restrict__ Z, int bw, double* __restrict__ C,
-                                                      int64_t ldc, int rows, int N) {
+                                                      const double* __restrict__ Z, int ldz, int K,
+                                                      double* __restrict__ C, int64_t ldc, int rows, int N) {
   __shared__ BtSmem<128> sm;
-  bt_tile<false, 128>(sm, Yp, ldp, Z, bw, rows, N, 0, bw, blockIdx.x * 128, blockIdx.y * 128, SubStore{C, ldc});
+  bt_tile<false, 128>(sm, Yp, ldp, Z, ldz, rows, N, 0, K, blockIdx.x * 128, blockIdx.y * 128, SubStore{C, ldc});
 }
 
 }  // namespace
@@ -269,7 +270,11 @@ void launch_backtr(int trans, int m, int p, int k, int offset, const double* Y, 
     const int64_t ptot = (int64_t)rows * bw;
     hipLaunchKernelGGL(k_bt_pack, dim3((unsigned)std::min<int64_t>((ptot + 255) / 256, 4096)), dim3(256), 0, st, Y,
                        rs, cs, tau, m, i0, bw, offset, Yp, rows);
-    const int slices = std::min(kBtSlices, (rows + 255) / 256);
+    // depth slices: about a thousand workgroups for W = Y^T C over all of
+    // C's columns, at least 256 rows each (a function of rows and p only, so
+    // every panel width sums in the same order)
+    const int ctiles = (p + 127) / 128;
+    const int slices = std::max(1, std::min({kBtSlices, (rows + 255) / 256, (1024 + ctiles - 1) / ctiles}));
     const int chunk = ((rows + slices - 1) / slices + kTK - 1) / kTK * kTK;
     // T^{-1} = Y^T Y (upper part), 1/tau on the diagonal
     hipLaunchKernelGGL(k_bt_ytx, dim3((bw + 127) / 128, 1, slices), dim3(256), 0, st, Yp, rows, Yp, (int64_t)rows,
@@ -293,9 +298,16 @@ void launch_backtr(int trans, int m, int p, int k, int offset, const double* Y, 
         hipLaunchKernelGGL(k_bt_trsm<false>, dim3((pw + 255) / 256), dim3(256), 0, st, Ti, bw, W, pw);
       // C -= Y Z
       hipLaunchKernelGGL(k_bt_update, dim3((rows + 127) / 128, (pw + 127) / 128), dim3(256), 0, st, Yp, rows, W,
-                         bw, Cb, (int64_t)ldc, rows, pw);
+                         bw, bw, Cb, (int64_t)ldc, rows, pw);
     }
   }
+}
+
+void launch_sub_product(int rows, int N, int K, const double* Y, int ldy, const double* Z, int ldz, double* C,
+                        int ldc, hipStream_t st) {
+  if (rows <= 0 || N <= 0 || K <= 0) return;
+  hipLaunchKernelGGL(k_bt_update, dim3((rows + 127) / 128, (N + 127) / 128), dim3(256), 0, st, Y, ldy, Z, ldz, K,
+                     C, (int64_t)ldc, rows, N);
 }
 
 // ---------------------------------------------------------------- fixed scratch

@@ -33,6 +33,7 @@ namespace bdc {
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 
 // ------------------------------------------------------------ moduli tables
 // moduli in descending order; Garner constants inv(m_j) mod m_l (balanced)
@@ -201,97 +202,141 @@ __global__ __launch_bounds__(256) void k_crt_split(const double* __restrict__ X,
 }
 
 // ------------------------------------------------------------ 3. residue products
-// 128 x 128 output tile per 256-thread workgroup, four wavefronts in 2 x 2,
-// each 64 x 64 as 4 x 4 blocks of v_mfma_i32_16x16x64_i8; 64-deep k steps of
-// both residue tiles in LDS (double-buffered, rows padded to 80 bytes so the
-// 16-byte operand reads of a quarter-wavefront hit distinct banks), the next
-// step's global loads issued before the current step's products.
-// Grid: x = output tiles (row tile fastest), z = modulus.  The int32 sums
-// are reduced mod m_l and stored as balanced int8, column-major (ldr rows).
-constexpr int kTile = 128, kKs = 64, kLdsRow = 80;
+// 256 x 128 output tile per 256-thread workgroup: four wavefronts in 2 x 2,
+// each 128 x 64 as 4 x 2 blocks of v_mfma_i32_32x32x32_i8 (the int32 sums
+// of a block stay in 16 accumulation registers per lane).  k advances in
+// 64-byte stages: the residue tiles of a stage (256 and 128 rows of 64 bytes)
+// are copied from global memory straight into LDS by the memory unit
+// (global_load_lds_dwordx4: lane i of an instruction lands at the
+// instruction's LDS base + 16 i), into a ring of four stage buffers, three
+// stages ahead of the one being multiplied; a stage is waited for by the
+// vector-memory counter and one barrier.  In LDS the four 16-byte chunks of
+// row r are stored in the order c ^ f(r), f(r) = ((r >> 1) ^ (r >> 3)) & 3
+// (each lane loads the chunk that belongs at its slot), so the operand reads
+// of 8 or 16 consecutive lanes, which read the same chunk of consecutive
+// rows, fall on distinct banks.  Each lane feeds the matrix cores the 16
+// bytes of chunk 2 kk + (lane >> 5) of row (lane & 31) of its A and B blocks:
+// the products sum over all 32 k of a step whichever lanes hold which k, as
+// long as A and B agree.  The int32 sums are reduced mod m_l and stored as
+// balanced int8, column-major (ldr rows).
+constexpr int kTile = 256, kTileN = 128, kKs = 64, kRing = 4;
+constexpr int kStageA = kTile * kKs, kStageB = kTileN * kKs;  // bytes
 
 struct CrtSmem {
-  int8_t A[2][kTile * kLdsRow];
-  int8_t B[2][kTile * kLdsRow];
+  int8_t A[kRing][kStageA];
+  int8_t B[kRing][kStageB];
 };
 
-// One 128 x 128 tile: A rows row0.., B^T rows col0.. (both k contiguous,
-// stride P, nk k steps); the residue of output (i, j) mod m_l goes to
-// store(i, j, byte) for i < M, j < N (tile-relative bounds).
-template <class Store>
+__device__ __forceinline__ int crt_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+// s_waitcnt with only the vector-memory count set (gfx9 encoding: vmcnt in
+// bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 at their maxima)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// One 256 x 128 tile: A rows row0.., B^T rows col0.. (both k contiguous,
+// stride P, nk stages; the rows up to 255 (A) and 127 (B) past the tile's
+// first ones must be readable), output (i, j) mod m_l at C[j ldr + i] for
+// i < M, j < N (tile-relative bounds).
 __device__ __forceinline__ void crt_tile(CrtSmem& sm, const int8_t* __restrict__ A, const int8_t* __restrict__ B,
-                                         int P, int nk, int M, int N, int l, Store store) {
+                                         int P, int nk, int M, int N, int l, int8_t* __restrict__ C, int64_t ldr) {
   const int t = threadIdx.x, wv = t >> 6, ln = t & 63;
   const int wm = wv & 1, wn = wv >> 1;
-  // global -> LDS: thread t copies 16 bytes of rows t/4 and t/4 + 64
-  const int gr = t >> 2, gc = (t & 3) * 16;
-  v4i ra[2], rb[2];
-  auto gload = [&](int k0) {
+  // slot q * 256 + t of a stage (q = 0..3 for A, 0..1 for B): row slot / 4,
+  // position slot % 4, holding chunk position ^ f(row) of that row
+  const int8_t* ga[4];
+  const int8_t* gb[2];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      ra[h] = *reinterpret_cast<const v4i*>(A + (int64_t)(gr + 64 * h) * P + k0 + gc);
-      rb[h] = *reinterpret_cast<const v4i*>(B + (int64_t)(gr + 64 * h) * P + k0 + gc);
-    }
-  };
-  auto lstore = [&](int buf) {
+  for (int q = 0; q < 4; ++q) {
+    const int slot = q * 256 + t, row = slot >> 2, c = (slot & 3) ^ crt_swz(row);
+    ga[q] = A + (int64_t)row * P + 16 * c;
+    if (q < 2) gb[q] = B + (int64_t)row * P + 16 * c;
+  }
+  // the six copies of stage s into ring buffer s % kRing; the LDS base of an
+  // instruction is uniform over the wavefront
+  auto issue = [&](int s) {
+    const int buf = s & (kRing - 1), k0 = s * kKs;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      *reinterpret_cast<v4i*>(&sm.A[buf][(gr + 64 * h) * kLdsRow + gc]) = ra[h];
-      *reinterpret_cast<v4i*>(&sm.B[buf][(gr + 64 * h) * kLdsRow + gc]) = rb[h];
-    }
+    for (int q = 0; q < 4; ++q)
+      __builtin_amdgcn_global_load_lds(ga[q] + k0, &sm.A[buf][16 * (q * 256 + wv * 64)], 16, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      __builtin_amdgcn_global_load_lds(gb[q] + k0, &sm.B[buf][16 * (q * 256 + wv * 64)], 16, 0, 0);
   };
-  v4i acc[4][4];
+  v16i acc[4][2];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = v4i{0, 0, 0, 0};
-  __syncthreads();  // the previous tile's readers of buffer 0 are done
-  gload(0);
-  lstore(0);
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0;
+  const int lr = ln & 31, lh = ln >> 5;
+  // the previous tile's readers are done with every ring buffer
   __syncthreads();
-  const int li = ln & 15, lq = (ln >> 4) * 16;
+#pragma unroll
+  for (int s = 0; s < kRing - 1; ++s)
+    if (s < nk) issue(s);
   for (int s = 0; s < nk; ++s) {
-    const int buf = s & 1;
-    if (s + 1 < nk) gload((s + 1) * kKs);
-    v4i af[4], bf[4];
+    // stage s has landed (the copies of the stages after it may still fly)
+    if (s + 2 < nk) wait_vm<12>();
+    else if (s + 1 < nk) wait_vm<6>();
+    else wait_vm<0>();
+    // every wavefront's copies of stage s are in, and every wavefront is done
+    // reading the buffer that stage s + 3 reuses (stage s - 1's)
+    __builtin_amdgcn_s_barrier();
+    if (s + kRing - 1 < nk) issue(s + kRing - 1);
+    const int buf = s & (kRing - 1);
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-      af[a] = *reinterpret_cast<const v4i*>(&sm.A[buf][(wm * 64 + a * 16 + li) * kLdsRow + lq]);
+    for (int kk = 0; kk < 2; ++kk) {
+      v4i af[4], bf[2];
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
-      bf[b] = *reinterpret_cast<const v4i*>(&sm.B[buf][(wn * 64 + b * 16 + li) * kLdsRow + lq]);
+      for (int a = 0; a < 4; ++a) {
+        const int row = wm * 128 + a * 32 + lr;
+        af[a] = *reinterpret_cast<const v4i*>(&sm.A[buf][row * kKs + 16 * ((2 * kk + lh) ^ crt_swz(row))]);
+      }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 2; ++b) {
+        const int row = wn * 64 + b * 32 + lr;
+        bf[b] = *reinterpret_cast<const v4i*>(&sm.B[buf][row * kKs + 16 * ((2 * kk + lh) ^ crt_swz(row))]);
+      }
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
-    if (s + 1 < nk) {
-      lstore(buf ^ 1);
-      __syncthreads();
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
   }
-  // D[i][j] of a 16 x 16 block: lane j + 16 (i / 4), register i % 4
+  // D[i][j] of a 32 x 32 block: lane j + 32 h, register r holds row
+  // 8 (r / 4) + 4 h + r % 4: four consecutive rows per register quad
   const double m = (double)kMod[l], im = 1.0 / m;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int col = wn * 64 + b * 16 + li;
-      const int row = wm * 64 + a * 16 + (ln >> 4) * 4;
+    for (int b = 0; b < 2; ++b) {
+      const int col = wn * 64 + b * 32 + lr;
       if (col >= N) continue;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (row + q >= M) break;
-        const double x = (double)acc[a][b][q];
-        store(row + q, col, (int8_t)(int)fma(-rint(x * im), m, x));
+      for (int g = 0; g < 4; ++g) {
+        const int row = wm * 128 + a * 32 + 8 * g + 4 * lh;
+        unsigned int word = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double x = (double)acc[a][b][4 * g + q];
+          const int v = (int)fma(-rint(x * im), m, x);
+          word |= ((unsigned int)v & 255u) << (8 * q);
+        }
+        int8_t* dst = C + (int64_t)col * ldr + row;
+        if (row + 3 < M && (reinterpret_cast<uintptr_t>(dst) & 3) == 0) {
+          *reinterpret_cast<unsigned int*>(dst) = word;
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (row + q < M) dst[q] = (int8_t)(word >> (8 * q));
+        }
       }
     }
 }
-
-struct PlainResStore {
-  int8_t* C;
-  int ldr;
-  __device__ void operator()(int i, int j, int8_t v) const { C[(int64_t)j * ldr + i] = v; }
-};
 
 // Grid: x = output tiles (row tile fastest), z = modulus.  Residues of the
 // products, column-major (ldr rows).
@@ -303,9 +348,9 @@ __global__ __launch_bounds__(256, 1) void k_crt_gemm(const int8_t* __restrict__ 
   const int l = blockIdx.z;
   const int tiles_m = (M + kTile - 1) / kTile;
   const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
-  const int row0 = tm * kTile, col0 = tn * kTile;
+  const int row0 = tm * kTile, col0 = tn * kTileN;
   crt_tile(sm, RA + l * planeA + (int64_t)row0 * P, RB + l * planeB + (int64_t)col0 * P, P, P / kKs, M - row0,
-           N - col0, l, PlainResStore{RC + l * planeC + (int64_t)col0 * ldr + row0, ldr});
+           N - col0, l, RC + l * planeC + (int64_t)col0 * ldr + row0, ldr);
 }
 
 // ------------------------------------------------------------ 4. rebuild
@@ -501,12 +546,6 @@ __global__ __launch_bounds__(256) void k_crt_lvl_splitb(const NodeDesc* __restri
   split16<L>(Mv, ld, 1, st.N, h.K, c, k0, E, out, w.crt.planeB);
 }
 
-struct NodeResStore {
-  int8_t* C;
-  int64_t ldr;
-  __device__ void operator()(int i, int j, int8_t v) const { C[(int64_t)j * ldr + i] = v; }
-};
-
 // Residue products: grid (node, tile slot, sub * L + modulus).
 template <int L>
 __global__ __launch_bounds__(256, 1) void k_crt_lvl_gemm(const NodeDesc* __restrict__ nodes, Work w) {
@@ -521,12 +560,12 @@ __global__ __launch_bounds__(256, 1) void k_crt_lvl_gemm(const NodeDesc* __restr
   const int8_t* B = (h.bottom ? w.crt.Bb[h.isV] : w.crt.Bt[h.isV]) + l * w.crt.planeB + (int64_t)nd.r0 * P;
   int8_t* C = w.crt.C[h.isV] + l * w.crt.planeC + (int64_t)nd.r0 * w.crt.ldr + nd.r0 + h.rowoff;
   const int nk = crt_kpad(h.K) / kKs;
-  const int tiles_m = (h.rows + kTile - 1) / kTile, tiles_n = (st.N + kTile - 1) / kTile;
+  const int tiles_m = (h.rows + kTile - 1) / kTile, tiles_n = (st.N + kTileN - 1) / kTileN;
   for (int tile = blockIdx.y; tile < tiles_m * tiles_n; tile += gridDim.y) {
     const int tm = tile % tiles_m, tn = tile / tiles_m;
-    const int row0 = tm * kTile, col0 = tn * kTile;
+    const int row0 = tm * kTile, col0 = tn * kTileN;
     crt_tile(sm, A + (int64_t)row0 * P, B + (int64_t)col0 * P, P, nk, h.rows - row0, st.N - col0, l,
-             NodeResStore{C + (int64_t)col0 * w.crt.ldr + row0, w.crt.ldr});
+             C + (int64_t)col0 * w.crt.ldr + row0, w.crt.ldr);
   }
 }
 
@@ -564,7 +603,7 @@ void launch_crt_level(const NodeDesc* nodes, int nnodes, int max_m, const Work& 
                      beta, w);
   hipLaunchKernelGGL(k_crt_lvl_splitb<L>, dim3(nnodes, ((kmax + 63) / 64) * kb64, 4), dim3(256), 0, st, nodes, kb64,
                      beta, w);
-  const int tiles = ((rmax + kTile - 1) / kTile) * ((kmax + kTile - 1) / kTile);
+  const int tiles = ((rmax + kTile - 1) / kTile) * ((kmax + kTileN - 1) / kTileN);
   int gy = tiles;
   const int cap = std::max(1, 2048 / std::max(1, nnodes));
   if (gy > cap) gy = cap;
@@ -590,7 +629,7 @@ void gemm_crt_plain_L(int M, int N, int K, const double* A, int lda, const doubl
   k_crt_split<L><<<dim3(Np / 64, P / 64), 256, 0, st>>>(B, ldb, 1, N, K, b.bmax, beta, b.rb, planeB, P, Np, b.eb);
   const int ldr = Mp;
   const int64_t planeC = (int64_t)Mp * N;
-  const int tiles = (Mp / kTile) * (Np / kTile);
+  const int tiles = (Mp / kTile) * (Np / kTileN);
   k_crt_gemm<L><<<dim3(tiles, 1, L), 256, 0, st>>>(b.ra, b.rb, planeA, planeB, P, M, N, b.rc, planeC, ldr);
   const int64_t items = (int64_t)M * N;
   k_crt_combine<L><<<dim3((unsigned)((items + 255) / 256)), 256, 0, st>>>(b.rc, planeC, ldr, M, N, b.ea, b.eb, C,

@@ -75,7 +75,7 @@ def _dispatches(path):
 
 def traffic(fetch_csv, write_csv, kernels, copy_bytes, launches, out_json):
     """LAUNCHES = "auto": the number of dispatches of the first named kernel."""
-    from .build import source_hash
+    from .build import kernel_sources, source_hash
     frags = [k for k in kernels.split(",") if k]
     if launches == "auto":
         launches = sum(1 for n, _ in _dispatches(write_csv) if kernel_label(n) and kernel_label(n).startswith(frags[0]))
@@ -92,7 +92,7 @@ def traffic(fetch_csv, write_csv, kernels, copy_bytes, launches, out_json):
     out = {"kernels": frags, "launches": int(launches), "copy_bytes": int(copy_bytes),
            "fetch": res["fetch"], "write": res["write"],
            "traffic_bytes_per_launch": (res["fetch"]["bytes_per_launch"] or 0) + (res["write"]["bytes_per_launch"] or 0),
-           "source_hash": source_hash()}
+           "source_files": kernel_sources(frags), "source_hash": source_hash(kernel_sources(frags))}
     json.dump(out, open(out_json, "w"), indent=1)
     print(json.dumps(out, indent=1))
 

@@ -37,7 +37,7 @@ def test_noalloc_matches_allocating_entry_point(gpu):
     from paper_2508_11467_amd.api import Solver
     s = Solver(0)
     try:
-        # first call: more columns than one 2048-column panel, blocks of 64;
+        # first call: more columns than one 512-column panel, blocks of 64;
         # second call: smaller, row-stored reflectors with offset 1, Q^T C
         for (m, p, k, seed, trans, offset, rows, block) in ((3000, 2600, 1500, 1, False, 0, False, 0),
                                                             (700, 300, 500, 2, True, 1, True, 32)):
@@ -58,7 +58,7 @@ def test_noalloc_refuses_problems_beyond_its_scratch(gpu):
     from paper_2508_11467_amd.api import Solver
     s = Solver(0)
     try:
-        m, p, k = 70000, 8, 64  # 8 (70000 * 64 + 64^2 + 9 * 64 * 64) + 1024 bytes > 32 MiB
+        m, p, k = 70000, 8, 64  # 8 (70000 * 64 + 64^2 + 33 * 64 * 64) + 1024 bytes > 32 MiB
         Y = torch.zeros((m, k), dtype=torch.float64, device="cuda")
         tau = torch.zeros(k, dtype=torch.float64, device="cuda")
         C = torch.zeros((p, m), dtype=torch.float64, device="cuda").T
