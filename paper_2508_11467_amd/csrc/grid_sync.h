@@ -17,34 +17,35 @@ struct GridSync {
   unsigned pad;
 };
 
-__device__ __forceinline__ double ld_coherent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // All workgroups of the grid meet; returns false if the wait expired.  The
 // writes of every thread before the barrier are visible to every thread
-// after it (device-scope release before, acquire after).
+// after it.  One thread per workgroup arrives: a device-scope release fence
+// (the L2 write-back that makes this XCD's writes visible to the others), a
+// relaxed increment of the counter, and, while the generation has not moved,
+// relaxed coherent polling; then one device-scope acquire fence (the L2
+// invalidate).  Acquire loads inside the poll would invalidate the XCD's L2
+// on every spin and slow every workgroup on it.
 __device__ inline bool grid_barrier(GridSync* s, unsigned nwg, unsigned* sh_ok) {
-  __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned ok = 1;
-    const unsigned g = __hip_atomic_load(&s->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    if (atomicAdd(&s->count, 1u) == nwg - 1) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned g = __hip_atomic_load(&s->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__hip_atomic_fetch_add(&s->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nwg - 1) {
       __hip_atomic_store(&s->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(&s->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       unsigned it = 0;
-      while (__hip_atomic_load(&s->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+      while (__hip_atomic_load(&s->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
         if (++it > kSpin) {
-          atomicExch(&s->expired, 1u);
+          __hip_atomic_store(&s->expired, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           ok = 0;
           break;
         }
         __builtin_amdgcn_s_sleep(1);
       }
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *sh_ok = ok;
   }
   __syncthreads();

@@ -16,11 +16,16 @@
 // where A is the panel-start trailing matrix (its two matrix-vector
 // products are the only passes over it).  One cooperative grid runs the
 // whole panel: workgroup g owns a slice of the rows and a slice of the
-// columns; the phases are separated by grid barriers (five per column), and
-// partial sums cross workgroups through per-workgroup slots added in a fixed
-// order (deterministic).  Storage as LAPACK's gebrd: d and e on the
-// bidiagonal, v below the diagonal (unit pivot at row c), u right of the
-// superdiagonal (unit pivot at column c + 1), tauq, taup.
+// columns, and partial sums cross workgroups through per-workgroup slots
+// added in a fixed order (deterministic).  Two grid barriers per column:
+// the reduction after (a) carries ||x||^2, alpha and P^T x together (P^T v
+// is P's pivot row plus the reflector's scale times P^T x), and the one after
+// (c) carries the row's ||x||^2, alpha and Q^T x.  Until the scale is known
+// the unscaled column (row) stands in P (Q) and every workgroup applies the
+// scale as it reads; the owners scale their stored entries once every
+// workgroup is past the reads (after the next barrier).  Storage as LAPACK's
+// gebrd: d and e on the bidiagonal, v below the diagonal (unit pivot at row
+// c), u right of the superdiagonal (unit pivot at column c + 1), tauq, taup.
 #include <algorithm>
 
 #include "bdc_internal.h"
@@ -36,7 +41,11 @@ constexpr int kBrdMaxB = 32;              // panel width, at most (2b <= 64 colu
 constexpr int kSlot = 2 * kBrdMaxB + 2;   // doubles per workgroup per reduction
 
 struct BrdLds {
-  double q[2 * kBrdMaxB + 2];  // small vectors of the current phase
+  double q[2 * kBrdMaxB + 2];  // partial sums, then totals, of a reduction
+  double qc[2 * kBrdMaxB];     // Q's row c (column c of Q^T)
+  double pc[2 * kBrdMaxB];     // P's row c
+  double pv[2 * kBrdMaxB + 2];  // P^T v, then Q^T u
+  double xa[16];                // x of 16 rows
   double red[4 * 64];
   double sc[8];
   unsigned ok;
@@ -74,156 +83,246 @@ __global__ __launch_bounds__(256, 1) void k_brd_panel(double* __restrict__ A, in
   const int rlo = j0 + g * rows_per_wg, rhi = min(m, rlo + rows_per_wg);
   const int clo = j0 + g * cols_per_wg, chi = min(n, clo + cols_per_wg);
   int phase = 0;
-  auto slot = [&](int q) -> double* { return slots + (size_t)phase * G * kSlot + (size_t)q * kSlot; };
-  // reduce `cnt` values (thread t < cnt holds value t) over the grid; every
-  // thread t < cnt gets the total of value t
-  auto grid_reduce = [&](double* vals_lds, int cnt) -> bool {
-    double* mine = slot(g);
-    for (int q = t; q < cnt; q += 256) mine[q] = vals_lds[q];
+  // L.q[0, cnt) <- its totals over the grid
+  auto grid_reduce = [&](int cnt) -> bool {
+    double* base = slots + (size_t)phase * G * kSlot;
+    for (int q = t; q < cnt; q += 256) base[(size_t)g * kSlot + q] = L.q[q];
     if (!grid_barrier(sync, G, &L.ok)) return false;
-    sum_slots(slots + (size_t)phase * G * kSlot, kSlot, G, cnt, vals_lds, L.red);
+    sum_slots(base, kSlot, G, cnt, L.q, L.red);
     phase ^= 1;
     return true;
   };
+  // the owned columns' entries of the previous row reflector, still unscaled
+  auto scale_u = [&](int cp, double sc) {
+    const int qp = 2 * (cp - j0) + 1;
+    for (int k = max(clo, cp + 2) + t; k < chi; k += 256) {
+      Qt[qp + (int64_t)k * ldq] *= sc;
+      A[cp + (int64_t)k * lda] *= sc;
+    }
+  };
+  double uscale = 0.0;  // scale of the previous column's row reflector
+  bool upend = false;   // its owned entries are still unscaled
   for (int i = 0; i < bw; ++i) {
     const int c = j0 + i, nP = 2 * i;
-    // ---- (a) column c over the owned rows from c down, and ||x below c||^2
-    if (t < nP) L.q[t] = Qt[t + (int64_t)c * ldq];
+    // ---- (a) column c from row c down (owned rows): x = A[:, c] - P Q[c, :]^T,
+    // stored unscaled in A's column c and P's column nP (1 at the pivot)
+    if (t < nP) L.qc[t] = Qt[t + (int64_t)c * ldq];
     __syncthreads();
-    double sg = 0.0;
-    for (int r = max(rlo, c) + t; r < rhi; r += 256) {
-      double a = A[r + (int64_t)c * lda];
-      for (int q = 0; q < nP; ++q) a -= P[r + (int64_t)q * ldp] * L.q[q];
-      A[r + (int64_t)c * lda] = a;
-      if (r > c) sg += a * a;
+    // 16 rows at a time.  Thread (rr, cg) holds P[r, q] for q = cg + 16 j
+    // (registers): first the 2i products of the row, added over the 16
+    // groups in a fixed order, then, once x_r is known, its share of P^T x
+    // (rows below the pivot), added over the 16 rows by a butterfly
+    const int rr = t & 15, cg = t >> 4;
+    double sg = 0.0, al = 0.0;
+    double ptx[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r0 = max(rlo, c); r0 < rhi; r0 += 16) {
+      const int r = r0 + rr;
+      double pr[4], s = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int q = cg + 16 * j;
+        pr[j] = (r < rhi && q < nP) ? P[r + (int64_t)q * ldp] : 0.0;
+        if (q < nP) s += pr[j] * L.qc[q];
+      }
+      L.red[cg * 16 + rr] = s;
+      __syncthreads();
+      if (t < 16) {
+        const int rw = r0 + t;
+        double xr = 0.0;
+        if (rw < rhi) {
+          double acc = 0.0;
+          for (int p = 0; p < 16; ++p) acc += L.red[p * 16 + t];
+          const double a = A[rw + (int64_t)c * lda] - acc;
+          A[rw + (int64_t)c * lda] = a;
+          if (rw > c) {
+            sg += a * a;
+            xr = a;
+            P[rw + (int64_t)nP * ldp] = a;
+          } else {
+            al = a;
+            P[rw + (int64_t)nP * ldp] = 1.0;
+          }
+        }
+        L.xa[t] = xr;
+      }
+      __syncthreads();
+      const double xr = L.xa[rr];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ptx[j] += pr[j] * xr;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double v = ptx[j];
+      for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      const int q = cg + 16 * j;
+      if (rr == 0 && q < nP) L.q[2 + q] = v;
     }
     sg = wg_sum(sg, L.sc);
-    if (t == 0) L.q[0] = sg;
+    al = wg_sum(al, L.sc);  // alpha from the pivot row's owner, 0 elsewhere
+    if (t == 0) {
+      L.q[0] = sg;
+      L.q[1] = al;
+    }
     __syncthreads();
-    if (!grid_reduce(L.q, 1)) return;
-    const double sigma = L.q[0];
-    const Refl h = reflector(A[c + (int64_t)c * lda], sigma);
-    __syncthreads();
-    // ---- (b) v below the pivot (owned rows), P's column nP, and P^T v
-    for (int r = max(rlo, c) + t; r < rhi; r += 256) {
-      if (r == c) {
-        P[r + (int64_t)nP * ldp] = 1.0;
-      } else {
-        const double v = A[r + (int64_t)c * lda] * h.scale;
-        A[r + (int64_t)c * lda] = v;
-        P[r + (int64_t)nP * ldp] = v;
+    if (!grid_reduce(2 + nP)) return;  // also publishes x, P's row c and Q's updates
+    const Refl h = reflector(L.q[1], L.q[0]);
+    if (t < nP) {
+      const double pc = P[c + (int64_t)t * ldp];
+      L.pc[t] = pc;
+      L.pv[t] = pc + h.scale * L.q[2 + t];  // P^T v
+    }
+    if (t == 0) {
+      if (rlo <= c && c < rhi) A[c + (int64_t)c * lda] = h.beta;
+      if (g == 0) {
+        tauq[c] = h.tau;
+        dv[c] = h.beta;
       }
     }
-    __syncthreads();  // v of the owned rows, read below by other threads
-    // partial P^T v over the owned rows (column q of P by wavefront q % 4)
-    for (int q = wv; q < nP; q += 4) {
-      double s = 0.0;
-      for (int r = max(rlo, c) + ln; r < rhi; r += 64) {
-        const double v = r == c ? 1.0 : A[r + (int64_t)c * lda];
-        s += P[r + (int64_t)q * ldp] * v;
-      }
-      s = wave_sum(s);
-      if (ln == 0) L.q[q] = s;
-    }
+    if (upend) scale_u(c - 1, uscale);
+    upend = false;
     __syncthreads();
-    if (!grid_reduce(L.q, nP)) return;  // also publishes v, P's column nP and A's column c
-    if (g == 0 && t == 0) {
-      tauq[c] = h.tau;
-      dv[c] = h.beta;
-    }
-    // ---- y = tau (A^T v - Q (P^T v)) over the owned columns k > c, then row
-    // c over those columns: a_k = A[c, k] - P[c, :] Q[k, :]^T (with v, y)
-    double sg2 = 0.0;
-    {
-      const double pc_v = 1.0;  // P[c, nP]
-      for (int k = max(clo, c + 1) + wv; k < chi; k += 4) {
-        double s = 0.0;
-        for (int r = c + ln; r < m; r += 64) {
-          const double v = r == c ? 1.0 : P[r + (int64_t)nP * ldp];
-          s += A[r + (int64_t)k * lda] * v;
+    // ---- (b) y = tau (A^T v - Q (P^T v)) on the owned columns k > c, and
+    // (c) row c there: x_k = A[c, k] - y_k - P[c, :] Q[k, :]^T, stored
+    // unscaled in A's row c and Q's column nP + 1 (1 at the pivot)
+    // 16 owned columns at a time: every thread accumulates A^T v over its
+    // rows for all 16 (16 loads in flight), added over the waves in a fixed
+    // order; then thread (kk, qg) finishes column kk with q = qg + 16 j of
+    // Q's row (registers): the products with P^T v and P's row c by a
+    // butterfly over the 16 lanes, and its share of Q^T x (q <= nP, Q's
+    // column nP being y) for the columns right of the pivot
+    const int kk = t >> 4, qg = t & 15;
+    double qtx[4] = {0.0, 0.0, 0.0, 0.0};
+    double sg2 = 0.0, al2 = 0.0;
+    for (int kb = max(clo, c + 1); kb < chi; kb += 16) {
+      const int nk = min(16, chi - kb);
+      double acc[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+      for (int r = c + t; r < m; r += 256) {
+        const double v = r == c ? 1.0 : P[r + (int64_t)nP * ldp] * h.scale;
+        const double* Ar = A + r + (int64_t)kb * lda;
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (j < nk) acc[j] += Ar[(int64_t)j * lda] * v;
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const double v = wave_sum(acc[j]);
+        if (ln == 0) L.red[wv * 16 + j] = v;
+      }
+      __syncthreads();
+      const int k = kb + kk;
+      const bool live = kk < nk;  // uniform over each 16-lane group
+      double q4[4], d1 = 0.0, d2 = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int q = qg + 16 * j;
+        q4[j] = (live && q < nP) ? Qt[q + (int64_t)k * ldq] : 0.0;
+        if (q < nP) {
+          d1 += q4[j] * L.pv[q];
+          d2 += L.pc[q] * q4[j];
         }
-        s = wave_sum(s);
-        double y = s;
-        for (int q = 0; q < nP; ++q) y -= Qt[q + (int64_t)k * ldq] * L.q[q];
-        y *= h.tau;
-        double a = A[c + (int64_t)k * lda] - pc_v * y;
-        for (int q = 0; q < nP; ++q) a -= P[c + (int64_t)q * ldp] * Qt[q + (int64_t)k * ldq];
-        if (ln == 0) {
+      }
+      for (int off = 8; off > 0; off >>= 1) {
+        d1 += __shfl_xor(d1, off, 64);
+        d2 += __shfl_xor(d2, off, 64);
+      }
+      if (live) {
+        const double s = (L.red[kk] + L.red[16 + kk]) + (L.red[32 + kk] + L.red[48 + kk]);
+        const double y = h.tau * (s - d1);
+        const double a = A[c + (int64_t)k * lda] - y - d2;
+        if (qg == 0) {
           Qt[nP + (int64_t)k * ldq] = y;
           A[c + (int64_t)k * lda] = a;
+          Qt[nP + 1 + (int64_t)k * ldq] = k == c + 1 ? 1.0 : a;
+          if (k == c + 1)
+            al2 = a;
+          else
+            sg2 += a * a;
         }
-        if (k > c + 1) sg2 += (ln == 0) ? a * a : 0.0;
+        if (k > c + 1) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int q = qg + 16 * j;
+            qtx[j] += (q == nP ? y : q4[j]) * a;
+          }
+        }
       }
+      __syncthreads();  // L.red
     }
     if (c + 1 >= n) {  // the last column: no row reflector
-      // every workgroup has read alpha (before the last reduction); the
-      // diagonal entry is written after the barrier
-      if (!grid_barrier(sync, G, &L.ok)) return;
-      if (g == 0 && t == 0) {
-        A[c + (int64_t)c * lda] = h.beta;
-        taup[c] = 0.0;
+      // nobody else reads this column's unscaled entries (no columns right
+      // of it): scale the owned ones
+      for (int r = max(rlo, c + 1) + t; r < rhi; r += 256) {
+        P[r + (int64_t)nP * ldp] *= h.scale;
+        A[r + (int64_t)c * lda] *= h.scale;
       }
+      if (g == 0 && t == 0) taup[c] = 0.0;
       continue;
     }
+    // Q^T x: over the 4 columns of a wave (lanes 16 and 32 apart), then
+    // over the waves in a fixed order
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double v = qtx[j];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      if (ln < 16) L.red[wv * 64 + qg + 16 * j] = v;
+    }
     sg2 = wg_sum(sg2, L.sc);
-    if (t == 0) L.q[0] = sg2;
+    al2 = wg_sum(al2, L.sc);
+    if (t <= nP) L.q[2 + t] = (L.red[t] + L.red[64 + t]) + (L.red[128 + t] + L.red[192 + t]);
+    if (t == 0) {
+      L.q[0] = sg2;
+      L.q[1] = al2;
+    }
     __syncthreads();
-    if (!grid_reduce(L.q, 1)) return;  // also publishes y and row c
-    const double sigma2 = L.q[0];
-    const Refl gr = reflector(A[c + (int64_t)(c + 1) * lda], sigma2);
-    __syncthreads();
-    // ---- (d) u right of the diagonal (owned columns), Q's column nP + 1,
-    // and Q^T u (columns q = 0..nP of Q)
-    for (int k = max(clo, c + 1) + t; k < chi; k += 256) {
-      if (k == c + 1) {
-        Qt[nP + 1 + (int64_t)k * ldq] = 1.0;
-      } else {
-        const double u = A[c + (int64_t)k * lda] * gr.scale;
-        A[c + (int64_t)k * lda] = u;
-        Qt[nP + 1 + (int64_t)k * ldq] = u;
+    if (!grid_reduce(3 + nP)) return;  // also publishes y and row c
+    const Refl gr = reflector(L.q[1], L.q[0]);
+    if (t <= nP) L.pv[t] = Qt[t + (int64_t)(c + 1) * ldq] + gr.scale * L.q[2 + t];  // Q^T u
+    if (t == 0) {
+      if (clo <= c + 1 && c + 1 < chi) A[c + (int64_t)(c + 1) * lda] = gr.beta;
+      if (g == 0) {
+        taup[c] = gr.tau;
+        ev[c] = gr.beta;
       }
     }
-    __syncthreads();  // u of the owned columns, read below by other threads
-    for (int q = wv; q <= nP; q += 4) {
-      double s = 0.0;
-      for (int k = max(clo, c + 1) + ln; k < chi; k += 64) {
-        const double u = k == c + 1 ? 1.0 : A[c + (int64_t)k * lda];
-        s += Qt[q + (int64_t)k * ldq] * u;
-      }
-      s = wave_sum(s);
-      if (ln == 0) L.q[q] = s;
+    // v: every workgroup has read the unscaled column
+    for (int r = max(rlo, c + 1) + t; r < rhi; r += 256) {
+      P[r + (int64_t)nP * ldp] *= h.scale;
+      A[r + (int64_t)c * lda] *= h.scale;
     }
     __syncthreads();
-    if (!grid_reduce(L.q, nP + 1)) return;  // also publishes u
-    if (g == 0 && t == 0) {
-      taup[c] = gr.tau;
-      ev[c] = gr.beta;
-    }
-    // ---- x = pi (A u - P (Q^T u)) over the owned rows r > c
-    for (int r0 = max(rlo, c + 1); r0 < rhi; r0 += 64) {
-      const int r = r0 + ln;
+    // ---- (d) x = pi (A u - P (Q^T u)) on the owned rows r > c: 16 rows at
+    // a time, the columns of A and of P split over 16 groups of threads, the
+    // 16 partial sums of a row added in a fixed order
+    for (int r0 = max(rlo, c + 1); r0 < rhi; r0 += 16) {
+      const int r = r0 + rr;
       double s = 0.0;
-      if (r < rhi)
-        for (int k = c + 1 + wv; k < n; k += 4) {
-          const double u = k == c + 1 ? 1.0 : Qt[nP + 1 + (int64_t)k * ldq];
+      if (r < rhi) {
+#pragma unroll 4
+        for (int k = c + 1 + cg; k < n; k += 16) {
+          const double u = k == c + 1 ? 1.0 : Qt[nP + 1 + (int64_t)k * ldq] * gr.scale;
           s += A[r + (int64_t)k * lda] * u;
         }
-      L.red[wv * 64 + ln] = s;
+        for (int q = cg; q <= nP; q += 16) s -= P[r + (int64_t)q * ldp] * L.pv[q];
+      }
+      L.red[cg * 16 + rr] = s;
       __syncthreads();
-      if (t < 64 && r < rhi) {
-        double x = (L.red[t] + L.red[64 + t]) + (L.red[128 + t] + L.red[192 + t]);
-        for (int q = 0; q <= nP; ++q) x -= P[r + (int64_t)q * ldp] * L.q[q];
-        P[r + (int64_t)(nP + 1) * ldp] = gr.tau * x;
+      if (t < 16 && r0 + t < rhi) {
+        double x = 0.0;
+        for (int p = 0; p < 16; ++p) x += L.red[p * 16 + t];
+        P[r0 + t + (int64_t)(nP + 1) * ldp] = gr.tau * x;
       }
       __syncthreads();
     }
-    if (!grid_barrier(sync, G, &L.ok)) return;  // publishes x
-    // the diagonal and superdiagonal entries, after every workgroup has read
-    // the alphas they held (nothing reads row c again in this panel)
-    if (g == 0 && t == 0) {
-      A[c + (int64_t)c * lda] = h.beta;
-      A[c + (int64_t)(c + 1) * lda] = gr.beta;
-    }
+    upend = true;
+    uscale = gr.scale;
+  }
+  // the panel's last row reflector: scale once every workgroup has read it
+  if (upend) {
+    if (!grid_barrier(sync, G, &L.ok)) return;
+    scale_u(j0 + bw - 1, uscale);
   }
 }
 
