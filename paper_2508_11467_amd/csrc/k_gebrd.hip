@@ -49,6 +49,7 @@ struct BrdLds {
   double red[4 * 64];
   double sc[8];
   unsigned ok;
+  unsigned sh[2];
 };
 
 struct Refl {
@@ -76,7 +77,8 @@ __global__ __launch_bounds__(256, 1) void k_brd_panel(double* __restrict__ A, in
                                                       double* __restrict__ Qt, int ldq, double* __restrict__ tauq,
                                                       double* __restrict__ taup, double* __restrict__ dv,
                                                       double* __restrict__ ev, double* __restrict__ slots,
-                                                      GridSync* sync, int rows_per_wg, int cols_per_wg) {
+                                                      double* __restrict__ gslots, GridSync* sync, int rows_per_wg,
+                                                      int cols_per_wg) {
   __shared__ BrdLds L;
   const int t = threadIdx.x, G = gridDim.x, g = blockIdx.x;
   const int ln = t & 63, wv = t >> 6;
@@ -86,9 +88,9 @@ __global__ __launch_bounds__(256, 1) void k_brd_panel(double* __restrict__ A, in
   // L.q[0, cnt) <- its totals over the grid
   auto grid_reduce = [&](int cnt) -> bool {
     double* base = slots + (size_t)phase * G * kSlot;
+    double* gbase = gslots + (size_t)phase * grid_group_doubles(kSlot);
     for (int q = t; q < cnt; q += 256) base[(size_t)g * kSlot + q] = L.q[q];
-    if (!grid_barrier(sync, G, &L.ok)) return false;
-    sum_slots(base, kSlot, G, cnt, L.q, L.red);
+    if (!grid_allreduce(sync, base, gbase, kSlot, cnt, L.q, L.red, L.sh)) return false;
     phase ^= 1;
     return true;
   };
@@ -198,12 +200,19 @@ __global__ __launch_bounds__(256, 1) void k_brd_panel(double* __restrict__ A, in
       double acc[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+      // unconditional loads (columns past the owned ones clamped to the last
+      // and not used), so all 16 are in flight before the first product
+      const double* Ab = A + (int64_t)kb * lda;
+      int col[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) col[j] = min(j, nk - 1);
       for (int r = c + t; r < m; r += 256) {
         const double v = r == c ? 1.0 : P[r + (int64_t)nP * ldp] * h.scale;
-        const double* Ar = A + r + (int64_t)kb * lda;
+        double av[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if (j < nk) acc[j] += Ar[(int64_t)j * lda] * v;
+        for (int j = 0; j < 16; ++j) av[j] = Ab[r + (int64_t)col[j] * lda];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] += av[j] * v;
       }
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
@@ -297,16 +306,25 @@ __global__ __launch_bounds__(256, 1) void k_brd_panel(double* __restrict__ A, in
     // a time, the columns of A and of P split over 16 groups of threads, the
     // 16 partial sums of a row added in a fixed order
     for (int r0 = max(rlo, c + 1); r0 < rhi; r0 += 16) {
-      const int r = r0 + rr;
+      // rows past the owned ones are clamped to the last and not used; the
+      // columns go in batches of 16 unconditional loads (past n: clamped)
+      const int r = min(r0 + rr, rhi - 1);
       double s = 0.0;
-      if (r < rhi) {
-#pragma unroll 4
-        for (int k = c + 1 + cg; k < n; k += 16) {
-          const double u = k == c + 1 ? 1.0 : Qt[nP + 1 + (int64_t)k * ldq] * gr.scale;
-          s += A[r + (int64_t)k * lda] * u;
+      for (int k0 = c + 1 + cg; k0 < n; k0 += 256) {
+        double av[16], uv[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int k = min(k0 + 16 * j, n - 1);
+          av[j] = A[r + (int64_t)k * lda];
+          uv[j] = Qt[nP + 1 + (int64_t)k * ldq];
         }
-        for (int q = cg; q <= nP; q += 16) s -= P[r + (int64_t)q * ldp] * L.pv[q];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int k = k0 + 16 * j;
+          if (k < n) s += av[j] * (k == c + 1 ? 1.0 : uv[j] * gr.scale);
+        }
       }
+      for (int q = cg; q <= nP; q += 16) s -= P[r + (int64_t)q * ldp] * L.pv[q];
       L.red[cg * 16 + rr] = s;
       __syncthreads();
       if (t < 16 && r0 + t < rhi) {
@@ -326,21 +344,15 @@ __global__ __launch_bounds__(256, 1) void k_brd_panel(double* __restrict__ A, in
   }
 }
 
-__global__ void k_brd_sync_init(GridSync* s) {
-  if (threadIdx.x == 0) {
-    s->count = 0;
-    s->gen = 0;
-    s->expired = 0;
-    s->pad = 0;
-  }
-}
+__global__ __launch_bounds__(256) void k_brd_sync_init(GridSync* s) { grid_sync_clear(s); }
 
 }  // namespace
 
 int gebrd_max_block() { return kBrdMaxB; }
 
 size_t gebrd_work_bytes(int m, int n, int b, int max_wg) {
-  return 256 + 8 * ((size_t)m * 2 * b + (size_t)2 * b * n + 2 * (size_t)max_wg * kSlot);
+  return kGridSyncBytes +
+         8 * ((size_t)m * 2 * b + (size_t)2 * b * n + 2 * (size_t)max_wg * kSlot + 2 * grid_group_doubles(kSlot));
 }
 
 int launch_gebrd(int device, int m, int n, double* A, int lda, double* tauq, double* taup, double* d, double* e,
@@ -350,15 +362,16 @@ int launch_gebrd(int device, int m, int n, double* A, int lda, double* tauq, dou
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(k_brd_panel), 256, 0) !=
       hipSuccess)
     return BDC_ERR_HIP;
-  const int maxg = std::min(max_wg, std::max(1, cus * std::max(per, 1)));
+  const int maxg = std::min(std::min(max_wg, kGridMaxWg), std::max(1, cus * std::max(per, 1)));
   if (gebrd_work_bytes(m, n, b, maxg) > work_bytes) return BDC_ERR_TOO_LARGE;
   char* w = reinterpret_cast<char*>(work);
   GridSync* sync = reinterpret_cast<GridSync*>(w);
-  double* P = reinterpret_cast<double*>(w + 256);
+  double* P = reinterpret_cast<double*>(w + kGridSyncBytes);
   double* Qt = P + (size_t)m * 2 * b;
   double* slots = Qt + (size_t)2 * b * n;
+  double* gslots = slots + 2 * (size_t)maxg * kSlot;
   const int ldq = 2 * b;
-  hipLaunchKernelGGL(k_brd_sync_init, dim3(1), dim3(64), 0, st, sync);
+  hipLaunchKernelGGL(k_brd_sync_init, dim3(1), dim3(256), 0, st, sync);
   for (int j0 = 0; j0 < n; j0 += b) {
     const int bw = std::min(b, n - j0);
     // at least 16 rows per workgroup
@@ -367,7 +380,7 @@ int launch_gebrd(int device, int m, int n, double* A, int lda, double* tauq, dou
     int64_t lda64 = lda, ldp64 = m;
     int ldq_ = ldq;
     void* args[] = {&A, &lda64, &m, &n, &j0, const_cast<int*>(&bw), &P, &ldp64, &Qt, &ldq_, &tauq, &taup, &d, &e,
-                    &slots, &sync, &rpw, &cpw};
+                    &slots, &gslots, &sync, &rpw, &cpw};
     if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_brd_panel), dim3(G), dim3(256), args, 0, st) !=
         hipSuccess)
       return BDC_ERR_HIP;

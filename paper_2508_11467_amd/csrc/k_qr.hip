@@ -22,10 +22,10 @@
 //      rows -- recomputed by a second grid reduction when that difference
 //      has cancelled by more than 7 bits;
 //   3. X -= tau y w^T on the owned rows and the top block.
-// One grid barrier per column.  The grid barrier is a counter and a
-// generation number in device memory; every wait is bounded (a flag reports
-// an expired wait and the kernel ends), and the launch is cooperative, so
-// all workgroups are resident.
+// One grid all-reduce per column (workgroups meet in groups of 16, each
+// group's sum formed once, in workgroup order); every wait is bounded (a
+// flag reports an expired wait and the kernel ends), and the launch is
+// cooperative, so all workgroups are resident.
 #include <algorithm>
 
 #include "bdc_internal.h"
@@ -46,7 +46,7 @@ struct PanelLds {
   double tot[kQrMaxB + 2];
   double red[4 * (kQrMaxB + 2)];
   double sc[4];
-  unsigned ok;
+  unsigned sh[2];
 };
 
 // Sum over the workgroup of the four wavefront partials of slot q
@@ -56,10 +56,11 @@ __device__ __forceinline__ double red4(const double* red, int q) {
 }
 
 // grid: G workgroups (cooperative), 256 threads.  slots: 2 x G x (64 + 2)
-// doubles.
+// doubles; gslots: 2 x grid_group_doubles(64 + 2).
 __global__ __launch_bounds__(256, 1) void k_qr_panel(double* __restrict__ A, int64_t lda, int m, int j0, int b,
                                                      int rows_per_wg, double* __restrict__ tau,
-                                                     double* __restrict__ slots, GridSync* sync) {
+                                                     double* __restrict__ slots, double* __restrict__ gslots,
+                                                     GridSync* sync) {
   constexpr int S = kQrMaxB + 2;  // slot stride: w partials, then two sums
   __shared__ PanelLds L;
   const int t = threadIdx.x, G = gridDim.x, g = blockIdx.x;
@@ -83,13 +84,13 @@ __global__ __launch_bounds__(256, 1) void k_qr_panel(double* __restrict__ A, int
   // owned-row sum of squares of column c, reduced over the grid (exact)
   auto owned_sq = [&](int c) -> double {
     double* sl = slots + (size_t)phase * G * S;
+    double* gsl = gslots + (size_t)phase * grid_group_doubles(S);
     phase ^= 1;
     double s = 0.0;
     for (int r = t; r < R; r += 256) s += L.X[r * b + c] * L.X[r * b + c];
     s = block_sum(s, L.sc);
     if (t == 0) sl[(size_t)g * S] = s;
-    if (!grid_barrier(sync, G, &L.ok)) return -1.0;
-    sum_slots(sl, S, G, 1, L.tot, L.red);
+    if (!grid_allreduce(sync, sl, gsl, S, 1, L.tot, L.red, L.sh)) return -1.0;
     return L.tot[0];
   };
   // sigma of column 0: everything below its pivot
@@ -122,6 +123,7 @@ __global__ __launch_bounds__(256, 1) void k_qr_panel(double* __restrict__ A, int
       // columns, and for the next column sum x^2 and sum y^2 (owned rows),
       // from which its sigma after the update follows
       double* sl = slots + (size_t)phase * G * S;
+      double* gsl = gslots + (size_t)phase * grid_group_doubles(S);
       phase ^= 1;
       const int k = c + 1 + ln;
       double s = 0.0, sxx = 0.0, syy = 0.0;
@@ -144,8 +146,7 @@ __global__ __launch_bounds__(256, 1) void k_qr_panel(double* __restrict__ A, int
       if (t < nk) sl[(size_t)g * S + t] = red4(L.red, t);
       if (t == 64) sl[(size_t)g * S + nk] = red4(L.red, kQrMaxB);
       if (t == 65) sl[(size_t)g * S + nk + 1] = red4(L.red, kQrMaxB + 1);
-      if (!grid_barrier(sync, G, &L.ok)) return;
-      sum_slots(sl, S, G, nk + 2, L.tot, L.red);
+      if (!grid_allreduce(sync, sl, gsl, S, nk + 2, L.tot, L.red, L.sh)) return;
       if (t < nk) {
         const int kk = c + 1 + t;
         const double tot = L.tot[t];
@@ -206,14 +207,7 @@ __global__ __launch_bounds__(256, 1) void k_qr_panel(double* __restrict__ A, int
     }
 }
 
-__global__ void k_qr_sync_init(GridSync* s) {
-  if (threadIdx.x == 0) {
-    s->count = 0;
-    s->gen = 0;
-    s->expired = 0;
-    s->pad = 0;
-  }
-}
+__global__ __launch_bounds__(256) void k_qr_sync_init(GridSync* s) { grid_sync_clear(s); }
 
 // Q (m x ncols, ldq) = the identity's first ncols columns
 __global__ __launch_bounds__(256) void k_qr_eye(double* __restrict__ Q, int64_t ldq, int m, int ncols) {
@@ -226,7 +220,9 @@ __global__ __launch_bounds__(256) void k_qr_eye(double* __restrict__ Q, int64_t 
 
 }  // namespace
 
-size_t qr_sync_bytes(int max_wg) { return 256 + 2 * (size_t)max_wg * (kQrMaxB + 2) * sizeof(double); }
+size_t qr_sync_bytes(int max_wg) {
+  return kGridSyncBytes + 2 * ((size_t)max_wg * (kQrMaxB + 2) + grid_group_doubles(kQrMaxB + 2)) * sizeof(double);
+}
 
 int qr_max_block() { return kQrMaxB; }
 
@@ -236,7 +232,7 @@ int qr_panel_grid(int device, int rows_below, int* grid, int* rows_per_wg) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(k_qr_panel), 256, 0) !=
       hipSuccess)
     return -1;
-  const int maxg = std::max(1, cus * std::max(per, 1));
+  const int maxg = std::max(1, std::min(kGridMaxWg, cus * std::max(per, 1)));
   // at least 16 rows per workgroup: fewer would spend the panel on barriers
   int G = std::max(1, std::min(maxg, (rows_below + 15) / 16));
   int R = (rows_below + G - 1) / G;
@@ -249,8 +245,8 @@ int qr_panel_grid(int device, int rows_below, int* grid, int* rows_per_wg) {
 int launch_geqrf(int device, int m, int n, double* A, int lda, double* tau, int b, void* sync_buf, size_t sync_bytes,
                  void* bt_scratch, hipStream_t st) {
   GridSync* sync = reinterpret_cast<GridSync*>(sync_buf);
-  double* slots = reinterpret_cast<double*>(reinterpret_cast<char*>(sync_buf) + 256);
-  hipLaunchKernelGGL(k_qr_sync_init, dim3(1), dim3(64), 0, st, sync);
+  double* slots = reinterpret_cast<double*>(reinterpret_cast<char*>(sync_buf) + kGridSyncBytes);
+  hipLaunchKernelGGL(k_qr_sync_init, dim3(1), dim3(256), 0, st, sync);
   for (int j0 = 0; j0 < n; j0 += b) {
     const int bw = std::min(b, n - j0);
     const int top = std::min(bw, m - j0);
@@ -259,7 +255,8 @@ int launch_geqrf(int device, int m, int n, double* A, int lda, double* tau, int 
     if (qr_panel_grid(device, rows_below, &G, &R) != 0) return BDC_ERR_TOO_LARGE;
     if (qr_sync_bytes(G) > sync_bytes) return BDC_ERR_TOO_LARGE;
     int64_t lda64 = lda;
-    void* args[] = {&A, &lda64, &m, &j0, const_cast<int*>(&bw), &R, &tau, &slots, &sync};
+    double* gslots = slots + 2 * (size_t)G * (kQrMaxB + 2);
+    void* args[] = {&A, &lda64, &m, &j0, const_cast<int*>(&bw), &R, &tau, &slots, &gslots, &sync};
     if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_qr_panel), dim3(G), dim3(256), args, 0, st) !=
         hipSuccess)
       return BDC_ERR_HIP;
