@@ -266,6 +266,37 @@ def test_trained_network_cuts_iterations(gpu):
     assert il <= 0.9 * ip
 
 
+@pytest.mark.parametrize("spectrum", ["uniform", "near_ones", "ones"])
+def test_trained_network_iterations_by_spectrum(gpu, spectrum):
+    """The shipped network on every merge against the plain start, n = 2048
+    held-out problems: fewer evaluations per root on spectra with irregular
+    gaps (uniform, a 10%-perturbed d = e = 1); on d = e = 1 itself, whose
+    evenly spread roots sit where the midpoint start is already close, at
+    most 10% more (measured +5%)."""
+    from paper_2508_11467_amd.api import Solver
+    n = 2048
+    d, e = {"uniform": lambda: inputs.uniform(n, inputs.split_seed(2, 0, "valid", 78)),
+            "near_ones": lambda: inputs.near_ones(n, inputs.split_seed(2, 3, "valid", 78)),
+            "ones": lambda: inputs.ones(n)}[spectrum]()
+    plain = Solver(0)
+    learned = Solver(0, start="learned", learned_min_n=0)
+    try:
+        s0, _, _, st0 = _solve_checks(plain, d, e)
+        s1, _, _, st1 = _solve_checks(learned, d, e)
+    finally:
+        plain.close()
+        learned.close()
+    assert np.max(np.abs(s1 - s0)) <= 1e-13 * s0[0]
+    ip = st0["secular_evals"] / st0["roots"]
+    il = st1["secular_evals"] / st1["roots"]
+    print(f"{spectrum}: secular evaluations per root: plain {ip:.3f}, learned {il:.3f}")
+    assert st0["roots"] == st1["roots"]
+    if spectrum == "ones":
+        assert il <= 1.1 * ip
+    else:
+        assert il <= 0.92 * ip
+
+
 def test_gated_network_leaves_small_merges_plain(gpu):
     """With the network gated to merges of at least learned_min_n kept values,
     a problem whose merges are all smaller solves exactly as with the plain
