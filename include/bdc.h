@@ -349,7 +349,8 @@ int bdc_orgqr(bdc_handle_t handle, int m, int ncols, int k, const double* A, int
  * tuning. */
 typedef struct {
   int small_n;  /* merges with at most this many kept values use 64 x 64 output
-                   tiles, larger ones 128 x 128 (32..4096; default 96) */
+                   tiles, larger ones 128 x 128 (32..2^20; default 96; at or
+                   above the largest merge, no 128 x 128 launch at all) */
   int flat;     /* 1: all tiles of a merge level in one flattened list walked by a
                    persistent grid; 0 (default): a grid slice per merge */
   int grid64;   /* workgroups of the 64-tile product (flat), or half the per-merge cap */

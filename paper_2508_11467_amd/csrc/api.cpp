@@ -986,8 +986,12 @@ int bdc_gebrd(bdc_handle_t h, int m, int n, double* A, int lda, double* d, doubl
 // ---- launch tuning -----------------------------------------------------------
 
 namespace {
+// small_n at or above every merge size: all merges take the 64 x 64 tiles
+// and the 128 x 128 launch is left out of every level
+constexpr int kSmallNAll = 1 << 20;
+
 bool tuning_valid(const bdc_tuning_t* t) {
-  return t->small_n >= 32 && t->small_n <= 4096 && (t->flat == 0 || t->flat == 1) && t->grid64 >= 1 &&
+  return t->small_n >= 32 && t->small_n <= kSmallNAll && (t->flat == 0 || t->flat == 1) && t->grid64 >= 1 &&
          t->grid64 <= 65535 && t->grid128 >= 1 && t->grid128 <= 65535 && t->sec_small_n >= 0 &&
          t->sec_small_n <= kSecLanesMaxN && (t->leaf_size == 0 || (t->leaf_size >= 4 && t->leaf_size <= kMaxLeaf)) &&
          (t->tile128 == 0 || t->tile128 == 1);
@@ -1069,7 +1073,7 @@ int bdc_autotune(bdc_handle_t h, int64_t batch, const int64_t* sizes, const doub
   if (rc == BDC_OK) {
     std::vector<Tuning> cand;
     for (int ss : {0, 256})
-      for (int sn : {64, 96, 192}) {
+      for (int sn : {64, 96, 192, kSmallNAll}) {
         cand.push_back(Tuning{sn, 0, 1024, 512, ss});
         for (int gm : {256, 512, 1024}) cand.push_back(Tuning{sn, 1, 2 * gm, gm, ss});
       }

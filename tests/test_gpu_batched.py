@@ -130,7 +130,9 @@ def test_flat_schedule_and_tile_classes_match(gpu):
                      {"small_n": 64, "flat": 0, "grid64": 1024, "grid128": 512},
                      {"small_n": 96, "flat": 0, "grid64": 1024, "grid128": 512, "sec_small_n": 64},
                      {"small_n": 96, "flat": 0, "grid64": 1024, "grid128": 512, "sec_small_n": 256},
-                     {"small_n": 96, "flat": 0, "grid64": 1024, "grid128": 512, "sec_small_n": 0}):
+                     {"small_n": 96, "flat": 0, "grid64": 1024, "grid128": 512, "sec_small_n": 0},
+                     {"small_n": 1 << 20, "flat": 0, "grid64": 1024, "grid128": 512},
+                     {"small_n": 1 << 20, "flat": 1, "grid64": 2048, "grid128": 1024}):
             alt.set_tuning(**tune)
             a = alt.svd_batched(sizes, dt, et)
             info, _ = alt.info()
@@ -161,7 +163,7 @@ def test_autotune_picks_a_valid_tuning(gpu):
     s = Solver(0)
     try:
         best = s.autotune(sizes, d, e, repeats=1)
-        assert best["ms"] > 0 and best["flat"] in (0, 1) and best["small_n"] in (64, 96, 192)
+        assert best["ms"] > 0 and best["flat"] in (0, 1) and best["small_n"] in (64, 96, 192, 1 << 20)
         assert best["leaf_size"] in (8, 12, 16, 20, 24, 32)
         assert best["tile128"] in (0, 1)
         assert s.tuning() == {k: best[k] for k in ("small_n", "flat", "grid64", "grid128", "sec_small_n",
