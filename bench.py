@@ -77,7 +77,7 @@ def parse():
     ap.add_argument("--no-control", action="store_true", help="skip the d = e = 1 control (FP64 vs split)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 2000-problem batch")
     ap.add_argument("--no-backtr", action="store_true", help="skip the back-transformation leg")
-    ap.add_argument("--no-qr", action="store_true", help="skip the tall-and-skinny QR leg")
+    ap.add_argument("--no-qr", action="store_true", help="skip the tall-and-skinny QR and SVD legs")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense SVD (reduction) leg")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch tuning only")
     ap.add_argument("--tuning", default="",
@@ -648,6 +648,78 @@ def qr_leg(steps: int) -> dict:
     return out
 
 
+def ts_svd_leg(m: int, n: int, steps: int) -> dict:
+    """The tall-and-skinny SVD on the GPU (Section 4.3.1: QR first, then the
+    SVD of R): bdc_geqrf, then R (the upper triangle) through bdc_gebrd,
+    bdc_svd and the back-transformations (U_R = Q_B U_2, V = P V_2), bdc_orgqr
+    for the explicit Q, and the final product U = Q U_R (bdc_step_gemm); each
+    stage timed with events, E_svd and orthogonality of the m x n N(0,1)
+    matrix's factors."""
+    import numpy as np
+    import torch
+
+    from paper_2508_11467_amd import inputs
+    from paper_2508_11467_amd.api import Solver
+    dev = torch.device("cuda:0")
+    A0 = inputs.dense_normal(m, n, inputs.DENSE_TS_SEED)
+    Ad0 = torch.from_numpy(np.ascontiguousarray(A0.T)).to(dev).T
+    Ad = torch.empty((n, m), dtype=torch.float64, device=dev).T
+    R = torch.empty((n, n), dtype=torch.float64, device=dev).T
+    UR = torch.empty((n, n), dtype=torch.float64, device=dev).T
+    V = torch.empty((n, n), dtype=torch.float64, device=dev).T
+    U = torch.empty((n, m), dtype=torch.float64, device=dev).T
+    s = Solver(0)
+    names = ("geqrf", "gebrd_R", "bdc", "back_transform", "orgqr", "gemm_QU")
+
+    def pipeline(ev=None):
+        def mark(i):
+            if ev is not None:
+                ev[i].record()
+        mark(0)
+        tau = s.geqrf(Ad)
+        mark(1)
+        R.copy_(torch.triu(Ad[:n, :]))
+        d, e, tq, tp = s.gebrd(R)
+        mark(2)
+        sig, U2, VT2 = s.svd(d, e)
+        mark(3)
+        UR.copy_(U2)
+        V.copy_(VT2.T)
+        s.apply_reflectors(R, tq, UR, trans=False, offset=0)
+        s.apply_reflectors(R, tp[:n - 1], V, trans=False, offset=1, rows=True)
+        mark(4)
+        Q = s.orgqr(Ad, tau)
+        mark(5)
+        s.gemm(Q, UR, U)
+        mark(6)
+        return sig
+
+    Ad.copy_(Ad0)
+    pipeline()
+    torch.cuda.synchronize()
+    tot = [0.0] * len(names)
+    sig = None
+    for _ in range(steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+        Ad.copy_(Ad0)
+        sig = pipeline(ev)
+        torch.cuda.synchronize()
+        for i in range(len(names)):
+            tot[i] += ev[i].elapsed_time(ev[i + 1]) / steps
+    s.close()
+    At = torch.from_numpy(A0).to(dev)
+    Uc, Vc = U.contiguous(), V.contiguous()
+    e_svd = float(torch.linalg.norm(At - (Uc * sig[None, :]) @ Vc.T.contiguous()) / torch.linalg.norm(At))
+    orth_u = float(torch.max(torch.abs(Uc.T.contiguous() @ Uc - torch.eye(n, dtype=torch.float64, device=dev))))
+    orth_v = float(torch.max(torch.abs(Vc.T.contiguous() @ Vc - torch.eye(n, dtype=torch.float64, device=dev))))
+    out = {"workload": f"m = {m}, n = {n}, iid N(0,1), seed {inputs.DENSE_TS_SEED}",
+           "ms_per_step": sum(tot), "stage_ms": dict(zip(names, tot)), "E_svd": e_svd,
+           "orth_U": orth_u, "orth_V": orth_v}
+    del Ad, Ad0, R, UR, V, U, At, Uc, Vc
+    torch.cuda.empty_cache()
+    return out
+
+
 def dense_svd_leg(n: int, steps: int) -> dict:
     """The dense square SVD on the GPU (Sections 4.1-4.3): bdc_gebrd (the
     merged-rank-(2b) reduction), bdc_svd of the bidiagonal, and the
@@ -905,7 +977,8 @@ def main():
         progress("back-transformation done")
     if headline and not args.no_qr:
         line["tall_skinny_qr"] = qr_leg(3)
-        progress("tall-and-skinny QR done")
+        line["tall_skinny_svd"] = ts_svd_leg(20000, 1000, 2)
+        progress("tall-and-skinny QR and SVD done")
     if headline and not args.no_dense:
         line["dense_svd"] = dense_svd_leg(4096, 2)
         progress("dense SVD done")

@@ -392,6 +392,17 @@ class Solver:
                                                             _ptr(zt), _ptr(UM), _ptr(VM), self._stream()))
         return zt, UM.T, VM.T
 
+    def gemm(self, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor) -> None:
+        """C (M, N) = A (M, K) @ B (K, N) on column-major float64 device views
+        (bdc_step_gemm, the FP64 matrix-core kernel; no copies)."""
+        M, K = A.shape
+        K2, N = B.shape
+        if K != K2 or tuple(C.shape) != (M, N):
+            raise ValueError("gemm: shapes do not match")
+        lda, ldb, ldc = self._colmajor_ld(A, "A"), self._colmajor_ld(B, "B"), self._colmajor_ld(C, "C")
+        check("bdc_step_gemm", self.lib.bdc_step_gemm(self.handle, M, N, K, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc,
+                                                      self._stream()))
+
     def step_gemm(self, A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
         """C = A @ B through the update kernel (A, B float64 on the device)."""
         M, K = A.shape

@@ -150,3 +150,40 @@ def test_geqrf_tall_skinny_full_size(solver):
     res = float(torch.linalg.norm(Qc @ R.contiguous() - At) / torch.linalg.norm(At))
     print(f"QR {m}x{n}: orth {orth:.2e} residual {res:.2e}", flush=True)
     assert orth <= 1e-13 and res <= 1e-14
+
+
+@pytest.mark.parametrize("m,n", [(3000, 300), (1000, 1000), (2500, 129)])
+def test_tall_skinny_svd_end_to_end(solver, m, n):
+    """The tall-and-skinny SVD on the GPU (Section 4.3.1): QR (bdc_geqrf), the
+    SVD of R (bdc_gebrd, bdc_svd, bdc_apply_reflectors), the explicit Q
+    (bdc_orgqr) and U = Q U_R (the FP64 matrix-core product of
+    bdc_step_gemm): the singular values against LAPACK's, E_svd and
+    orthogonality."""
+    import torch
+    g = np.random.default_rng(m + 3 * n)
+    A = g.standard_normal((m, n))
+    Ad = _dev(A)
+    tau = solver.geqrf(Ad)
+    R = torch.empty((n, n), dtype=torch.float64, device="cuda").T
+    R.copy_(torch.triu(Ad[:n, :]))
+    d, e, tq, tp = solver.gebrd(R)
+    sig, U2, VT2 = solver.svd(d, e)
+    UR = torch.empty((n, n), dtype=torch.float64, device="cuda").T
+    UR.copy_(U2)
+    V = torch.empty((n, n), dtype=torch.float64, device="cuda").T
+    V.copy_(VT2.T)
+    solver.apply_reflectors(R, tq, UR, trans=False, offset=0)
+    if n > 1:
+        solver.apply_reflectors(R, tp[:n - 1], V, trans=False, offset=1, rows=True)
+    Q = solver.orgqr(Ad, tau)
+    U = torch.empty((n, m), dtype=torch.float64, device="cuda").T
+    solver.gemm(Q, UR, U)
+    torch.cuda.synchronize()
+    s, Un, Vn = sig.cpu().numpy(), U.cpu().numpy(), V.cpu().numpy()
+    ref = np.linalg.svd(A, compute_uv=False)
+    e_svd = np.linalg.norm(A - (Un * s) @ Vn.T) / np.linalg.norm(A)
+    print(f"TS SVD {m}x{n}: E_svd {e_svd:.2e} max sigma err {np.max(np.abs(s - ref)) / ref[0]:.2e}", flush=True)
+    assert np.max(np.abs(s - ref)) <= 1e-13 * ref[0]
+    assert e_svd <= 1e-13
+    assert np.max(np.abs(Un.T @ Un - np.eye(n))) <= 1e-12
+    assert np.max(np.abs(Vn.T @ Vn - np.eye(n))) <= 1e-12
