@@ -964,22 +964,18 @@ __global__ __launch_bounds__(256) void k_final_u_chunks(int64_t n, Work w, doubl
 }
 
 // V^T (n a multiple of 8 chunks): element e = tv + j n holds V[j, column(tv)]
-// inside that column's support.  A workgroup owns 512 vectors tv and a
-// contiguous range of groups of kVtJ = 8 output columns j (chunks n/512
-// apart, all of the workgroup's residue mod 8).  Each wavefront covers 128
-// vectors: for the reads, four lanes take one vector's 64-byte run
-// V[j0 .. j0+7, column] (16 vectors per load instruction, so an instruction
-// touches at most 16 cache lines), and the runs are turned around through
-// LDS ([j][vector], 8 KB per wavefront) so that lane L stores vectors 2L and
-// 2L+1 of each output column -- one 16-byte store per chunk.  The reads of
-// the next group are issued before the current group's LDS round trip and
-// stores; every lane always issues the same loads (from a fixed address
-// where its vector's support misses the group) and the values are masked by
-// the support at the store.
+// inside that column's support.  A workgroup owns 512 vectors tv (one 4 KB
+// chunk of every output column) and a contiguous range of groups of kVtJ = 8
+// output columns j (all chunks of the workgroup's residue mod 8).  Lane L of
+// a wavefront stores vectors 2L and 2L+1 of its 128: one 16-byte store per
+// output column of the group.  It reads a vector's 64-byte run V[j0 .. j0+7,
+// column] only when that vector's support meets the group (supports are a
+// few hundred rows of n, so most lanes read nothing and an instruction with
+// no reading lane is skipped); no LDS and no barrier.  The next group's reads
+// are issued before the current group's stores.
 constexpr int kVtJ = 8;
 
 __global__ __launch_bounds__(256) void k_final_vt_chunks(int64_t n, Work w, double* VT) {
-  __shared__ double tr[4][kVtJ][128];
   const double* Vw = w.Vw;
   const int4* fv = w.fin + n;
   const int64_t cpc = n / kFinalChunk;  // chunks per output column
@@ -989,63 +985,42 @@ __global__ __launch_bounds__(256) void k_final_vt_chunks(int64_t n, Work w, doub
   const int64_t gpb = (ngroups + nblk - 1) / nblk;
   const int64_t g0 = (b / cpc) * gpb, gend = min(ngroups, g0 + gpb);
   if (g0 >= gend) return;
-  const int64_t tvw = ch * kFinalChunk + wv * 128;  // the wavefront's first vector
-  // the vectors this lane stores: 2 lane, 2 lane + 1
-  const int4 s0 = fv[tvw + 2 * lane], s1 = fv[tvw + 2 * lane + 1];
-  // the vectors this lane reads: 16 i + lane / 4, i < 8; run part lane % 4
-  const int part = lane & 3;
-  int pcl[8], lol[8], hil[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int4 mt = fv[tvw + 16 * i + (lane >> 2)];
-    pcl[i] = mt.x;
-    lol[i] = mt.y;
-    hil[i] = mt.z;
-  }
-  auto fetch = [&](int64_t g, double2 (&v)[8]) {
+  const int64_t tv = ch * kFinalChunk + wv * 128 + 2 * lane;  // this lane's two vectors
+  const int4 s0 = fv[tv], s1 = fv[tv + 1];
+  const double* p0 = Vw + (int64_t)s0.x * n;
+  const double* p1 = Vw + (int64_t)s1.x * n;
+  auto fetch = [&](int64_t g, double2 (&x)[4], double2 (&y)[4]) {
     const int64_t j0 = g * kVtJ;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const bool need = lol[i] < j0 + kVtJ && hil[i] > j0;
-      const double* src = need ? Vw + (int64_t)pcl[i] * n + j0 + 2 * part : Vw;
-      v[i] = *reinterpret_cast<const double2*>(src);
+    for (int q = 0; q < 4; ++q) x[q] = y[q] = make_double2(0.0, 0.0);
+    if (s0.y < j0 + kVtJ && s0.z > j0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = *reinterpret_cast<const double2*>(p0 + j0 + 2 * q);
+    }
+    if (s1.y < j0 + kVtJ && s1.z > j0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) y[q] = *reinterpret_cast<const double2*>(p1 + j0 + 2 * q);
     }
   };
-  double (*T)[128] = tr[wv];
-  auto put = [&](int64_t g, const double2 (&v)[8]) {
+  auto put = [&](int64_t g, const double2 (&x)[4], const double2 (&y)[4]) {
     const int64_t j0 = g * kVtJ;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int t = 16 * i + (lane >> 2);
-      T[2 * part][t] = v[i].x;
-      T[2 * part + 1][t] = v[i].y;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    double* out = VT + tvw + 2 * lane + j0 * n;
+    double* out = VT + tv + j0 * n;
 #pragma unroll
     for (int q = 0; q < kVtJ; ++q) {
       const int64_t j = j0 + q;
-      const double2 x = *reinterpret_cast<const double2*>(&T[q][2 * lane]);
-      const double a = (j >= s0.y && j < s0.z) ? x.x : 0.0;
-      const double c = (j >= s1.y && j < s1.z) ? x.y : 0.0;
+      const double a = (j >= s0.y && j < s0.z) ? ((q & 1) ? x[q >> 1].y : x[q >> 1].x) : 0.0;
+      const double c = (j >= s1.y && j < s1.z) ? ((q & 1) ? y[q >> 1].y : y[q >> 1].x) : 0.0;
       *reinterpret_cast<double2*>(out + q * n) = make_double2(a, c);
     }
   };
-  // one group of reads in flight ahead of the stores (the fetch after the
-  // last group reads a valid group again, unused)
-  double2 A[8], B[8];
-  fetch(g0, A);
+  double2 A0[4], B0[4], A1[4], B1[4];
+  fetch(g0, A0, B0);
   for (int64_t g = g0;; g += 2) {
-    fetch(g + 1 < gend ? g + 1 : gend - 1, B);
-    put(g, A);
+    if (g + 1 < gend) fetch(g + 1, A1, B1);
+    put(g, A0, B0);
     if (g + 1 >= gend) return;
-    fetch(g + 2 < gend ? g + 2 : gend - 1, A);
-    put(g + 1, B);
+    if (g + 2 < gend) fetch(g + 2, A0, B0);
+    put(g + 1, A1, B1);
     if (g + 2 >= gend) return;
   }
 }
@@ -1143,7 +1118,7 @@ void launch_final_single(int64_t n, const Work& w, double* sigma, double* U, dou
   const int64_t groups = (chunks + 8 * kFinalR - 1) / (8 * kFinalR);
   hipLaunchKernelGGL(k_final_u_chunks, dim3((unsigned)(groups * 8)), dim3(kBlock), 0, st, n, w, U);
   // a persistent grid: a multiple of the chunks per output column (and so of
-  // 8), three workgroups per CU (the registers allow three), at most one per
+  // 8), three workgroups per CU (measured faster than five), at most one per
   // group of kVtJ columns
   const int64_t cpc = n / kFinalChunk;
   int64_t gv = cpc * std::max<int64_t>(1, std::min<int64_t>(n / kVtJ, (768 + cpc - 1) / cpc));
