@@ -991,16 +991,16 @@ __global__ __launch_bounds__(256) void k_final_vt_chunks(int64_t n, Work w, doub
   const double* p1 = Vw + (int64_t)s1.x * n;
   auto fetch = [&](int64_t g, double2 (&x)[4], double2 (&y)[4]) {
     const int64_t j0 = g * kVtJ;
+    // every lane issues the same loads (a lane whose vector's support misses
+    // the group reads the cached first run of Vw instead), so the wait for a
+    // group's data is a fixed count that leaves the next group's loads and
+    // the previous group's stores in flight
+    const double* q0 = (s0.y < j0 + kVtJ && s0.z > j0) ? p0 + j0 : Vw;
+    const double* q1 = (s1.y < j0 + kVtJ && s1.z > j0) ? p1 + j0 : Vw;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) x[q] = y[q] = make_double2(0.0, 0.0);
-    if (s0.y < j0 + kVtJ && s0.z > j0) {
+    for (int q = 0; q < 4; ++q) x[q] = *reinterpret_cast<const double2*>(q0 + 2 * q);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) x[q] = *reinterpret_cast<const double2*>(p0 + j0 + 2 * q);
-    }
-    if (s1.y < j0 + kVtJ && s1.z > j0) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) y[q] = *reinterpret_cast<const double2*>(p1 + j0 + 2 * q);
-    }
+    for (int q = 0; q < 4; ++q) y[q] = *reinterpret_cast<const double2*>(q1 + 2 * q);
   };
   auto put = [&](int64_t g, const double2 (&x)[4], const double2 (&y)[4]) {
     const int64_t j0 = g * kVtJ;
@@ -1013,13 +1013,15 @@ __global__ __launch_bounds__(256) void k_final_vt_chunks(int64_t n, Work w, doub
       *reinterpret_cast<double2*>(out + q * n) = make_double2(a, c);
     }
   };
+  // the fetch after the last group reads a valid group again, unused (no
+  // branch around a fetch, so the waits stay fixed counts)
   double2 A0[4], B0[4], A1[4], B1[4];
   fetch(g0, A0, B0);
   for (int64_t g = g0;; g += 2) {
-    if (g + 1 < gend) fetch(g + 1, A1, B1);
+    fetch(g + 1 < gend ? g + 1 : gend - 1, A1, B1);
     put(g, A0, B0);
     if (g + 1 >= gend) return;
-    if (g + 2 < gend) fetch(g + 2, A0, B0);
+    fetch(g + 2 < gend ? g + 2 : gend - 1, A0, B0);
     put(g + 1, A1, B1);
     if (g + 2 >= gend) return;
   }
