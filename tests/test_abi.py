@@ -46,6 +46,18 @@ def test_null_handle_rejected(lib):
     assert lib.bdc_step_gemm(None, 1, 1, 1, None, 1, None, 1, None, 1, None) == _lib.BDC_ERR_INVALID_HANDLE
 
 
+def test_dense_stage_entry_points_reject_a_null_handle(lib):
+    """The entry points around the bidiagonal solve check the handle before
+    touching any pointer (no GPU needed)."""
+    bad = _lib.BDC_ERR_INVALID_HANDLE
+    assert lib.bdc_geqrf(None, 4, 4, None, 4, None, 0, None) == bad
+    assert lib.bdc_orgqr(None, 4, 4, 4, None, 4, None, None, 4, 0, None) == bad
+    assert lib.bdc_gebrd(None, 4, 4, None, 4, None, None, None, None, 0, None) == bad
+    assert lib.bdc_apply_reflectors(None, 0, 4, 4, 4, 0, None, 1, 4, None, None, 4, 0, None) == bad
+    assert lib.bdc_apply_reflectors_noalloc(None, 0, 4, 4, 4, 0, None, 1, 4, None, None, 4, 0, None) == bad
+    assert lib.bdc_step_gemm(None, 4, 4, 4, None, 4, None, 4, None, 4, None) == bad
+
+
 def test_create_validates_options(lib):
     h = ctypes.c_void_p()
     assert lib.bdc_create(None, 0, None) == -1
