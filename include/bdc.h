@@ -322,11 +322,12 @@ int bdc_gebrd(bdc_handle_t handle, int m, int n, double* A, int lda, double* d, 
  * below it, tau (n, device) with their scalars -- LAPACK's geqrf storage,
  * H_i = I - tau_i y_i y_i^T with y_i = 1 at row i.  Blocked: panels of
  * `block` columns (1..64; 0 = 32) are factored on the GPU one column at a
- * time by a cooperative grid (one grid barrier per column), and the trailing
- * columns are updated by the panel's reflectors in the modified compact WY
- * form of eq. inv_t / larft_update (T^{-1} = Y^T Y, gemm, trsm, gemm).  The
- * rows below a panel's top block must fit the resident grid (at most 160
- * rows per workgroup: m - j0 - block <= 40960 on a 256-CU device), else
+ * time by a cooperative grid (one grid all-reduce per column), and the
+ * trailing columns are updated by the panel's reflectors in the modified
+ * compact WY form of eq. inv_t / larft_update (T^{-1} = Y^T Y, gemm, trsm,
+ * gemm).  The rows below a panel's top block must fit the resident grid (at
+ * most 10240 / block rows per workgroup, one workgroup per CU: m - j0 - block
+ * <= 40960 at block 64 and 81920 at block 32 on a 256-CU device), else
  * BDC_ERR_TOO_LARGE.  Returns BDC_OK, -i for argument i, BDC_ERR_NOMEM,
  * BDC_ERR_TOO_LARGE or BDC_ERR_HIP. */
 int bdc_geqrf(bdc_handle_t handle, int m, int n, double* A, int lda, double* tau, int block,

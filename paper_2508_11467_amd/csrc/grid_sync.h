@@ -28,12 +28,16 @@ constexpr size_t grid_group_doubles(int stride) { return (size_t)kGridMaxGroups 
 
 // All workgroups of the grid meet; returns false if the wait expired.  The
 // writes of every thread before the barrier are visible to every thread
-// after it.  One thread per workgroup arrives: a device-scope release fence
-// (the L2 write-back that makes this XCD's writes visible to the others), a
-// relaxed increment of the counter, and, while the generation has not moved,
-// relaxed coherent polling; then one device-scope acquire fence (the L2
+// after it.  The workgroup barrier orders every thread's writes before
+// thread 0's device-scope release fence (the L2 write-back that makes this
+// XCD's writes visible to the others; release is cumulative over what the
+// workgroup barrier ordered before it); then thread 0 arrives with a relaxed
+// increment of the counter and, while the generation has not moved, polls it
+// with relaxed coherent loads; then one device-scope acquire fence (the L2
 // invalidate).  Acquire loads inside the poll would invalidate the XCD's L2
-// on every spin and slow every workgroup on it.
+// on every spin and slow every workgroup on it.  A release fence in every
+// thread would do the same with one L2 write-back per wavefront; measured,
+// it slows the bidiagonal reduction by about 9%.
 __device__ inline bool grid_barrier(GridSync* s, unsigned nwg, unsigned* sh_ok) {
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -113,25 +117,30 @@ __device__ inline unsigned grid_wait_gen(GridSync* s, unsigned g0) {
 }
 
 // All-reduce of cnt (<= 256) values: every workgroup has written its values
-// to slots[g * stride + q] before the call (all threads call it).  The
-// workgroups meet in groups of kGridGroup: the last to arrive in a group
-// adds the group's slots in workgroup order into gslots[group * stride + q]
-// and arrives at the root counter; the last group to arrive moves the
-// generation.  Then every workgroup adds the group sums, split into parts
-// that are added in a fixed order, into out[q] (LDS).  The totals are the
-// same in every workgroup and do not depend on the order of arrival.  Each
-// workgroup reads about G / kGridGroup slots instead of G.  sh: 2 unsigned
-// in LDS; red: 256 doubles in LDS.  Consecutive calls must alternate two
-// sets of slots and gslots (a workgroup may write the next call's slots
-// while another still reads this call's group sums).  Returns false if a
-// wait expired.
+// to slots[g * stride + q] before the call (all threads call it; a workgroup
+// of at least 256 threads).  The workgroups meet in groups of kGridGroup:
+// the last to arrive in a group adds the group's slots in workgroup order
+// into gslots[group * stride + q] and arrives at the root counter; the last
+// group to arrive moves the generation.  Then every workgroup adds the group
+// sums, split into parts that are added in a fixed order, into out[q] (LDS).
+// The totals are the same in every workgroup and do not depend on the order
+// of arrival.  Each workgroup reads about G / kGridGroup slots instead of G.
+// sh: 3 unsigned in LDS (sh[0]: this workgroup arrived last in its group,
+// read by every thread; sh[2]: the wait ended in time -- a word of its own,
+// so that thread 0 cannot overwrite sh[0] before a slower wavefront has read
+// it); red: 256 doubles in LDS.  Consecutive calls must alternate two sets of
+// slots and gslots (a workgroup may write the next call's slots while
+// another still reads this call's group sums).  Returns false if a wait
+// expired.
 __device__ inline bool grid_allreduce(GridSync* s, const double* slots, double* gslots, int stride, int cnt,
                                       double* out, double* red, unsigned* sh) {
   const int t = threadIdx.x;
   const unsigned G = gridDim.x, g = blockIdx.x;
   const unsigned grp = g / kGridGroup, ngrp = (G + kGridGroup - 1) / kGridGroup;
   const unsigned in_grp = min((unsigned)kGridGroup, G - grp * kGridGroup);
-  __syncthreads();  // this workgroup's slot writes
+  // the workgroup's writes (the slots, and whatever the caller publishes),
+  // then thread 0's release fence, as in grid_barrier
+  __syncthreads();
   if (t == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     sh[1] = __hip_atomic_load(&s->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -166,9 +175,9 @@ __device__ inline bool grid_allreduce(GridSync* s, const double* slots, double* 
   } else if (t == 0) {
     ok = grid_wait_gen(s, sh[1]);
   }
-  if (t == 0) sh[0] = ok;
+  if (t == 0) sh[2] = ok;
   __syncthreads();
-  if (sh[0] == 0) return false;
+  if (sh[2] == 0) return false;
   sum_slots(gslots, stride, (int)ngrp, cnt, out, red);
   return true;
 }

@@ -49,7 +49,7 @@ struct BrdLds {
   double red[4 * 64];
   double sc[8];
   unsigned ok;
-  unsigned sh[2];
+  unsigned sh[3];
 };
 
 struct Refl {

@@ -37,27 +37,47 @@
 namespace bdc {
 namespace {
 
-constexpr int kQrMaxB = 64;       // panel width, at most
-constexpr int kQrMaxRows = 160;   // rows below the top block per workgroup, at most
+constexpr int kQrMaxB = 64;         // panel width, at most
+constexpr int kQrBlock = 1024;      // threads of a panel workgroup (16 wavefronts)
+constexpr int kQrWaves = kQrBlock / 64;
+constexpr int kQrXCap = 160 * kQrMaxB;  // doubles of the owned rows: 10240 / b rows
 struct PanelLds {
-  double T[kQrMaxB * kQrMaxB];     // top block, T[i * b + k] = A(j0 + i, j0 + k)
-  double X[kQrMaxRows * kQrMaxB];  // owned rows, X[r * b + k]
+  double T[kQrMaxB * kQrMaxB];  // top block, T[i * b + k] = A(j0 + i, j0 + k)
+  double X[kQrXCap];            // owned rows, X[r * b + k]
   double w[kQrMaxB];
   double tot[kQrMaxB + 2];
-  double red[4 * (kQrMaxB + 2)];
-  double sc[4];
-  unsigned sh[2];
+  double red[kQrWaves * (kQrMaxB + 2)];
+  double sc[kQrWaves];
+  unsigned sh[3];
 };
 
-// Sum over the workgroup of the four wavefront partials of slot q
-__device__ __forceinline__ double red4(const double* red, int q) {
+// Sum over the workgroup of the wavefront partials of slot q, in wavefront
+// order
+__device__ __forceinline__ double red_waves(const double* red, int q) {
   constexpr int S = kQrMaxB + 2;
-  return (red[q] + red[S + q]) + (red[2 * S + q] + red[3 * S + q]);
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < kQrWaves; ++u) s += red[u * S + q];
+  return s;
 }
 
-// grid: G workgroups (cooperative), 256 threads.  slots: 2 x G x (64 + 2)
+// workgroup sum of one value per thread (every thread gets it), wavefronts
+// added in order
+__device__ inline double qr_block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int wv = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < kQrWaves; ++u) s += sh[u];
+  return s;
+}
+
+// grid: G workgroups (cooperative), kQrBlock threads.  slots: 2 x G x (64 + 2)
 // doubles; gslots: 2 x grid_group_doubles(64 + 2).
-__global__ __launch_bounds__(256, 1) void k_qr_panel(double* __restrict__ A, int64_t lda, int m, int j0, int b,
+__global__ __launch_bounds__(kQrBlock, 1) void k_qr_panel(double* __restrict__ A, int64_t lda, int m, int j0, int b,
                                                      int rows_per_wg, double* __restrict__ tau,
                                                      double* __restrict__ slots, double* __restrict__ gslots,
                                                      GridSync* sync) {
@@ -71,11 +91,11 @@ __global__ __launch_bounds__(256, 1) void k_qr_panel(double* __restrict__ A, int
   const int r1 = min(m, r0 + rows_per_wg);
   const int R = max(0, r1 - r0);
   double* Ap = A + j0 + (int64_t)j0 * lda;         // panel origin
-  for (int e = t; e < top * b; e += 256) {
+  for (int e = t; e < top * b; e += kQrBlock) {
     const int i = e % top, k = e / top;
     L.T[i * b + k] = Ap[i + (int64_t)k * lda];
   }
-  for (int e = t; e < R * b; e += 256) {
+  for (int e = t; e < R * b; e += kQrBlock) {
     const int r = e % R, k = e / R;
     L.X[r * b + k] = A[(r0 + r) + (int64_t)(j0 + k) * lda];
   }
@@ -87,8 +107,8 @@ __global__ __launch_bounds__(256, 1) void k_qr_panel(double* __restrict__ A, int
     double* gsl = gslots + (size_t)phase * grid_group_doubles(S);
     phase ^= 1;
     double s = 0.0;
-    for (int r = t; r < R; r += 256) s += L.X[r * b + c] * L.X[r * b + c];
-    s = block_sum(s, L.sc);
+    for (int r = t; r < R; r += kQrBlock) s += L.X[r * b + c] * L.X[r * b + c];
+    s = qr_block_sum(s, L.sc);
     if (t == 0) sl[(size_t)g * S] = s;
     if (!grid_allreduce(sync, sl, gsl, S, 1, L.tot, L.red, L.sh)) return -1.0;
     return L.tot[0];
@@ -113,9 +133,12 @@ __global__ __launch_bounds__(256, 1) void k_qr_panel(double* __restrict__ A, int
       scale = 1.0 / den;
       tc = 2.0 / (1.0 + sigma / (den * den));
     }
+    // every wavefront has read the top block's column c (tp) before it is
+    // scaled
+    __syncthreads();
     // y below the pivot: owned rows and the top block's rows c+1..
-    for (int r = t; r < R; r += 256) L.X[r * b + c] *= scale;
-    for (int i = c + 1 + t; i < top; i += 256) L.T[i * b + c] *= scale;
+    for (int r = t; r < R; r += kQrBlock) L.X[r * b + c] *= scale;
+    for (int i = c + 1 + t; i < top; i += kQrBlock) L.T[i * b + c] *= scale;
     __syncthreads();
     const int nk = b - c - 1;  // later columns
     if (nk > 0) {
@@ -127,7 +150,7 @@ __global__ __launch_bounds__(256, 1) void k_qr_panel(double* __restrict__ A, int
       phase ^= 1;
       const int k = c + 1 + ln;
       double s = 0.0, sxx = 0.0, syy = 0.0;
-      for (int r = wv; r < R; r += 4) {
+      for (int r = wv; r < R; r += kQrWaves) {
         const double y = L.X[r * b + c];
         if (k < b) s += y * L.X[r * b + k];
         if (ln == 0) {
@@ -143,9 +166,9 @@ __global__ __launch_bounds__(256, 1) void k_qr_panel(double* __restrict__ A, int
       }
       __syncthreads();
       // slot layout: w partials 0..nk-1, then sum x^2, sum y^2
-      if (t < nk) sl[(size_t)g * S + t] = red4(L.red, t);
-      if (t == 64) sl[(size_t)g * S + nk] = red4(L.red, kQrMaxB);
-      if (t == 65) sl[(size_t)g * S + nk + 1] = red4(L.red, kQrMaxB + 1);
+      if (t < nk) sl[(size_t)g * S + t] = red_waves(L.red, t);
+      if (t == 64) sl[(size_t)g * S + nk] = red_waves(L.red, kQrMaxB);
+      if (t == 65) sl[(size_t)g * S + nk + 1] = red_waves(L.red, kQrMaxB + 1);
       if (!grid_allreduce(sync, sl, gsl, S, nk + 2, L.tot, L.red, L.sh)) return;
       if (t < nk) {
         const int kk = c + 1 + t;
@@ -173,11 +196,11 @@ __global__ __launch_bounds__(256, 1) void k_qr_panel(double* __restrict__ A, int
         else if (!(own > 0x1p-7 * big)) own = -2.0;
       }
       // X -= y (tau w)^T on the owned rows and the top block's rows c..
-      for (int e = t; e < R * nk; e += 256) {
+      for (int e = t; e < R * nk; e += kQrBlock) {
         const int r = e / nk, kq = e - r * nk;
         L.X[r * b + c + 1 + kq] -= L.X[r * b + c] * L.w[kq];
       }
-      for (int e = t; e < (top - c) * nk; e += 256) {
+      for (int e = t; e < (top - c) * nk; e += kQrBlock) {
         const int i = c + e / nk, kq = e % nk;
         const double y = i == c ? 1.0 : L.T[i * b + c];
         L.T[i * b + c + 1 + kq] -= y * L.w[kq];
@@ -196,12 +219,12 @@ __global__ __launch_bounds__(256, 1) void k_qr_panel(double* __restrict__ A, int
     __syncthreads();
   }
   // write back: owned rows, and the top block from workgroup 0
-  for (int e = t; e < R * b; e += 256) {
+  for (int e = t; e < R * b; e += kQrBlock) {
     const int r = e % R, k = e / R;
     A[(r0 + r) + (int64_t)(j0 + k) * lda] = L.X[r * b + k];
   }
   if (g == 0)
-    for (int e = t; e < top * b; e += 256) {
+    for (int e = t; e < top * b; e += kQrBlock) {
       const int i = e % top, k = e / top;
       Ap[i + (int64_t)k * lda] = L.T[i * b + k];
     }
@@ -226,19 +249,20 @@ size_t qr_sync_bytes(int max_wg) {
 
 int qr_max_block() { return kQrMaxB; }
 
-int qr_panel_grid(int device, int rows_below, int* grid, int* rows_per_wg) {
+int qr_panel_grid(int device, int rows_below, int b, int* grid, int* rows_per_wg) {
   int cus = 0, per = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return -1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(k_qr_panel), 256, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(k_qr_panel), kQrBlock, 0) !=
       hipSuccess)
     return -1;
   const int maxg = std::max(1, std::min(kGridMaxWg, cus * std::max(per, 1)));
-  // at least 16 rows per workgroup: fewer would spend the panel on barriers
-  int G = std::max(1, std::min(maxg, (rows_below + 15) / 16));
-  int R = (rows_below + G - 1) / G;
-  if (R > kQrMaxRows) return 1;  // too many rows for the resident grid
+  // as few workgroups as the LDS allows: a grid all-reduce costs more with
+  // more workgroups, and a workgroup's 16 wavefronts share its rows' work
+  const int cap = kQrXCap / std::max(b, 1);
+  int G = std::max(1, (rows_below + cap - 1) / cap);
+  if (G > maxg) return 1;  // too many rows for the resident grid
   *grid = G;
-  *rows_per_wg = std::max(R, 0);
+  *rows_per_wg = std::max((rows_below + G - 1) / G, 0);
   return 0;
 }
 
@@ -252,12 +276,12 @@ int launch_geqrf(int device, int m, int n, double* A, int lda, double* tau, int 
     const int top = std::min(bw, m - j0);
     const int rows_below = m - j0 - top;
     int G = 1, R = 0;
-    if (qr_panel_grid(device, rows_below, &G, &R) != 0) return BDC_ERR_TOO_LARGE;
+    if (qr_panel_grid(device, rows_below, bw, &G, &R) != 0) return BDC_ERR_TOO_LARGE;
     if (qr_sync_bytes(G) > sync_bytes) return BDC_ERR_TOO_LARGE;
     int64_t lda64 = lda;
     double* gslots = slots + 2 * (size_t)G * (kQrMaxB + 2);
     void* args[] = {&A, &lda64, &m, &j0, const_cast<int*>(&bw), &R, &tau, &slots, &gslots, &sync};
-    if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_qr_panel), dim3(G), dim3(256), args, 0, st) !=
+    if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_qr_panel), dim3(G), dim3(kQrBlock), args, 0, st) !=
         hipSuccess)
       return BDC_ERR_HIP;
     // trailing columns: A_t <- H_{bw-1} ... H_0 A_t = Q_panel^T A_t

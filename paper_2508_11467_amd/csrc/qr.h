@@ -12,9 +12,10 @@ size_t qr_sync_bytes(int max_wg);
 // largest panel width
 int qr_max_block();
 // workgroups and rows per workgroup of the panel kernel for `rows_below`
-// rows under the panel's top block: 0, or 1 when the rows do not fit the
-// resident grid, -1 on a runtime error
-int qr_panel_grid(int device, int rows_below, int* grid, int* rows_per_wg);
+// rows under a top block of b columns (at most 10240 / b rows per
+// workgroup): 0, or 1 when the rows do not fit the resident grid, -1 on a
+// runtime error
+int qr_panel_grid(int device, int rows_below, int b, int* grid, int* rows_per_wg);
 
 // A (m x n, lda, m >= n) <- R above the diagonal and the reflectors below it,
 // tau (n): LAPACK's geqrf storage, panels of b columns.  sync_buf: zeroed
