@@ -211,8 +211,13 @@ __global__ __launch_bounds__(256) void k_order(const NodeDesc* __restrict__ node
 // multiplied.
 constexpr int TK = 16;
 
-// the 64 x 64 output tile is turned around in LDS for the stores (column
-// stride kCt doubles: 16-byte aligned, spreads the writes over the banks)
+// the 64 x 64 output tile is turned around in LDS for the stores, half its
+// columns at a time (column stride kCt doubles: 16-byte aligned, spreads the
+// writes over the banks).  The half-tile buffer is no larger than the two
+// K slabs it shares the LDS with: 17 KB per workgroup, so LDS admits eight
+// workgroups per CU as the registers do (the whole tile's 34 KB held it to
+// four, and the small merges of a batch, a latency chain of K slabs per
+// tile, run at the number of tiles in flight).
 constexpr int kCt = 66;
 
 template <int TM, int TN>
@@ -222,7 +227,7 @@ struct TileSmem {
       double A[TK * TM];
       double B[TK * TN];
     } ab;
-    double C[TM <= 64 ? TN * kCt : 1];
+    double C[TM <= 64 ? (TN / 2) * kCt : 1];
   };
 };
 
@@ -301,31 +306,38 @@ __device__ inline void gemm_tile(TileSmem<TM, TN>& sm, const double* __restrict_
   // D[i][j] of a 16x16 block sits in lane j + 16 * (i % 4), register i / 4
   // (checked against a host product)
   if constexpr (TM <= 64) {
-    // through LDS: each output column's 64 rows leave as one 512-byte run
-    // (32 lanes x 16 bytes), two columns per store instruction
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < BM; ++a)
-#pragma unroll
-      for (int b = 0; b < BN; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          sm.C[(wn * (TN / 2) + b * 16 + li) * kCt + wm * (TM / 2) + a * 16 + lk + 4 * r] = acc[a][b][r];
-    __syncthreads();
+    // through LDS, one column half (the two wavefronts that own it) at a
+    // time: each output column's 64 rows leave as one 512-byte run (32
+    // lanes x 16 bytes), two columns per store instruction
+    constexpr int TH = TN / 2;
     const int half = l >> 5, rr = 2 * (l & 31);
     const int grow = tm0 + rr;
 #pragma unroll
-    for (int q = 0; q < TN / 8; ++q) {
-      const int c = wv * (TN / 4) + 2 * q + half;
-      const int colc = tn0 + c;
-      if (colc >= N) continue;
-      double* dst = store.col(colc);
-      const double2 v = *reinterpret_cast<const double2*>(&sm.C[c * kCt + rr]);
-      if (grow + 1 < M) {
-        dst[grow] = v.x;
-        dst[grow + 1] = v.y;
-      } else if (grow < M) {
-        dst[grow] = v.x;
+    for (int h = 0; h < 2; ++h) {
+      __syncthreads();
+      if (wn == h) {
+#pragma unroll
+        for (int a = 0; a < BM; ++a)
+#pragma unroll
+          for (int b = 0; b < BN; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              sm.C[(b * 16 + li) * kCt + wm * (TM / 2) + a * 16 + lk + 4 * r] = acc[a][b][r];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < TH / 8; ++q) {
+        const int c = wv * (TH / 4) + 2 * q + half;
+        const int colc = tn0 + h * TH + c;
+        if (colc >= N) continue;
+        double* dst = store.col(colc);
+        const double2 v = *reinterpret_cast<const double2*>(&sm.C[c * kCt + rr]);
+        if (grow + 1 < M) {
+          dst[grow] = v.x;
+          dst[grow + 1] = v.y;
+        } else if (grow < M) {
+          dst[grow] = v.x;
+        }
       }
     }
     __syncthreads();
