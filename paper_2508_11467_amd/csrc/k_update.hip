@@ -29,6 +29,7 @@ namespace bdc {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 inline int grid_y(int nnodes, int units, int cap_total) {
   int gy = units;
@@ -925,7 +926,13 @@ __global__ __launch_bounds__(256) void k_final_meta(int64_t n, Work w, double* s
 // (XCD = workgroup index mod 8), and workgroup b writes chunks congruent to b
 // mod 8 only, so each XCD streams a fixed eighth of the output's 4 KB pages;
 // measured on this part, that is the pattern that reaches the fill rate, where
-// longer per-workgroup runs fall 10-15% short.
+// longer per-workgroup runs fall 10-15% short.  Both passes store
+// non-temporally (the 2 x 8n^2 bytes are written once and never read here):
+// the stores then leave the caches to the V^T pass's scattered support
+// reads, which otherwise cost it about 100 us of its 480 (measured: 0.79
+// against 0.87 ms for the two passes; either pass alone non-temporal gains
+// little or loses).  The batch's final kernels, whose reads are a quarter of
+// their traffic, are slower with non-temporal stores and keep plain ones.
 constexpr int kFinalR = 4;  // chunks per workgroup
 
 __device__ inline int64_t div_n(int64_t e, int64_t n, double inv_n) {
@@ -972,7 +979,7 @@ __global__ __launch_bounds__(256) void k_final_u_chunks(int64_t n, Work w, doubl
   }
 #pragma unroll
   for (int q = 0; q < kFinalR; ++q)
-    if (e[q] < total) *reinterpret_cast<double2*>(U + e[q]) = v[q];
+    if (e[q] < total) __builtin_nontemporal_store(v2d{v[q].x, v[q].y}, reinterpret_cast<v2d*>(U + e[q]));
 }
 
 // V^T (n a multiple of 8 chunks): element e = tv + j n holds V[j, column(tv)]
@@ -981,10 +988,10 @@ __global__ __launch_bounds__(256) void k_final_u_chunks(int64_t n, Work w, doubl
 // output columns j (all chunks of the workgroup's residue mod 8).  Lane L of
 // a wavefront stores vectors 2L and 2L+1 of its 128: one 16-byte store per
 // output column of the group.  It reads a vector's 64-byte run V[j0 .. j0+7,
-// column] only when that vector's support meets the group (supports are a
-// few hundred rows of n, so most lanes read nothing and an instruction with
-// no reading lane is skipped); no LDS and no barrier.  The next group's reads
-// are issued before the current group's stores.
+// column] when that vector's support meets the group, and a fixed cached run
+// otherwise (supports are a few hundred rows of n, so most lanes read the
+// cached run); no LDS and no barrier.  The next group's reads are issued
+// before the current group's stores.
 constexpr int kVtJ = 8;
 
 __global__ __launch_bounds__(256) void k_final_vt_chunks(int64_t n, Work w, double* VT) {
@@ -1022,7 +1029,7 @@ __global__ __launch_bounds__(256) void k_final_vt_chunks(int64_t n, Work w, doub
       const int64_t j = j0 + q;
       const double a = (j >= s0.y && j < s0.z) ? ((q & 1) ? x[q >> 1].y : x[q >> 1].x) : 0.0;
       const double c = (j >= s1.y && j < s1.z) ? ((q & 1) ? y[q >> 1].y : y[q >> 1].x) : 0.0;
-      *reinterpret_cast<double2*>(out + q * n) = make_double2(a, c);
+      __builtin_nontemporal_store(v2d{a, c}, reinterpret_cast<v2d*>(out + q * n));
     }
   };
   // the fetch after the last group reads a valid group again, unused (no
