@@ -83,7 +83,7 @@ def parse():
     ap.add_argument("--tuning", default="",
                     help="launch tuning to time instead of running the autotuner, as k=v,... (the fields of "
                          "bdc_tuning_t, e.g. small_n=192,flat=0,grid64=1024,grid128=512,sec_small_n=256,"
-                         "leaf_size=12,tile128=1)")
+                         "leaf_size=12,tile128=1,streams=1)")
     ap.add_argument("--gemm", default="fp64", choices=["fp64", "crt", "ozaki"],
                     help="update-product form of the main timed solves (the library's default is fp64)")
     ap.add_argument("--no-config5", action="store_true", help="skip the n = 32768 plain/learned comparison")

@@ -365,6 +365,13 @@ typedef struct {
   int tile128;     /* 128 x 128 products with a grid per merge: 0 a
                       single-buffered LDS tile, 1 (default) a double-buffered
                       tile at two workgroups per CU (bitwise the same sums) */
+  int streams;     /* 1 (default): every launch of a solve on one stream; 2:
+                      each level's rotations and gather of the kept columns
+                      run on a second stream beside its secular solve, Löwner
+                      z and vectors (captured solves only; the same results).
+                      Pays where the gathers are long (batches of undeflated
+                      merges); costs a few microseconds per level where every
+                      launch is short */
   float ms;     /* out (bdc_autotune): time per solve of the chosen tuning */
 } bdc_tuning_t;
 
@@ -373,7 +380,8 @@ int bdc_set_tuning(bdc_handle_t handle, const bdc_tuning_t* tuning);
 /* Times candidate tunings on bdc_svd_batched(batch, sizes, d, e, sigma, U,
  * VT) (arguments as there; a single problem is batch = 1): one warm-up and
  * `repeats` timed solves each, with HIP events on `stream`; first the leaf
- * size (8, 12, 16, 20, 24, 32), then the launch shapes with the best one.  Keeps the
+ * size (8, 12, 16, 20, 24, 32), then the launch shapes with the best one, then
+ * the other 128 x 128 tile and the other stream count.  Keeps the
  * fastest in the handle and returns it in *best.  Synchronous: waits for the
  * stream.  The outputs hold the last solve's results. */
 int bdc_autotune(bdc_handle_t handle, int64_t batch, const int64_t* sizes, const double* d,

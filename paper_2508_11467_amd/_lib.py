@@ -82,6 +82,7 @@ class Tuning(ctypes.Structure):
         ("sec_small_n", c_int),
         ("leaf_size", c_int),
         ("tile128", c_int),
+        ("streams", c_int),
         ("ms", ctypes.c_float),
     ]
 

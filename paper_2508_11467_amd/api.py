@@ -161,8 +161,8 @@ class Solver:
         return d
 
     def set_tuning(self, small_n: int, flat: int, grid64: int, grid128: int, sec_small_n: int = 256,
-                   leaf_size: int = 0, tile128: int = 1, **_ignored) -> None:
-        t = _lib.Tuning(small_n, flat, grid64, grid128, sec_small_n, leaf_size, tile128, 0.0)
+                   leaf_size: int = 0, tile128: int = 1, streams: int = 1, **_ignored) -> None:
+        t = _lib.Tuning(small_n, flat, grid64, grid128, sec_small_n, leaf_size, tile128, streams, 0.0)
         check("bdc_set_tuning", self.lib.bdc_set_tuning(self.handle, ctypes.byref(t)))
 
     def autotune(self, sizes, d, e, out=None, repeats: int = 2) -> dict:

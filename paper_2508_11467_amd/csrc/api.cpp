@@ -85,6 +85,11 @@ struct bdc_handle_s {
   bool have_call = false;
   // captured launch sequence of the current plan and buffers
   hipStream_t cap_stream = nullptr;
+  // second stream of the captured sequence (each level's rotations and
+  // gather beside its secular solve, Löwner z and vectors) and its fork and
+  // join events
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraphExec_t gexec = nullptr;
   const void* gkey[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   struct Rec {
@@ -445,8 +450,10 @@ struct Timer {
   }
 };
 
+// side: a second stream for each level's rotations and gather, or null to
+// run every launch on st
 int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, double* U, double* VT,
-             hipStream_t st) {
+             hipStream_t st, hipStream_t side = nullptr) {
   const Plan& p = h->plan;
   Work w = h->w;
   w.d = d;
@@ -482,12 +489,23 @@ int run_plan(bdc_handle_t h, const double* d, const double* e, double* sigma, do
   }
   for (const Level& L : p.levels) {
     { Timer t(h, st, kPrep); launch_prep(L.dev, L.nnodes, L.max_m, w, st); }
-    { Timer t(h, st, kRotate); launch_rotate(L.dev, L.nnodes, L.max_m, w, st); }
-    { Timer t(h, st, kGather); launch_gather(L.dev, L.nnodes, L.max_m, w, st); }
+    // The rotations of the deflated pairs and the gather of the kept columns
+    // (the U and V data) need only the deflation's lists; the secular solve,
+    // the Löwner z and the vectors of M~ (the small matrices) need only the
+    // deflated values and z.  Neither chain reads what the other writes, so
+    // with a second stream they run side by side, joined before the update
+    // products, which need both.
+    hipStream_t sr = side ? side : st;
+    if (side && (hipEventRecord(h->ev_fork, st) != hipSuccess || hipStreamWaitEvent(side, h->ev_fork, 0) != hipSuccess))
+      return BDC_ERR_HIP;
+    { Timer t(h, sr, kRotate); launch_rotate(L.dev, L.nnodes, L.max_m, w, sr); }
+    { Timer t(h, sr, kGather); launch_gather(L.dev, L.nnodes, L.max_m, w, sr); }
+    if (side && hipEventRecord(h->ev_join, side) != hipSuccess) return BDC_ERR_HIP;
     { Timer t(h, st, kSecular); launch_secular(L.dev, L.nnodes, L.max_m, w, st); }
     if (h->harvest) launch_harvest(L.dev, L.nnodes, L.max_m, w, h->hv, st);
     { Timer t(h, st, kLowner); launch_lowner(L.dev, L.nnodes, L.max_m, w, st); }
     { Timer t(h, st, kVectors); launch_vectors(L.dev, L.nnodes, L.max_m, w, st); }
+    if (side && hipStreamWaitEvent(st, h->ev_join, 0) != hipSuccess) return BDC_ERR_HIP;
     // the update launches carry the merge of roots and deflated values
     // (k_order) as well
     { Timer t(h, st, kUpdate); launch_update(L.dev, L.nnodes, L.max_m, w, h->tune, st); }
@@ -550,8 +568,12 @@ int solve(bdc_handle_t h, int64_t batch, const int64_t* sizes, const double* d, 
     drop_graph(h);
     if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
       return BDC_ERR_HIP;
+    if (!h->side_stream && hipStreamCreateWithFlags(&h->side_stream, hipStreamNonBlocking) != hipSuccess)
+      return BDC_ERR_HIP;
+    if (!h->ev_fork && hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess) return BDC_ERR_HIP;
+    if (!h->ev_join && hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) return BDC_ERR_HIP;
     if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return BDC_ERR_HIP;
-    const int rc = run_plan(h, d, e, sigma, U, VT, h->cap_stream);
+    const int rc = run_plan(h, d, e, sigma, U, VT, h->cap_stream, h->tune.streams == 2 ? h->side_stream : nullptr);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(h->cap_stream, &g);
     if (rc != BDC_OK || ec != hipSuccess || !g) {
@@ -641,6 +663,9 @@ int bdc_destroy(bdc_handle_t h) {
     if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
     drop_graph(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->side_stream) (void)hipStreamDestroy(h->side_stream);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     free_plan(h->plan);
     if (h->arena) (void)hipFree(h->arena);
     if (h->oz_arena) (void)hipFree(h->oz_arena);
@@ -994,7 +1019,7 @@ bool tuning_valid(const bdc_tuning_t* t) {
   return t->small_n >= 32 && t->small_n <= kSmallNAll && (t->flat == 0 || t->flat == 1) && t->grid64 >= 1 &&
          t->grid64 <= 65535 && t->grid128 >= 1 && t->grid128 <= 65535 && t->sec_small_n >= 0 &&
          t->sec_small_n <= kSecLanesMaxN && (t->leaf_size == 0 || (t->leaf_size >= 4 && t->leaf_size <= kMaxLeaf)) &&
-         (t->tile128 == 0 || t->tile128 == 1);
+         (t->tile128 == 0 || t->tile128 == 1) && (t->streams == 1 || t->streams == 2);
 }
 }  // namespace
 
@@ -1008,6 +1033,7 @@ int bdc_get_tuning(bdc_handle_t h, bdc_tuning_t* t) {
   t->sec_small_n = h->tune.sec_small_n;
   t->leaf_size = h->opt.leaf_size;
   t->tile128 = h->tune.tile128;
+  t->streams = h->tune.streams;
   return BDC_OK;
 }
 
@@ -1017,7 +1043,7 @@ int bdc_set_tuning(bdc_handle_t h, const bdc_tuning_t* t) {
   DeviceGuard g(h->device);
   if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
   drop_graph(h);  // launch shapes are part of a captured sequence
-  h->tune = Tuning{t->small_n, t->flat, t->grid64, t->grid128, t->sec_small_n, t->tile128};
+  h->tune = Tuning{t->small_n, t->flat, t->grid64, t->grid128, t->sec_small_n, t->tile128, t->streams};
   if (t->leaf_size) h->opt.leaf_size = t->leaf_size;  // the plan is rebuilt on the next solve
   return BDC_OK;
 }
@@ -1098,6 +1124,17 @@ int bdc_autotune(bdc_handle_t h, int64_t batch, const int64_t* sizes, const doub
       best_t = c;
     }
   }
+  // 4. the rotations and gathers on a second stream (captured solves only)
+  if (rc == BDC_OK && h->opt.use_graph) {
+    Tuning c = best_t;
+    c.streams = 3 - c.streams;
+    float ms = 0.0f;
+    rc = time_one(best_leaf, c, ms);
+    if (rc == BDC_OK && ms < best_ms) {
+      best_ms = ms;
+      best_t = c;
+    }
+  }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (h->have_call) (void)hipStreamSynchronize(h->last_stream);
@@ -1111,6 +1148,7 @@ int bdc_autotune(bdc_handle_t h, int64_t batch, const int64_t* sizes, const doub
   best->sec_small_n = h->tune.sec_small_n;
   best->leaf_size = h->opt.leaf_size;
   best->tile128 = h->tune.tile128;
+  best->streams = h->tune.streams;
   best->ms = rc == BDC_OK ? best_ms : 0.0f;
   return rc;
 }

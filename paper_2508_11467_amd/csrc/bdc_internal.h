@@ -208,6 +208,7 @@ struct Tuning {
   int grid128;
   int sec_small_n;  // secular problems with N <= this (at most kSecLanesMaxN) use 8 or 16 lanes per root
   int tile128 = 1;  // 128 x 128 products (per-merge grids): 0 single-buffered tile, 1 double-buffered (default)
+  int streams = 1;  // 2: each level's rotations and gather on a second stream (captured solves)
 };
 
 // Workspace layout of tn positions, tn2 matrix entries and nnodes merges

@@ -155,6 +155,46 @@ def test_flat_schedule_and_tile_classes_match(gpu):
         alt.close()
 
 
+@pytest.mark.parametrize("flat", [0, 1])
+def test_second_stream_gives_the_same_results(gpu, flat):
+    """Rotations and gathers on a second stream beside the secular solve,
+    Löwner z and vectors (streams = 2): bitwise the same sigma, U and V^T as
+    one stream, on a batch and on single problems (n a multiple of 4096 takes
+    the chunked final pass), over replays of the captured solve."""
+    import torch
+    from paper_2508_11467_amd.api import Solver
+    sizes = [40, 900, 33, 260, 1200, 75, 31, 500, 2048, 64]
+    d, e = inputs.batch_uniform(sizes, 92)
+    dt, et = torch.from_numpy(d).cuda(), torch.from_numpy(e).cuda()
+    one = Solver(0)
+    two = Solver(0)
+    try:
+        tune = {"small_n": 96, "flat": flat, "grid64": 1024, "grid128": 512}
+        one.set_tuning(**tune, streams=1)
+        two.set_tuning(**tune, streams=2)
+        assert two.tuning()["streams"] == 2
+        r = [x.clone() for x in one.svd_batched(sizes, dt, et)]
+        for _ in range(3):
+            a = two.svd_batched(sizes, dt, et)
+            torch.cuda.synchronize()
+            for x, y in zip(r, a):
+                assert torch.equal(x, y)
+        assert one.info()[0] == 0 and two.info()[0] == 0
+        for n, seed in ((4096, 13), (3000, 14)):
+            d1, e1 = inputs.normal(n, seed)
+            r1 = [x.clone() for x in one.svd(d1, e1)]
+            for _ in range(2):
+                a1 = two.svd(d1, e1)
+                torch.cuda.synchronize()
+                for x, y in zip(r1, a1):
+                    assert torch.equal(x, y)
+        with pytest.raises(Exception):
+            two.set_tuning(**tune, streams=3)
+    finally:
+        one.close()
+        two.close()
+
+
 def test_autotune_picks_a_valid_tuning(gpu):
     import torch
     from paper_2508_11467_amd.api import Solver
@@ -165,9 +205,9 @@ def test_autotune_picks_a_valid_tuning(gpu):
         best = s.autotune(sizes, d, e, repeats=1)
         assert best["ms"] > 0 and best["flat"] in (0, 1) and best["small_n"] in (64, 96, 192, 1 << 20)
         assert best["leaf_size"] in (8, 12, 16, 20, 24, 32)
-        assert best["tile128"] in (0, 1)
+        assert best["tile128"] in (0, 1) and best["streams"] in (1, 2)
         assert s.tuning() == {k: best[k] for k in ("small_n", "flat", "grid64", "grid128", "sec_small_n",
-                                                    "leaf_size", "tile128")}
+                                                    "leaf_size", "tile128", "streams")}
         sig, U, VT = s.svd_batched(sizes, torch.from_numpy(d), torch.from_numpy(e))
         info, _ = s.info()
         assert info == 0
