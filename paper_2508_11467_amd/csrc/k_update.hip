@@ -826,7 +826,8 @@ __global__ __launch_bounds__(256) void k_final_u(const int64_t* __restrict__ pn,
 // vector's kVtTile-entry run of its Vwork column is read inside its support
 // only (eight threads per 128-byte run, two entries each; entries outside
 // the support are zeros without a read), the tile is turned around in LDS
-// and each output column's kVtBand rows leave as one 2 KB run.  The next
+// and each output column's kVtBand rows leave as one 2 KB run (non-temporal
+// stores: written once, they would only displace the reads).  The next
 // tile's reads are issued before the current tile's LDS round trip and
 // stores.  Measured on the 2000-problem batch, this shape beats 64 x 64
 // tiles (512-byte runs), 512 x 8 tiles and one entry per lane.
@@ -893,7 +894,7 @@ __global__ __launch_bounds__(256) void k_final_vt(const int64_t* __restrict__ pn
     __syncthreads();
     // output column g kVtTile + jj, rows t0 .. t0 + kVtBand - 1, a row per thread
     if (tv < n)
-      for (int jj = 0; jj < jn; ++jj) out[tv + (g * kVtTile + jj) * n] = tileS[jj][t];
+      for (int jj = 0; jj < jn; ++jj) __builtin_nontemporal_store(tileS[jj][t], out + tv + (g * kVtTile + jj) * n);
     __syncthreads();
   };
   double A[2 * kPass], B[2 * kPass];
@@ -931,8 +932,9 @@ __global__ __launch_bounds__(256) void k_final_meta(int64_t n, Work w, double* s
 // the stores then leave the caches to the V^T pass's scattered support
 // reads, which otherwise cost it about 100 us of its 480 (measured: 0.79
 // against 0.87 ms for the two passes; either pass alone non-temporal gains
-// little or loses).  The batch's final kernels, whose reads are a quarter of
-// their traffic, are slower with non-temporal stores and keep plain ones.
+// little or loses).  Of the batch's final kernels, whose reads are a quarter
+// of their traffic, the V^T one stores non-temporally too (4.75 against 4.89
+// ms for the two) and the U one keeps plain stores (5.27 with them).
 constexpr int kFinalR = 4;  // chunks per workgroup
 
 __device__ inline int64_t div_n(int64_t e, int64_t n, double inv_n) {
