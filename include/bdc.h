@@ -45,7 +45,7 @@ enum {
   BDC_ERR_NOMEM = -1003,          /* workspace would exceed the cap, or hipMalloc failed */
   BDC_ERR_HIP = -1004,            /* a HIP runtime call failed */
   BDC_ERR_NONFINITE = -1005,      /* (info) d or e holds Inf or NaN */
-  BDC_ERR_UNSUPPORTED = -1006,    /* option value not supported by this build */
+  BDC_ERR_UNSUPPORTED = -1006,    /* option value not supported by this library */
   BDC_ERR_NO_MODEL = -1007,       /* learned start requested before bdc_mlp_set */
   BDC_ERR_TOO_LARGE = -1008       /* beyond the fixed scratch of an allocation-free entry point */
 };
@@ -389,7 +389,7 @@ int bdc_autotune(bdc_handle_t handle, int64_t batch, const int64_t* sizes, const
                  int repeats, bdc_tuning_t* best);
 
 /* ---- learned start of the secular iteration ------------------------------
- * The paper solves each secular equation with LAPACK's lasd4; this build
+ * The paper solves each secular equation with LAPACK's lasd4; this library
  * adds an optional learned first point: a 19 -> 64 -> 64 -> 64 -> 1 MLP
  * (GELU hidden layers, logistic output) maps the features above to the
  * root's fractional position in its interval.  Its hidden-layer products run
