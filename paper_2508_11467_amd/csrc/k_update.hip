@@ -935,7 +935,10 @@ __global__ __launch_bounds__(256) void k_final_meta(int64_t n, Work w, double* s
 // little or loses).  Of the batch's final kernels, whose reads are a quarter
 // of their traffic, the V^T one stores non-temporally too (4.75 against 4.89
 // ms for the two) and the U one keeps plain stores (5.27 with them).
-constexpr int kFinalR = 4;  // chunks per workgroup
+// One chunk per workgroup: with non-temporal stores, measured 0.735 ms for
+// the two passes of n = 16384 against 0.764-0.771 with two chunks, 0.79
+// with four and 0.773-0.779 with eight (with plain stores four was best).
+constexpr int kFinalR = 1;  // chunks per workgroup
 
 __device__ inline int64_t div_n(int64_t e, int64_t n, double inv_n) {
   int64_t q = (int64_t)((double)e * inv_n);
