@@ -990,7 +990,8 @@ __global__ __launch_bounds__(256) void k_final_u_chunks(int64_t n, Work w, doubl
 // V^T (n a multiple of 8 chunks): element e = tv + j n holds V[j, column(tv)]
 // inside that column's support.  A workgroup owns 512 vectors tv (one 4 KB
 // chunk of every output column) and a contiguous range of groups of kVtJ = 8
-// output columns j (all chunks of the workgroup's residue mod 8).  Lane L of
+// output columns j (one group as launched; the chunk row's residue mod 8 is
+// the workgroup's XCD).  Lane L of
 // a wavefront stores vectors 2L and 2L+1 of its 128: one 16-byte store per
 // output column of the group.  It reads a vector's 64-byte run V[j0 .. j0+7,
 // column] when that vector's support meets the group, and a fixed cached run
@@ -1143,11 +1144,13 @@ void launch_final_single(int64_t n, const Work& w, double* sigma, double* U, dou
   const int64_t chunks = (n * n + kFinalChunk - 1) / kFinalChunk;
   const int64_t groups = (chunks + 8 * kFinalR - 1) / (8 * kFinalR);
   hipLaunchKernelGGL(k_final_u_chunks, dim3((unsigned)(groups * 8)), dim3(kBlock), 0, st, n, w, U);
-  // a persistent grid: a multiple of the chunks per output column (and so of
-  // 8), three workgroups per CU (measured faster than five), at most one per
-  // group of kVtJ columns
+  // V^T: one workgroup per (chunk row, group of kVtJ columns), a multiple of
+  // the chunks per output column and so of 8.  With non-temporal stores,
+  // short-lived workgroups stream best: 0.677 ms for the two passes of n =
+  // 16384 against 0.73-0.74 with persistent grids of 768 to 8192 workgroups
+  // walking column ranges (with plain stores three workgroups per CU were).
   const int64_t cpc = n / kFinalChunk;
-  int64_t gv = cpc * std::max<int64_t>(1, std::min<int64_t>(n / kVtJ, (768 + cpc - 1) / cpc));
+  const int64_t gv = cpc * (n / kVtJ);
   hipLaunchKernelGGL(k_final_vt_chunks, dim3((unsigned)gv), dim3(kBlock), 0, st, n, w, VT);
 }
 
