@@ -29,7 +29,10 @@ constexpr int kMaxLeaf = 32;
 // Batched final pass of V^T: bands of kVtBand output rows (singular
 // vectors) by tiles of kVtTile output columns, kVtTilesPerGroup tiles per
 // work item (one workgroup); work items of a problem of size n
-constexpr int kVtTilesPerGroup = 16;
+// One tile per work item: short-lived workgroups stream the non-temporal
+// stores best (the 2000-problem batch's final kernels 4.0-4.1 ms against
+// 4.6-4.8 with 16 tiles per item and 4.4-4.5 with 4).
+constexpr int kVtTilesPerGroup = 1;
 constexpr int kVtBand = 256, kVtTile = 16;
 __host__ __device__ inline int64_t vt_bands(int64_t n) { return (n + kVtBand - 1) / kVtBand; }
 __host__ __device__ inline int64_t vt_groups(int64_t n) {
